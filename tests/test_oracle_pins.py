@@ -1,0 +1,350 @@
+"""Pins of the FP64 oracle against what the mathematics fixes (no GPU).
+
+Each test states what it pins.  None of them re-calls the oracle's own
+formula: they use closed forms, an independent dense assembly
+(``dense_check``), numpy/scipy library routines, high-precision arithmetic or
+exact invariants.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+from paper_2010_14132_amd import workloads as wl
+from tests import dense_check as dc
+
+RNG = np.random.default_rng(12345)
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def stretched(nz, seed=0):
+    r = np.random.default_rng(seed)
+    dz = 20.0 * 1.03 ** np.arange(nz) * r.uniform(0.6, 1.4, nz)
+    rho = np.exp(-np.cumsum(dz) / 8000.0) * r.uniform(0.8, 1.2, nz)
+    return dz, rho
+
+
+# ---------------------------------------------------------------- P1
+def eigenmode(nx, ny, nz, kx, ky, m, phase=0.0):
+    i = np.arange(nx)[None, None, :]
+    j = np.arange(ny)[None, :, None]
+    k = np.arange(nz)[:, None, None]
+    return (np.cos(2 * np.pi * (kx * i / nx + ky * j / ny) + phase)
+            * np.cos(np.pi * m * (k + 0.5) / nz))
+
+
+def eigenvalue(nx, ny, nz, dx, dy, dz, kx, ky, m):
+    """Closed-form eigenvalue of the constant-coefficient 7-point operator
+    with periodic x/y and mirrored (zero-flux) ends in z."""
+    return -(4 * np.sin(np.pi * kx / nx) ** 2 / dx ** 2
+             + 4 * np.sin(np.pi * ky / ny) ** 2 / dy ** 2
+             + 4 * np.sin(np.pi * m / (2 * nz)) ** 2 / dz ** 2)
+
+
+def test_p1_stencil_has_closed_form_eigenmodes():
+    """The independent stencil reproduces the textbook eigenpairs (pins the
+    checker itself on the constant-coefficient case)."""
+    nx, ny, nz, dx, dy, dzv = 8, 6, 5, 50.0, 37.0, 40.0
+    dz, rho = np.full(nz, dzv), np.ones(nz)
+    for kx, ky, m in [(1, 0, 0), (0, 2, 1), (3, 1, 4), (4, 3, 2)]:
+        for ph in (0.0, 0.7):
+            phi = eigenmode(nx, ny, nz, kx, ky, m, ph)
+            lam = eigenvalue(nx, ny, nz, dx, dy, dzv, kx, ky, m)
+            assert rel(dc.stencil(phi, dx, dy, dz, rho), lam * phi) < 1e-13
+
+
+def test_p1_oracle_inverts_every_eigenmode_small():
+    """solve(Lambda phi) = phi for every nonzero mode of an 8x6x5 grid."""
+    nx, ny, nz, dx, dy, dzv = 8, 6, 5, 50.0, 37.0, 40.0
+    dz, rho = np.full(nz, dzv), np.ones(nz)
+    worst = 0.0
+    for kx in range(nx):
+        for ky in range(ny):
+            for m in range(nz):
+                if kx == 0 and ky == 0 and m == 0:
+                    continue
+                for ph in (0.0, 1.1):
+                    phi = eigenmode(nx, ny, nz, kx, ky, m, ph)
+                    if np.abs(phi).max() < 1e-12:
+                        continue
+                    lam = eigenvalue(nx, ny, nz, dx, dy, dzv, kx, ky, m)
+                    p = oracle.solve(lam * phi, dx, dy, dz, rho)
+                    worst = max(worst, rel(p, phi))
+    assert worst < 1e-12, worst
+
+
+def test_p1_oracle_eigenmodes_uniform_32():
+    """Sampled modes on the 32^2 x 16, dz = 40 m, dx = dy = 50 m grid."""
+    g = wl.uniform_grid(32, 32, 16)
+    for kx, ky, m in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (16, 16, 15), (5, 27, 3), (31, 1, 8)]:
+        phi = eigenmode(32, 32, 16, kx, ky, m, 0.3)
+        lam = eigenvalue(32, 32, 16, g.dx, g.dy, 40.0, kx, ky, m)
+        p = oracle.solve(lam * phi, g.dx, g.dy, g.dz, g.rho)
+        assert rel(p, phi) < 1e-12
+
+
+# ---------------------------------------------------------------- P2
+@pytest.mark.parametrize("shape", [(5, 6, 8), (7, 12, 10), (16, 32, 32), (3, 9, 27)])
+def test_p2_manufactured_stretched(shape):
+    """Random zero-mean p on a stretched, variable-density grid; b = A p by
+    the independent stencil; the oracle must return p."""
+    nz, ny, nx = shape
+    dz, rho = stretched(nz, seed=nz)
+    p = RNG.standard_normal(shape)
+    p -= p.mean()
+    b = dc.stencil(p, 50.0, 45.0, dz, rho)
+    q = oracle.solve(b, 50.0, 45.0, dz, rho)
+    assert rel(q, p) < 1e-12
+
+
+def test_p2_apply_matches_independent_stencil():
+    nz, ny, nx = 6, 10, 12
+    dz, rho = stretched(nz, seed=3)
+    p = RNG.standard_normal((nz, ny, nx))
+    assert rel(oracle.apply(p, 50.0, 30.0, dz, rho), dc.stencil(p, 50.0, 30.0, dz, rho)) < 1e-14
+
+
+def test_vertical_coefficients_independent():
+    dz, rho = stretched(9, seed=5)
+    f, D = oracle.vertical_coefficients(dz, rho)
+    assert f[0] == 0.0 and f[-1] == 0.0
+    np.testing.assert_allclose(f[1:-1], dc.face_coefficients(dz, rho), rtol=1e-15)
+    np.testing.assert_allclose(D, rho * dz, rtol=1e-15)
+
+
+# ---------------------------------------------------------------- P3
+@pytest.mark.parametrize("shape", [(4, 4, 4), (5, 6, 4), (3, 4, 6), (1, 4, 6), (4, 1, 1)])
+def test_p3_dense_bordered_incompatible(shape):
+    """Brute force: bordered K solved by LAPACK, for an incompatible b (its
+    D-weighted mean is not zero), so the projection and gauge are pinned."""
+    nz, ny, nx = shape
+    dz, rho = stretched(nz, seed=7)
+    b = RNG.standard_normal(shape) + 0.37
+    ref = dc.dense_solve(b, 50.0, 41.0, dz, rho)
+    p = oracle.solve(b, 50.0, 41.0, dz, rho)
+    assert rel(p, ref) < 1e-12
+
+
+# ---------------------------------------------------------------- P4 / P5
+def test_p4_residual_and_p5_gauge_plain_256_slice():
+    """Residual of the stretched smooth problem is at rounding level and the
+    plain mean of p is zero; a constant added to b changes nothing."""
+    prob = wl.stretched_smooth(64, 64, 24, seed=11)
+    g = prob.grid
+    b = prob.rhs + 0.05  # incompatible on purpose
+    p = oracle.solve(b, g.dx, g.dy, g.dz, g.rho)
+    D = g.rho * g.dz
+    mu = (D * b.sum(axis=(1, 2))).sum() / (g.nx * g.ny * D.sum())
+    Ap = dc.stencil(p, g.dx, g.dy, g.dz, g.rho)
+    f, _ = oracle.vertical_coefficients(g.dz, g.rho)
+    normA = 4 / g.dx ** 2 + 4 / g.dy ** 2 + 2 * np.max((f[:-1] + f[1:]) / D)
+    res = np.abs(Ap - (b - mu)).max() / (normA * np.abs(p).max() + np.abs(b).max())
+    assert res < 10 * 2.2e-16 * np.log2(p.size)
+    assert abs(p.sum()) < 1e-13 * np.abs(p).sum()
+    p2 = oracle.solve(b + 3.5, g.dx, g.dy, g.dz, g.rho)
+    assert rel(p2, p) < 1e-12
+
+
+# ---------------------------------------------------------------- P6 / P7
+def test_p6_mean_mode_only_column():
+    """nx = ny = 1: only the singular (0,0) column exists; compare with the
+    dense bordered 1D system."""
+    nz = 12
+    dz, rho = stretched(nz, seed=2)
+    b = RNG.standard_normal((nz, 1, 1))
+    ref = dc.dense_solve(b, 50.0, 50.0, dz, rho)
+    assert rel(oracle.solve(b, 50.0, 50.0, dz, rho), ref) < 1e-12
+
+
+def test_p6_level_only_input_matches_dense():
+    """b depends on z only (pure (0,0) input) on a 6x4 horizontal grid."""
+    nz = 7
+    dz, rho = stretched(nz, seed=9)
+    col = RNG.standard_normal(nz)
+    b = np.broadcast_to(col[:, None, None], (nz, 4, 6)).copy()
+    ref = dc.dense_solve(b, 50.0, 40.0, dz, rho)
+    p = oracle.solve(b, 50.0, 40.0, dz, rho)
+    assert rel(p, ref) < 1e-12
+    assert np.abs(p - p[:, :1, :1]).max() < 1e-12 * np.abs(p).max()
+
+
+def test_p7_single_level_is_2d_periodic_poisson():
+    """nz = 1 reduces to the 2D periodic 5-point Poisson problem.  Its
+    eigenvalues are the DFT of the stencil's first column (circulant
+    operator), computed here by numpy.fft, not by a formula."""
+    ny, nx, dx, dy = 12, 16, 50.0, 30.0
+    b = RNG.standard_normal((1, ny, nx))
+    c = np.zeros((ny, nx))
+    c[0, 0] = -2 / dx ** 2 - 2 / dy ** 2
+    c[0, 1] = c[0, -1] = 1 / dx ** 2
+    c[1, 0] = c[-1, 0] = 1 / dy ** 2
+    lam = np.fft.fft2(c).real
+    bh = np.fft.fft2(b[0] - b[0].mean())
+    ph = np.zeros_like(bh)
+    nz_ = np.abs(lam) > 1e-14
+    ph[nz_] = bh[nz_] / lam[nz_]
+    ref = np.fft.ifft2(ph).real
+    p = oracle.solve(b, dx, dy, [40.0], [1.0])
+    assert rel(p[0], ref) < 1e-12
+
+
+# ---------------------------------------------------------------- P8
+@pytest.mark.parametrize("shape", [(3, 8, 8), (2, 6, 10), (2, 9, 12), (1, 5, 7), (2, 32, 32)])
+def test_p8_dft_stage_matches_numpy(shape):
+    x = RNG.standard_normal(shape)
+    X = oracle.dft2_forward(x)
+    ref = np.fft.rfft2(x, axes=(1, 2))
+    assert rel(X, ref) < 1e-13
+    back = oracle.dft2_inverse(X, shape[2])
+    assert rel(back, np.fft.irfft2(ref, s=shape[1:], axes=(1, 2))) < 1e-13
+
+
+def test_p8_round_trip_without_solve():
+    """Transform there and back with the solve switched off returns the
+    input (the paper's own decomposition test, Section 2.1)."""
+    x = RNG.standard_normal((4, 24, 18))
+    assert rel(oracle.dft2_inverse(oracle.dft2_forward(x), 18), x) < 1e-14
+
+
+# ---------------------------------------------------------------- P9
+def banded_reference(s, r, dz, rho):
+    """(-s I + V) x = r with V assembled independently, scipy banded solve."""
+    nz = len(r)
+    f = np.zeros(nz + 1)
+    f[1:-1] = dc.face_coefficients(dz, rho)
+    D = np.asarray(rho) * np.asarray(dz)
+    ab = np.zeros((3, nz), dtype=complex)
+    ab[1] = -s - (f[:-1] + f[1:]) / D
+    ab[0, 1:] = f[1:-1] / D[:-1]
+    ab[2, :-1] = f[1:-1] / D[1:]
+    return scipy.linalg.solve_banded((1, 1), ab, r)
+
+
+@pytest.mark.parametrize("s", [1e-9, 1.5e-8, 1e-5, 1e-2, 10.0])
+def test_p9_column_solve_vs_banded(s):
+    nz = 128
+    g = wl.stretched_grid(4, 4, nz)
+    r = RNG.standard_normal(nz) + 1j * RNG.standard_normal(nz)
+    x = oracle.column_solve(s, r, g.dz, g.rho)
+    ref = banded_reference(s, r, g.dz, g.rho)
+    # LAPACK's banded LU is backward stable but not as accurate as the
+    # dominance-excess form on near-singular columns; compare to its error
+    # scale, then pin the worst column with 50-digit arithmetic below.
+    assert rel(x, ref) < 1e-12 * max(1.0, 1e-6 / s)
+
+
+def test_p9_near_singular_column_high_precision():
+    """Lowest nonzero wavenumber of the 1024^2 x 128 stretched grid, solved
+    with 50-digit arithmetic: the oracle's column solve is accurate to a few
+    ulps even though the textbook Thomas pivot cancels here."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 50
+    nz = 128
+    g = wl.stretched_grid(1024, 1024, nz)
+    s = 4 * np.sin(np.pi / 1024) ** 2 / g.dx ** 2
+    r = RNG.standard_normal(nz)
+    x = oracle.column_solve(s, r + 0j, g.dz, g.rho).real
+    fz = [mpmath.mpf(0)] * (nz + 1)
+    for k in range(nz - 1):
+        fz[k + 1] = (mpmath.mpf(g.rho[k]) + mpmath.mpf(g.rho[k + 1])) / 2 / (
+            (mpmath.mpf(g.dz[k]) + mpmath.mpf(g.dz[k + 1])) / 2)
+    D = [mpmath.mpf(g.rho[k]) * mpmath.mpf(g.dz[k]) for k in range(nz)]
+    M = mpmath.zeros(nz, nz)
+    for k in range(nz):
+        M[k, k] = -mpmath.mpf(s) - (fz[k] + fz[k + 1]) / D[k]
+        if k + 1 < nz:
+            M[k, k + 1] = fz[k + 1] / D[k]
+        if k > 0:
+            M[k, k - 1] = fz[k] / D[k]
+    ref = mpmath.lu_solve(M, mpmath.matrix([mpmath.mpf(v) for v in r]))
+    ref = np.array([float(v) for v in ref])
+    assert rel(x, ref) < 1e-14
+
+
+# ---------------------------------------------------------------- P10
+def test_p10_linearity():
+    nz, ny, nx = 6, 8, 10
+    dz, rho = stretched(nz, seed=4)
+    b1, b2 = RNG.standard_normal((2, nz, ny, nx))
+    s = lambda b: oracle.solve(b, 50.0, 50.0, dz, rho)
+    assert rel(s(2.5 * b1 - 0.75 * b2), 2.5 * s(b1) - 0.75 * s(b2)) < 1e-12
+
+
+# ---------------------------------------------------------------- P11
+def test_p11_adjoint_dot_product():
+    nz, ny, nx = 9, 12, 16
+    dz, rho = stretched(nz, seed=8)
+    b, w = RNG.standard_normal((2, nz, ny, nx))
+    lhs = np.vdot(w, oracle.solve(b, 50.0, 44.0, dz, rho))
+    rhs = np.vdot(oracle.solve_adjoint(w, 50.0, 44.0, dz, rho), b)
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs) * 100
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 4), (5, 6, 4), (1, 4, 6)])
+def test_p11_adjoint_vs_dense_transpose(shape):
+    nz, ny, nx = shape
+    dz, rho = stretched(nz, seed=6)
+    w = RNG.standard_normal(shape) + 0.2
+    ref = dc.dense_adjoint(w, 50.0, 35.0, dz, rho)
+    assert rel(oracle.solve_adjoint(w, 50.0, 35.0, dz, rho), ref) < 1e-12
+
+
+def test_p11_symmetric_case_adjoint_equals_forward():
+    """Constant D makes the bordered matrix symmetric, so S^T = S."""
+    g = wl.uniform_grid(16, 12, 8)
+    w = RNG.standard_normal(g.shape) + 0.1
+    a = oracle.solve_adjoint(w, g.dx, g.dy, g.dz, g.rho)
+    f = oracle.solve(w, g.dx, g.dy, g.dz, g.rho)
+    assert rel(a, f) < 1e-12
+
+
+# ---------------------------------------------------------------- P12
+def complex_step_grad(b, w, dx, dy, dz, rho):
+    """dL/drho_k for L = <w, S b> by complex-step differentiation of the
+    dense bordered solve (independent of the oracle)."""
+    nz = len(rho)
+    h = 1e-30
+    g = np.zeros(nz)
+    for k in range(nz):
+        rc = np.asarray(rho, dtype=complex).copy()
+        rc[k] += 1j * h
+        A = dc.dense_operator(b.shape, dx, dy, dz, rc)
+        sol = np.linalg.solve(dc.bordered(A), np.append(b.ravel(), 0.0).astype(complex))
+        g[k] = np.vdot(w.ravel(), sol[:-1]).imag / h
+    return g
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 4), (5, 6, 4)])
+def test_p12_grad_rho_complex_step(shape):
+    nz, ny, nx = shape
+    dz, rho = stretched(nz, seed=10)
+    b, w = RNG.standard_normal((2,) + shape)
+    p = oracle.solve(b, 50.0, 45.0, dz, rho)
+    lam = oracle.solve_adjoint(w, 50.0, 45.0, dz, rho)
+    g = oracle.grad_rho(lam, p, 50.0, 45.0, dz, rho)
+    ref = complex_step_grad(b, w, 50.0, 45.0, dz, rho)
+    assert np.abs(g - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+def test_p12_euler_identity_and_fd():
+    """V is invariant under rho -> c rho, so sum_k rho_k g_k = 0 exactly;
+    and central differences of L agree with g."""
+    nz, ny, nx = 10, 16, 16
+    dz, rho = stretched(nz, seed=12)
+    b, w = RNG.standard_normal((2, nz, ny, nx))
+    p = oracle.solve(b, 50.0, 50.0, dz, rho)
+    lam = oracle.solve_adjoint(w, 50.0, 50.0, dz, rho)
+    g = oracle.grad_rho(lam, p, 50.0, 50.0, dz, rho)
+    assert abs(np.dot(rho, g)) < 1e-12 * np.abs(rho * g).sum()
+    for k in (0, 3, nz - 1):
+        h = 1e-4
+        rp, rm = rho.copy(), rho.copy()
+        rp[k] *= 1 + h
+        rm[k] *= 1 - h
+        Lp = np.vdot(w, oracle.solve(b, 50.0, 50.0, dz, rp))
+        Lm = np.vdot(w, oracle.solve(b, 50.0, 50.0, dz, rm))
+        fd = (Lp - Lm) / (2 * h * rho[k])
+        assert abs(fd - g[k]) < 1e-6 * np.abs(g).max()
