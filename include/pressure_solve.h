@@ -1,0 +1,195 @@
+/*
+ * pressure_solve.h -- C ABI of the MI355X (gfx950) direct FFT pressure solve.
+ *
+ * The method (paper Section 2.1, "Direct FFT"): a forward Fourier transform
+ * of every horizontal level turns the pressure equation into one vertical
+ * ODE per horizontal wavenumber; each ODE is a tridiagonal system solved by
+ * a sweep up and down its column, independently of every other column; a
+ * backward transform gives the pressure.  As in the paper, the problem is
+ * described once to a plan (FFTW-style planning, Section 2.1) and the plan,
+ * with its reusable buffers (the decomposition plan of Section 2.1, last
+ * paragraphs), is executed every timestep.
+ *
+ * Discrete problem solved (a reading of the paper, which names only a
+ * Poisson-like elliptic equation, lateral periodicity and vertical
+ * tridiagonal columns):
+ *   A p = b - mu,   sum(p) = 0,
+ *   A = periodic 3-point second differences in x and y (spacings dx, dy)
+ *     + V, (V p)_k = [f_{k+1/2}(p_{k+1}-p_k) - f_{k-1/2}(p_k-p_{k-1})] / D_k,
+ *   f_{k+1/2} = (rho_k + rho_{k+1})/2 / ((dz_k + dz_{k+1})/2),
+ *   D_k = rho_k dz_k, zero flux through the bottom and the top,
+ *   mu = the D-weighted mean of b (projection onto the range of A).
+ * This is the p-block of [[A,1],[1^T,0]] [p; mu] = [b; 0].
+ *
+ * Layout of every field argument: level-major C order [nz][ny][nx], x
+ * fastest, device memory, element type double for PS_FP64 plans and float
+ * for every other precision.  Fields are owned by the caller; the plan owns
+ * its workspace and tables.
+ *
+ * Execution: every call that takes device pointers only enqueues work on
+ * the plan's HIP stream and returns; it does not synchronise.  A plan is not
+ * reentrant: at most one call per plan may be in flight on its stream, and
+ * calls on one plan from several host threads must be serialised by the
+ * caller.  Every argument is validated on the host before any device work
+ * is enqueued, so an error return means nothing was enqueued.
+ *
+ * Errors: every function returns a ps_status.  PS_EHIP means a HIP runtime
+ * call failed; ps_last_error() then describes it (per host thread).
+ */
+#ifndef PRESSURE_SOLVE_H
+#define PRESSURE_SOLVE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ps_plan ps_plan;
+typedef struct ps_batch ps_batch;
+
+typedef enum ps_status {
+    PS_OK = 0,
+    PS_EINVAL = 1,        /* null/aliased pointer, non-positive spacing or coefficient, NaN/inf */
+    PS_EUNSUPPORTED = 2,  /* grid size or precision this library does not implement */
+    PS_ENOMEM = 3,        /* device or host allocation failed */
+    PS_EHIP = 4,          /* a HIP runtime call failed; see ps_last_error() */
+    PS_ESTATE = 5         /* call not valid in the object's current state */
+} ps_status;
+
+typedef enum ps_precision {
+    /* FP64 transforms and FP64 column solves throughout. */
+    PS_FP64 = 0,
+    /* FP32 transforms and FP32 column solves; the singular mean column and
+     * every near-singular column (lateral eigenvalue below tau times the
+     * largest vertical diagonal) are solved in FP64; level sums in FP64. */
+    PS_FP32 = 1,
+    /* PS_FP32 plus one refinement of every FP32 column solve: the residual
+     * of the tridiagonal system is formed in FP64 in registers and one
+     * correction sweep is applied. */
+    PS_FP32_R2 = 2,
+    /* PS_FP32 plus one step of iterative refinement on the 3D residual:
+     * r = b - A p is formed with FP64 accumulation, A d = r is solved in
+     * PS_FP32 form, and p += d.  Needs rhs and p not to alias. */
+    PS_FP32_R1 = 3
+} ps_precision;
+
+/* Supported sizes: nx even with nx/2 = 2^a 3^b, 1 <= nx/2 <= 1024;
+ * ny = 2^a 3^b, 1 <= ny <= 1024; 1 <= nz <= 256.  Other sizes give
+ * PS_EUNSUPPORTED (the CPU oracle accepts any size). */
+#define PS_MAX_NX 2048
+#define PS_MAX_NY 1024
+#define PS_MAX_NZ 256
+
+/* Create a plan (the one-off planning phase of Section 2.1).
+ *   out        : receives the plan handle (host pointer, must not be NULL).
+ *   nx, ny, nz : grid points in x, y (periodic) and levels in z.
+ *   dx, dy     : lateral spacings, > 0.
+ *   dz         : host array of nz level thicknesses, each > 0 (copied).
+ *   rho        : host array of nz per-level densities rho_k > 0 (copied).
+ *   precision  : a ps_precision value.
+ *   tau        : near-singular threshold for the FP64 columns of the FP32
+ *                forms; <= 0 selects the default 1e-3.  Ignored for PS_FP64.
+ *   stream     : hipStream_t to enqueue on (NULL = the null stream).
+ * Allocates the device workspace (ps_workspace_bytes) on the current
+ * device and uploads the tables; this call synchronises.  Errors:
+ * PS_EINVAL, PS_EUNSUPPORTED, PS_ENOMEM, PS_EHIP; *out is NULL on error. */
+int ps_plan_create(ps_plan **out, int nx, int ny, int nz, double dx, double dy,
+                   const double *dz, const double *rho, int precision, double tau,
+                   void *stream);
+
+/* Release the plan and its device memory (synchronises its stream).  NULL is
+ * accepted and ignored. */
+int ps_plan_destroy(ps_plan *plan);
+
+/* Change the stream later calls enqueue on. */
+int ps_plan_set_stream(ps_plan *plan, void *stream);
+
+/* Replace the per-level densities (host array of nz values > 0) without
+ * reallocating; synchronises the plan's stream.  The set of columns solved
+ * in FP64 by the FP32 forms stays the one chosen at planning. */
+int ps_plan_set_coeffs(ps_plan *plan, const double *rho);
+
+/* Solve A p = b - mu, sum(p) = 0 (Section 2.1: forward transform, one
+ * tridiagonal solve per wavenumber column, backward transform).
+ *   rhs : device [nz][ny][nx], read only.
+ *   p   : device [nz][ny][nx], written.  May alias rhs except for
+ *         PS_FP32_R1 (PS_EINVAL).  rhs is not modified. */
+int ps_solve(ps_plan *plan, const void *rhs, void *p);
+
+/* Adjoint solve: grhs = S^T gp, the lambda-block of
+ * [[A^T,1],[1^T,0]] [lambda; nu] = [gp; 0] -- the gradient of <gp, p> with
+ * respect to rhs.  Same layout and aliasing rules as ps_solve (refinement
+ * forms run the adjoint in their base FP32 form plus the same refinement). */
+int ps_solve_adjoint(ps_plan *plan, const void *gp, void *grhs);
+
+/* Gradient of L = <w, p> with respect to the per-level densities, given
+ * lam = S^T w (from ps_solve_adjoint) and the solution p (from ps_solve):
+ * grho[k] = -lam^T (dA/drho_k) p.  lam and p are device fields of the
+ * plan's element type; grho is a device array of nz doubles, written.
+ * Deterministic (fixed-order reductions, no atomics). */
+int ps_grad_coeffs(ps_plan *plan, const void *lam, const void *p, double *grho);
+
+/* Device workspace owned by the plan, in bytes. */
+size_t ps_workspace_bytes(const ps_plan *plan);
+
+typedef struct ps_plan_info {
+    int nx, ny, nz, precision;
+    int fp64_columns;     /* near-singular columns solved in FP64 (FP32 forms) */
+    double tau;           /* threshold in effect */
+    int fft_variant_x;    /* transform kernels chosen by planning / autotuning */
+    int fft_variant_y;
+    size_t spectrum_elems;/* complex elements of the spectral layout, nz*(nx/2)*ny */
+} ps_plan_info;
+
+int ps_plan_query(const ps_plan *plan, ps_plan_info *info);
+
+/* Time the implemented transform variants for this plan's sizes on its
+ * stream (reps timed runs each) and keep the fastest; results are cached per
+ * device architecture, length and precision for the life of the process and
+ * can be saved/loaded as text.  Synchronises. */
+int ps_plan_autotune(ps_plan *plan, int reps);
+int ps_tune_cache_save(const char *path);
+int ps_tune_cache_load(const char *path);
+
+/* ---- stages, for testing each kernel on its own ------------------------
+ * spectrum: device buffer of spectrum_elems complex values of the plan's
+ * element type (interleaved re, im) in the packed, transposed layout
+ *   spec[k][kx][ky], kx in [0, nx/2), ky in [0, ny),
+ * where for kx >= 1 the entry is the 2D DFT coefficient (kx, ky) of level k,
+ * and the kx = 0 row packs two real-input transforms: along y it holds
+ * DFT_y(X_0 + i X_{nx/2}), X_0 and X_{nx/2} being the x-DC and x-Nyquist
+ * coefficients of each row.  Unnormalised forward transform. */
+int ps_forward_transform(ps_plan *plan, const void *rhs, void *spectrum);
+/* Column solves on a spectrum produced by ps_forward_transform from the same
+ * rhs (in place; adjoint != 0 selects the adjoint solve).  The mean column
+ * uses the level sums recorded by the preceding ps_forward_transform. */
+int ps_spectral_solve(ps_plan *plan, void *spectrum, int adjoint);
+/* Backward transform of a solved spectrum (the 1/(nx*ny) factor is applied
+ * inside ps_spectral_solve). */
+int ps_inverse_transform(ps_plan *plan, const void *spectrum, void *p);
+
+/* ---- batched: many independent solves of uneven sizes ------------------
+ * Describe count problems once (each with its own grid and densities, all
+ * of one precision); ps_batch_solve then solves all of them with one
+ * persistent launch per step replayed from a captured hipGraph.
+ *   nx, ny, nz, dx, dy : host arrays of count values.
+ *   dz, rho            : host arrays of count host pointers to nz[i] values.
+ *   precision          : PS_FP64 or PS_FP32. */
+int ps_batch_create(ps_batch **out, int count, const int *nx, const int *ny,
+                    const int *nz, const double *dx, const double *dy,
+                    const double *const *dz, const double *const *rho,
+                    int precision, void *stream);
+/* rhs, p: host arrays of count device pointers.  The first call (and any
+ * call with different pointers) captures the graph; later calls replay it. */
+int ps_batch_solve(ps_batch *batch, const void *const *rhs, void *const *p);
+int ps_batch_destroy(ps_batch *batch);
+
+const char *ps_status_string(int status);
+const char *ps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PRESSURE_SOLVE_H */

@@ -1,0 +1,283 @@
+"""Thin ctypes binding of libpressure_solve.so (the C ABI in
+include/pressure_solve.h).  Argument marshalling only: every step of the
+solve runs in the library's HIP kernels.  PyTorch supplies device memory and
+the current stream.
+
+The library is loaded on first use; if it has not been built, or a call is
+made without a GPU, an error is raised -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpressure_solve.so")
+
+PS_FP64, PS_FP32, PS_FP32_R2, PS_FP32_R1 = 0, 1, 2, 3
+PRECISIONS = {"fp64": PS_FP64, "fp32": PS_FP32, "fp32_r2": PS_FP32_R2, "fp32_r1": PS_FP32_R1}
+STATUS = {0: "PS_OK", 1: "PS_EINVAL", 2: "PS_EUNSUPPORTED", 3: "PS_ENOMEM", 4: "PS_EHIP",
+          5: "PS_ESTATE"}
+
+_lib = None
+_lock = threading.Lock()
+_vp = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int)
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("precision", ctypes.c_int), ("fp64_columns", ctypes.c_int),
+                ("tau", ctypes.c_double), ("fft_variant_x", ctypes.c_int),
+                ("fft_variant_y", ctypes.c_int), ("spectrum_elems", ctypes.c_size_t)]
+
+
+# name -> (restype, argtypes); mirrors include/pressure_solve.h
+SIGNATURES = {
+    "ps_plan_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_double, ctypes.c_double, _D, _D, ctypes.c_int,
+                                      ctypes.c_double, _vp]),
+    "ps_plan_destroy": (ctypes.c_int, [_vp]),
+    "ps_plan_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "ps_plan_set_coeffs": (ctypes.c_int, [_vp, _D]),
+    "ps_solve": (ctypes.c_int, [_vp, _vp, _vp]),
+    "ps_solve_adjoint": (ctypes.c_int, [_vp, _vp, _vp]),
+    "ps_grad_coeffs": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "ps_workspace_bytes": (ctypes.c_size_t, [_vp]),
+    "ps_plan_query": (ctypes.c_int, [_vp, ctypes.POINTER(PlanInfo)]),
+    "ps_plan_autotune": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "ps_tune_cache_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "ps_tune_cache_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "ps_forward_transform": (ctypes.c_int, [_vp, _vp, _vp]),
+    "ps_spectral_solve": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "ps_inverse_transform": (ctypes.c_int, [_vp, _vp, _vp]),
+    "ps_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, _I, _I, _I, _D, _D,
+                                       ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.c_int, _vp]),
+    "ps_batch_solve": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
+    "ps_batch_destroy": (ctypes.c_int, [_vp]),
+    "ps_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "ps_last_error": (ctypes.c_char_p, []),
+}
+
+
+class PressureSolveError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str = ""):
+        self.status = status
+        super().__init__("%s failed: %s%s" % (what, STATUS.get(status, str(status)),
+                                               (" (%s)" % detail) if detail else ""))
+
+
+def load():
+    """Load the HIP library (after torch, so both use one HIP runtime)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            import torch  # noqa: F401  -- loads the HIP runtime the library binds to
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError("libpressure_solve.so is not built (%s); run "
+                                   "paper_2010_14132_amd.build.build()" % LIB_PATH)
+            lib = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in SIGNATURES.items():
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = lib
+    return _lib
+
+
+def check(status: int, what: str):
+    if status != 0:
+        detail = load().ps_last_error()
+        raise PressureSolveError(status, what, detail.decode() if detail else "")
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_D)
+
+
+def _stream_handle():
+    import torch
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """A planned solve for one grid and precision (the C ABI's ps_plan).
+
+    precision: "fp64", "fp32" (FP64 mean and near-singular columns),
+    "fp32_r2" (plus in-register refinement of each column solve) or
+    "fp32_r1" (plus one step of iterative refinement on the 3D residual).
+    """
+
+    def __init__(self, nx, ny, nz, dx, dy, dz, rho, precision="fp64", tau=0.0, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the pressure-solve library needs a GPU (no CPU fallback)")
+        lib = load()
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.dx, self.dy = float(dx), float(dy)
+        self.dz = np.ascontiguousarray(dz, dtype=np.float64)
+        self.rho = np.ascontiguousarray(rho, dtype=np.float64)
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        h = _vp()
+        with torch.cuda.device(self.device):
+            check(lib.ps_plan_create(ctypes.byref(h), self.nx, self.ny, self.nz, self.dx, self.dy,
+                                     _dptr(self.dz), _dptr(self.rho), PRECISIONS[precision],
+                                     float(tau), _stream_handle()), "ps_plan_create")
+        self._h = h
+
+    # -- helpers
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    def _sync_stream(self):
+        check(load().ps_plan_set_stream(self._h, _stream_handle()), "ps_plan_set_stream")
+
+    def _check_field(self, t, name):
+        import torch
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("%s must be a torch tensor" % name)
+        if t.device != self.device or t.dtype != self.dtype or tuple(t.shape) != self.shape \
+                or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous %s tensor of shape %s on %s (got %s %s %s)"
+                             % (name, self.dtype, self.shape, self.device, t.dtype,
+                                tuple(t.shape), t.device))
+
+    def _out(self, out):
+        import torch
+        if out is None:
+            return torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        self._check_field(out, "out")
+        return out
+
+    # -- the C ABI
+    def solve(self, rhs, out=None):
+        self._check_field(rhs, "rhs")
+        out = self._out(out)
+        self._sync_stream()
+        check(load().ps_solve(self._h, _vp(rhs.data_ptr()), _vp(out.data_ptr())), "ps_solve")
+        return out
+
+    def solve_adjoint(self, gp, out=None):
+        self._check_field(gp, "gp")
+        out = self._out(out)
+        self._sync_stream()
+        check(load().ps_solve_adjoint(self._h, _vp(gp.data_ptr()), _vp(out.data_ptr())),
+              "ps_solve_adjoint")
+        return out
+
+    def grad_coeffs(self, lam, p):
+        import torch
+        self._check_field(lam, "lam")
+        self._check_field(p, "p")
+        g = torch.empty(self.nz, dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        check(load().ps_grad_coeffs(self._h, _vp(lam.data_ptr()), _vp(p.data_ptr()),
+                                    _vp(g.data_ptr())), "ps_grad_coeffs")
+        return g
+
+    def set_coeffs(self, rho):
+        self.rho = np.ascontiguousarray(rho, dtype=np.float64)
+        self._sync_stream()
+        check(load().ps_plan_set_coeffs(self._h, _dptr(self.rho)), "ps_plan_set_coeffs")
+
+    def info(self) -> dict:
+        inf = PlanInfo()
+        check(load().ps_plan_query(self._h, ctypes.byref(inf)), "ps_plan_query")
+        return {f: getattr(inf, f) for f, _ in PlanInfo._fields_}
+
+    def workspace_bytes(self) -> int:
+        return int(load().ps_workspace_bytes(self._h))
+
+    def autotune(self, reps: int = 5):
+        self._sync_stream()
+        check(load().ps_plan_autotune(self._h, int(reps)), "ps_plan_autotune")
+
+    def spectrum_shape(self):
+        return (self.nz, self.nx // 2, self.ny)
+
+    def forward_transform(self, rhs):
+        import torch
+        self._check_field(rhs, "rhs")
+        cdt = torch.complex128 if self.dtype == torch.float64 else torch.complex64
+        spec = torch.empty(self.spectrum_shape(), dtype=cdt, device=self.device)
+        self._sync_stream()
+        check(load().ps_forward_transform(self._h, _vp(rhs.data_ptr()), _vp(spec.data_ptr())),
+              "ps_forward_transform")
+        return spec
+
+    def spectral_solve(self, spec, adjoint=False):
+        self._sync_stream()
+        check(load().ps_spectral_solve(self._h, _vp(spec.data_ptr()), int(bool(adjoint))),
+              "ps_spectral_solve")
+        return spec
+
+    def inverse_transform(self, spec, out=None):
+        out = self._out(out)
+        self._sync_stream()
+        check(load().ps_inverse_transform(self._h, _vp(spec.data_ptr()), _vp(out.data_ptr())),
+              "ps_inverse_transform")
+        return out
+
+    def close(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h is not None and h.value and _lib is not None:
+            _lib.ps_plan_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _solve_fn():
+    import torch
+
+    class PoissonSolve(torch.autograd.Function):
+        """p = S(b; rho) with gradients with respect to b and the per-level
+        densities rho (the adjoint solve and the density-gradient kernel).
+        Nothing spectral is saved between forward and backward: the
+        backward pass recomputes through the adjoint solve."""
+
+        @staticmethod
+        def forward(ctx, b, rho, plan):
+            rho_h = rho.detach().to("cpu", torch.float64).numpy()
+            if not np.array_equal(rho_h, plan.rho):
+                plan.set_coeffs(rho_h)
+            p = plan.solve(b.detach().contiguous())
+            ctx.plan = plan
+            ctx.save_for_backward(p)
+            ctx.rho_dtype = rho.dtype
+            ctx.rho_device = rho.device
+            return p
+
+        @staticmethod
+        def backward(ctx, gp):
+            (p,) = ctx.saved_tensors
+            plan = ctx.plan
+            lam = plan.solve_adjoint(gp.contiguous().to(plan.dtype))
+            grho = None
+            if ctx.needs_input_grad[1]:
+                grho = plan.grad_coeffs(lam, p).to(device=ctx.rho_device, dtype=ctx.rho_dtype)
+            return lam, grho, None
+
+    return PoissonSolve
+
+
+_poisson = None
+
+
+def poisson_solve(b, rho, plan: Plan):
+    """Differentiable solve: gradients flow to b and to rho (a 1-D tensor of
+    the nz per-level densities)."""
+    global _poisson
+    if _poisson is None:
+        _poisson = _solve_fn()
+    return _poisson.apply(b, rho, plan)

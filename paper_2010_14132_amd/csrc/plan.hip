@@ -1,0 +1,522 @@
+// Host side of the pressure-solve library: planning (paper Section 2.1:
+// describe the problem once, reuse the plan every timestep), argument
+// validation, device tables and workspace, and the C ABI entry points.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ps_internal.h"
+#include "../../include/pressure_solve.h"
+
+using namespace ps;
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+#define PS_HIP(call)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(PS_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));               \
+    } while (0)
+
+namespace ps {
+
+bool is_2a3b(int n)
+{
+    if (n < 1) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+// Radix passes for length L = 2^a 3^b: as many radix-8 passes as possible
+// (a 16 or a 4 absorbing the remainder of a / 3), then radix-3 passes.
+StagePlan make_stage_plan(int L)
+{
+    StagePlan sp{};
+    int a = 0, b = 0, m = L;
+    while (m % 2 == 0) { m /= 2; ++a; }
+    while (m % 3 == 0) { m /= 3; ++b; }
+    std::vector<int> r(a / 3, 8);
+    if (a % 3 == 1) {
+        if (!r.empty()) r.back() = 16;
+        else r.push_back(2);
+    } else if (a % 3 == 2) {
+        r.push_back(4);
+    }
+    for (int i = 0; i < b; ++i) r.push_back(3);
+    sp.n = (int)r.size();
+    int ns = 1;
+    for (int s = 0; s < sp.n; ++s) {
+        sp.r[s] = r[s];
+        sp.ns[s] = ns;
+        ns *= r[s];
+    }
+    return sp;
+}
+
+} // namespace ps
+
+struct ps_plan {
+    int nx = 0, ny = 0, nz = 0, L = 0, precision = 0;
+    double dx = 0, dy = 0, tau = 0;
+    std::vector<double> dz, rho;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::vector<double> ax, ay, f, D;
+    StagePlan spx{}, spy{};
+    FftGeom geom;
+    Tables<float> t32;
+    Tables<double> t64;
+    int *d_maskcnt = nullptr;
+    int *d_mlist = nullptr;
+    int nmask = 0;
+    void *d_spec = nullptr;
+    double *d_rowsum = nullptr;
+    double *d_S = nullptr;
+    double *d_ws = nullptr;
+    double *d_gk = nullptr;
+    double *d_partial = nullptr;
+    int nblk = 0;
+    size_t bytes = 0;
+    std::vector<void *> allocs;
+    bool fp64() const { return precision == PS_FP64; }
+    size_t elem() const { return fp64() ? sizeof(double) : sizeof(float); }
+    size_t spec_elems() const { return (size_t)nz * L * ny; }
+};
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Validation shared by plan creation and batch creation; no HIP calls.
+static int validate_grid(int nx, int ny, int nz, double dx, double dy, const double *dz,
+                         const double *rho, int precision)
+{
+    if (!dz || !rho) return fail(PS_EINVAL, "dz and rho must not be NULL");
+    if (!finite_pos(dx) || !finite_pos(dy)) return fail(PS_EINVAL, "dx and dy must be finite and > 0");
+    if (precision < PS_FP64 || precision > PS_FP32_R1)
+        return fail(PS_EUNSUPPORTED, "unknown precision");
+    if (nx < 2 || nx % 2 || nx > PS_MAX_NX || !is_2a3b(nx / 2))
+        return fail(PS_EUNSUPPORTED, "nx must be even with nx/2 = 2^a 3^b and nx <= 2048");
+    if (ny < 1 || ny > PS_MAX_NY || !is_2a3b(ny))
+        return fail(PS_EUNSUPPORTED, "ny must be 2^a 3^b and <= 1024");
+    if (nz < 1 || nz > PS_MAX_NZ) return fail(PS_EUNSUPPORTED, "nz must be in [1, 256]");
+    for (int k = 0; k < nz; ++k) {
+        if (!finite_pos(dz[k])) return fail(PS_EINVAL, "dz values must be finite and > 0");
+        if (!finite_pos(rho[k])) return fail(PS_EINVAL, "rho values must be finite and > 0");
+    }
+    return PS_OK;
+}
+
+static double lateral(int m, int n, double d)
+{
+    int mm = m % n;
+    if (mm > n - mm) mm = n - mm;
+    const double s = std::sin(M_PI * (double)mm / (double)n);
+    return 4.0 * s * s / (d * d);
+}
+
+// exp(-2 pi i m / n) with the angle formed from the exactly reduced ratio.
+static void root(int m, int n, double &c, double &s)
+{
+    m %= n;
+    const double a = 2.0 * M_PI * (double)m / (double)n;
+    c = std::cos(a);
+    s = -std::sin(a);
+}
+
+static void host_tables(ps_plan *p)
+{
+    const int nz = p->nz;
+    p->f.assign(nz + 1, 0.0);
+    p->D.assign(nz, 0.0);
+    for (int k = 0; k + 1 < nz; ++k) {
+        const double h = 0.5 * (p->dz[k] + p->dz[k + 1]);
+        p->f[k + 1] = 0.5 * (p->rho[k] + p->rho[k + 1]) / h;
+    }
+    for (int k = 0; k < nz; ++k) p->D[k] = p->rho[k] * p->dz[k];
+    p->ax.resize(p->L + 1);
+    for (int kx = 0; kx <= p->L; ++kx) p->ax[kx] = lateral(kx, p->nx, p->dx);
+    p->ay.resize(p->ny);
+    for (int ky = 0; ky < p->ny; ++ky) p->ay[ky] = lateral(ky, p->ny, p->dy);
+}
+
+template <typename T> static int dev_alloc(ps_plan *p, T **ptr, size_t n)
+{
+    void *q = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(&q, n * sizeof(T));
+    if (e != hipSuccess) return fail(PS_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    p->allocs.push_back(q);
+    p->bytes += n * sizeof(T);
+    *ptr = reinterpret_cast<T *>(q);
+    return PS_OK;
+}
+
+template <typename T, typename S> static int upload(T *dst, const std::vector<S> &src)
+{
+    std::vector<T> tmp(src.begin(), src.end());
+    PS_HIP(hipMemcpy(dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
+    return PS_OK;
+}
+
+#define PS_TRY(x)                                                                                  \
+    do {                                                                                           \
+        int rc_ = (x);                                                                             \
+        if (rc_) return rc_;                                                                       \
+    } while (0)
+
+template <typename T> static int alloc_tables(ps_plan *p, Tables<T> &t)
+{
+    PS_TRY(dev_alloc(p, &t.ax, p->L + 1));
+    PS_TRY(dev_alloc(p, &t.ay, p->ny));
+    PS_TRY(dev_alloc(p, &t.f, p->nz + 1));
+    PS_TRY(dev_alloc(p, &t.D, p->nz));
+    PS_TRY(dev_alloc(p, &t.rs_fwd, p->nz));
+    PS_TRY(dev_alloc(p, &t.rs_adj, p->nz));
+    PS_TRY(dev_alloc(p, &t.os_adj, p->nz));
+    PS_TRY(dev_alloc(p, &t.tw_x, p->L));
+    PS_TRY(dev_alloc(p, &t.tw_s, p->L));
+    PS_TRY(dev_alloc(p, &t.tw_y, p->ny));
+    return PS_OK;
+}
+
+template <typename T> static int upload_coeff_tables(ps_plan *p, Tables<T> &t)
+{
+    const double on = 1.0 / ((double)p->nx * (double)p->ny);
+    std::vector<double> rsf(p->nz), rsa(p->nz, -on);
+    for (int k = 0; k < p->nz; ++k) rsf[k] = -p->D[k] * on;
+    PS_TRY(upload(t.f, p->f));
+    PS_TRY(upload(t.D, p->D));
+    PS_TRY(upload(t.rs_fwd, rsf));
+    PS_TRY(upload(t.rs_adj, rsa));
+    PS_TRY(upload(t.os_adj, p->D));
+    return PS_OK;
+}
+
+template <typename T> static int upload_tables(ps_plan *p, Tables<T> &t)
+{
+    using C = cx_t<T>;
+    PS_TRY(upload(t.ax, p->ax));
+    PS_TRY(upload(t.ay, p->ay));
+    PS_TRY(upload_coeff_tables(p, t));
+    auto roots = [&](C *dst, int count, int n) -> int {
+        std::vector<C> h(count);
+        for (int m = 0; m < count; ++m) {
+            double c, s;
+            root(m, n, c, s);
+            h[m] = C{(T)c, (T)s};
+        }
+        PS_HIP(hipMemcpy(dst, h.data(), h.size() * sizeof(C), hipMemcpyHostToDevice));
+        return PS_OK;
+    };
+    PS_TRY(roots(t.tw_x, p->L, p->L));
+    PS_TRY(roots(t.tw_s, p->L, p->nx));
+    PS_TRY(roots(t.tw_y, p->ny, p->ny));
+    return PS_OK;
+}
+
+static int upload_grad_table(ps_plan *p)
+{
+    const int nz = p->nz;
+    std::vector<double> gk(4 * (size_t)nz + 2, 0.0);
+    for (int k = 0; k <= nz; ++k) gk[k] = p->f[k];
+    for (int k = 0; k < nz; ++k) {
+        gk[nz + 1 + k] = p->D[k];
+        gk[2 * nz + 1 + k] = p->rho[k];
+    }
+    for (int k = 1; k < nz; ++k) gk[3 * nz + 1 + k] = 2.0 / (p->dz[k - 1] + p->dz[k]);
+    return upload(p->d_gk, gk);
+}
+
+// Launch geometry of the transform kernels: as many rows per block as fit in
+// 64 KiB of LDS (two row buffers plus twiddles), at most 64.
+static void choose_geometry(ps_plan *p)
+{
+    const size_t cs = 2 * p->elem();
+    const size_t budget = 65536 / cs;
+    int rx = (int)((budget - 2 * (size_t)p->L) / (2 * (size_t)p->L));
+    int ry = (int)((budget - (size_t)p->ny) / (2 * (size_t)p->ny));
+    rx = std::max(1, std::min(64, rx));
+    ry = std::max(1, std::min(64, ry));
+    p->geom.rows_x = std::min(rx, p->ny * p->nz);
+    p->geom.rows_y = std::min(ry, p->nz * p->L);
+}
+
+// Near-singular columns of the FP32 forms: lateral eigenvalue
+// s = ax + ay below tau * max_k (f_{k-1/2} + f_{k+1/2}) / D_k.  s grows with
+// kx and with min(ky, ny - ky), so per kx the set is min(ky, ny-ky) < cnt[kx].
+static void choose_mask(ps_plan *p, std::vector<int> &cnt, std::vector<int> &list)
+{
+    cnt.assign(p->L, 0);
+    list.clear();
+    if (p->fp64()) return;
+    double vmax = 0.0;
+    for (int k = 0; k < p->nz; ++k) vmax = std::max(vmax, (p->f[k] + p->f[k + 1]) / p->D[k]);
+    const double thr = p->tau * vmax;
+    for (int kx = 1; kx < p->L; ++kx) {
+        int c = 0;
+        while (c <= p->ny / 2 && p->ax[kx] + p->ay[c] < thr) ++c;
+        cnt[kx] = c;
+        for (int ky = 0; ky < p->ny; ++ky)
+            if (std::min(ky, p->ny - ky) < c) list.push_back(kx * p->ny + ky);
+    }
+}
+
+static void free_plan(ps_plan *p)
+{
+    for (void *q : p->allocs) (void)hipFree(q);
+    p->allocs.clear();
+    delete p;
+}
+
+extern "C" int ps_plan_create(ps_plan **out, int nx, int ny, int nz, double dx, double dy,
+                              const double *dz, const double *rho, int precision, double tau,
+                              void *stream)
+{
+    if (!out) return fail(PS_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    PS_TRY(validate_grid(nx, ny, nz, dx, dy, dz, rho, precision));
+    if (std::isnan(tau) || std::isinf(tau)) return fail(PS_EINVAL, "tau must be finite");
+    ps_plan *p = new ps_plan();
+    p->nx = nx;
+    p->ny = ny;
+    p->nz = nz;
+    p->L = nx / 2;
+    p->precision = precision;
+    p->dx = dx;
+    p->dy = dy;
+    p->tau = tau > 0 ? tau : 1e-3;
+    p->dz.assign(dz, dz + nz);
+    p->rho.assign(rho, rho + nz);
+    p->stream = reinterpret_cast<hipStream_t>(stream);
+    host_tables(p);
+    p->spx = make_stage_plan(p->L);
+    p->spy = make_stage_plan(ny);
+    choose_geometry(p);
+    std::vector<int> cnt, list;
+    choose_mask(p, cnt, list);
+    p->nmask = (int)list.size();
+    p->nblk = grad_blocks(nx, ny);
+
+    int rc = PS_OK;
+    auto step = [&](int r) {
+        if (rc == PS_OK) rc = r;
+    };
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        free_plan(p);
+        return fail(PS_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    step(alloc_tables(p, p->t64));
+    if (!p->fp64()) step(alloc_tables(p, p->t32));
+    const size_t ntask = (size_t)(ny / 2 + 1 + p->nmask);
+    if (p->fp64()) {
+        double *sp = nullptr;
+        step(dev_alloc(p, &sp, 2 * p->spec_elems()));
+        p->d_spec = sp;
+    } else {
+        float *sp = nullptr;
+        step(dev_alloc(p, &sp, 2 * p->spec_elems()));
+        p->d_spec = sp;
+    }
+    step(dev_alloc(p, &p->d_rowsum, (size_t)ny * nz));
+    step(dev_alloc(p, &p->d_S, (size_t)nz));
+    step(dev_alloc(p, &p->d_ws, 5 * (size_t)nz * ntask));
+    step(dev_alloc(p, &p->d_gk, 4 * (size_t)nz + 2));
+    step(dev_alloc(p, &p->d_partial, (size_t)nz * p->nblk));
+    step(dev_alloc(p, &p->d_maskcnt, (size_t)p->L));
+    step(dev_alloc(p, &p->d_mlist, list.size()));
+    if (rc == PS_OK) step(upload_tables(p, p->t64));
+    if (rc == PS_OK && !p->fp64()) step(upload_tables(p, p->t32));
+    if (rc == PS_OK) step(upload(p->d_maskcnt, cnt));
+    if (rc == PS_OK && !list.empty()) step(upload(p->d_mlist, list));
+    if (rc == PS_OK) step(upload_grad_table(p));
+    if (rc != PS_OK) {
+        free_plan(p);
+        return rc;
+    }
+    *out = p;
+    return PS_OK;
+}
+
+extern "C" int ps_plan_destroy(ps_plan *p)
+{
+    if (!p) return PS_OK;
+    hipError_t e = hipStreamSynchronize(p->stream);
+    free_plan(p);
+    if (e != hipSuccess) return fail(PS_EHIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    return PS_OK;
+}
+
+extern "C" int ps_plan_set_stream(ps_plan *p, void *stream)
+{
+    if (!p) return fail(PS_EINVAL, "plan is NULL");
+    p->stream = reinterpret_cast<hipStream_t>(stream);
+    return PS_OK;
+}
+
+extern "C" int ps_plan_set_coeffs(ps_plan *p, const double *rho)
+{
+    if (!p || !rho) return fail(PS_EINVAL, "plan and rho must not be NULL");
+    for (int k = 0; k < p->nz; ++k)
+        if (!finite_pos(rho[k])) return fail(PS_EINVAL, "rho values must be finite and > 0");
+    PS_HIP(hipStreamSynchronize(p->stream));
+    p->rho.assign(rho, rho + p->nz);
+    host_tables(p);
+    PS_TRY(upload_coeff_tables(p, p->t64));
+    if (!p->fp64()) PS_TRY(upload_coeff_tables(p, p->t32));
+    PS_TRY(upload_grad_table(p));
+    return PS_OK;
+}
+
+extern "C" size_t ps_workspace_bytes(const ps_plan *p) { return p ? p->bytes : 0; }
+
+extern "C" int ps_plan_query(const ps_plan *p, ps_plan_info *info)
+{
+    if (!p || !info) return fail(PS_EINVAL, "plan and info must not be NULL");
+    info->nx = p->nx;
+    info->ny = p->ny;
+    info->nz = p->nz;
+    info->precision = p->precision;
+    info->fp64_columns = p->nmask;
+    info->tau = p->fp64() ? 0.0 : p->tau;
+    info->fft_variant_x = p->geom.variant_x;
+    info->fft_variant_y = p->geom.variant_y;
+    info->spectrum_elems = p->spec_elems();
+    return PS_OK;
+}
+
+// ------------------------------------------------------------------ stages
+template <typename T> static Tables<T> &tables(ps_plan *p);
+template <> Tables<float> &tables<float>(ps_plan *p) { return p->t32; }
+template <> Tables<double> &tables<double>(ps_plan *p) { return p->t64; }
+
+template <typename T> static int fwd(ps_plan *p, const T *rhs, cx_t<T> *spec)
+{
+    PS_HIP(launch_fwd_x<T>(rhs, spec, p->d_rowsum, p->nx, p->ny, p->nz, p->geom, p->spx,
+                           tables<T>(p), p->stream));
+    PS_HIP(launch_level_sums(p->d_rowsum, p->d_S, p->ny, p->nz, p->stream));
+    PS_HIP(launch_fft_y<T>(spec, p->nz * p->L, p->ny, -1, p->geom, p->spy, tables<T>(p), p->stream));
+    return PS_OK;
+}
+
+template <typename T> static int fwd_residual(ps_plan *p, const T *b, const T *x, cx_t<T> *spec, int adjoint)
+{
+    PS_HIP(launch_fwd_x_residual<T>(b, x, spec, p->d_rowsum, p->nx, p->ny, p->nz,
+                                    1.0 / (p->dx * p->dx), 1.0 / (p->dy * p->dy), p->t64.f,
+                                    p->t64.D, adjoint, p->geom, p->spx, tables<T>(p), p->stream));
+    PS_HIP(launch_level_sums(p->d_rowsum, p->d_S, p->ny, p->nz, p->stream));
+    PS_HIP(launch_fft_y<T>(spec, p->nz * p->L, p->ny, -1, p->geom, p->spy, tables<T>(p), p->stream));
+    return PS_OK;
+}
+
+template <typename T> static int columns(ps_plan *p, cx_t<T> *spec, int adjoint, int refine)
+{
+    const int *mc = p->fp64() ? nullptr : p->d_maskcnt;
+    PS_HIP(launch_columns_impl<T>(spec, p->nx, p->ny, p->nz, adjoint, refine, mc, tables<T>(p),
+                                  &p->t64, p->stream));
+    PS_HIP(launch_special<T>(spec, p->nx, p->ny, p->nz, adjoint, p->d_mlist, p->nmask, p->d_S,
+                             p->d_ws, p->t64, p->stream));
+    return PS_OK;
+}
+
+template <typename T> static int inv(ps_plan *p, cx_t<T> *spec, T *out, int accumulate)
+{
+    PS_HIP(launch_fft_y<T>(spec, p->nz * p->L, p->ny, 1, p->geom, p->spy, tables<T>(p), p->stream));
+    PS_HIP(launch_inv_x<T>(spec, out, p->nx, p->ny, p->nz, accumulate, p->geom, p->spx,
+                           tables<T>(p), p->stream));
+    return PS_OK;
+}
+
+template <typename T> static int run(ps_plan *p, const T *in, T *out, int adjoint)
+{
+    auto *spec = reinterpret_cast<cx_t<T> *>(p->d_spec);
+    const int refine = p->precision == PS_FP32_R2;
+    PS_TRY(fwd<T>(p, in, spec));
+    PS_TRY(columns<T>(p, spec, adjoint, refine));
+    PS_TRY(inv<T>(p, spec, out, 0));
+    if (p->precision == PS_FP32_R1) {
+        PS_TRY(fwd_residual<T>(p, in, out, spec, adjoint));
+        PS_TRY(columns<T>(p, spec, adjoint, 0));
+        PS_TRY(inv<T>(p, spec, out, 1));
+    }
+    return PS_OK;
+}
+
+static int solve_common(ps_plan *p, const void *in, void *out, int adjoint)
+{
+    if (!p || !in || !out) return fail(PS_EINVAL, "plan, input and output must not be NULL");
+    if (p->precision == PS_FP32_R1 && in == out)
+        return fail(PS_EINVAL, "the PS_FP32_R1 form needs input and output not to alias");
+    if (p->fp64()) return run<double>(p, (const double *)in, (double *)out, adjoint);
+    return run<float>(p, (const float *)in, (float *)out, adjoint);
+}
+
+extern "C" int ps_solve(ps_plan *p, const void *rhs, void *out) { return solve_common(p, rhs, out, 0); }
+
+extern "C" int ps_solve_adjoint(ps_plan *p, const void *gp, void *grhs)
+{
+    return solve_common(p, gp, grhs, 1);
+}
+
+extern "C" int ps_grad_coeffs(ps_plan *p, const void *lam, const void *x, double *grho)
+{
+    if (!p || !lam || !x || !grho) return fail(PS_EINVAL, "arguments must not be NULL");
+    if (p->fp64())
+        PS_HIP(launch_grad_rho<double>((const double *)lam, (const double *)x, p->nx, p->ny, p->nz,
+                                       p->d_gk, p->d_partial, p->nblk, grho, p->stream));
+    else
+        PS_HIP(launch_grad_rho<float>((const float *)lam, (const float *)x, p->nx, p->ny, p->nz,
+                                      p->d_gk, p->d_partial, p->nblk, grho, p->stream));
+    return PS_OK;
+}
+
+extern "C" int ps_forward_transform(ps_plan *p, const void *rhs, void *spectrum)
+{
+    if (!p || !rhs || !spectrum) return fail(PS_EINVAL, "arguments must not be NULL");
+    if (p->fp64()) return fwd<double>(p, (const double *)rhs, (double2 *)spectrum);
+    return fwd<float>(p, (const float *)rhs, (float2 *)spectrum);
+}
+
+extern "C" int ps_spectral_solve(ps_plan *p, void *spectrum, int adjoint)
+{
+    if (!p || !spectrum) return fail(PS_EINVAL, "arguments must not be NULL");
+    const int refine = p->precision == PS_FP32_R2;
+    if (p->fp64()) return columns<double>(p, (double2 *)spectrum, adjoint != 0, 0);
+    return columns<float>(p, (float2 *)spectrum, adjoint != 0, refine);
+}
+
+extern "C" int ps_inverse_transform(ps_plan *p, const void *spectrum, void *out)
+{
+    if (!p || !spectrum || !out) return fail(PS_EINVAL, "arguments must not be NULL");
+    // The backward y pass runs in place, so work on the plan's own buffer.
+    const size_t bytes = p->spec_elems() * 2 * p->elem();
+    if (spectrum != p->d_spec)
+        PS_HIP(hipMemcpyAsync(p->d_spec, spectrum, bytes, hipMemcpyDeviceToDevice, p->stream));
+    if (p->fp64()) return inv<double>(p, (double2 *)p->d_spec, (double *)out, 0);
+    return inv<float>(p, (float2 *)p->d_spec, (float *)out, 0);
+}
+
+extern "C" const char *ps_status_string(int s)
+{
+    switch (s) {
+    case PS_OK: return "ok";
+    case PS_EINVAL: return "invalid argument";
+    case PS_EUNSUPPORTED: return "unsupported size or precision";
+    case PS_ENOMEM: return "out of memory";
+    case PS_EHIP: return "HIP runtime error";
+    case PS_ESTATE: return "invalid state";
+    default: return "unknown status";
+    }
+}
+
+extern "C" const char *ps_last_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,194 @@
+// Device helpers for the gfx950 pressure-solve kernels: complex arithmetic,
+// small in-register DFTs, and one radix pass of a Stockham (self-sorting)
+// FFT over rows held in LDS.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ps {
+
+template <typename T> struct cx;
+template <> struct cx<float> { using type = float2; };
+template <> struct cx<double> { using type = double2; };
+template <typename T> using cx_t = typename cx<T>::type;
+
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C> __device__ __forceinline__ C cconj(C a) { return C{a.x, -a.y}; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b)
+{
+    return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * (conj(b) if DIR > 0 else b): twiddle tables hold the forward roots.
+template <int DIR, typename C> __device__ __forceinline__ C ctw(C a, C b)
+{
+    if (DIR > 0) b.y = -b.y;
+    return cmul(a, b);
+}
+// a * (DIR * i)
+template <int DIR, typename C> __device__ __forceinline__ C cmul_i(C a)
+{
+    return DIR < 0 ? C{a.y, -a.x} : C{-a.y, a.x};
+}
+template <typename C, typename S> __device__ __forceinline__ C cscale(C a, S s) { return C{a.x * s, a.y * s}; }
+
+// cos and sin of 2 pi m / 16, m = 1..3 (exact mathematical constants).
+#define PS_C16_1 0.92387953251128675613
+#define PS_S16_1 0.38268343236508977173
+#define PS_R2_2 0.70710678118654752440
+#define PS_S3_2 0.86602540378443864676
+
+// ---- small DFTs, X_k = sum_n v_n exp(DIR 2 pi i n k / R), in place --------
+template <int DIR, typename C> __device__ __forceinline__ void dft2(C &a, C &b)
+{
+    C t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft3(C *v)
+{
+    using T = decltype(v[0].x);
+    C s = cadd(v[1], v[2]);
+    C d = csub(v[1], v[2]);
+    C t = C{v[0].x - T(0.5) * s.x, v[0].y - T(0.5) * s.y};
+    C u = cscale(cmul_i<DIR>(d), T(PS_S3_2));
+    v[0] = cadd(v[0], s);
+    v[1] = cadd(t, u);
+    v[2] = csub(t, u);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft4(C *v)
+{
+    C a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+    C c = cadd(v[1], v[3]), d = cmul_i<DIR>(csub(v[1], v[3]));
+    v[0] = cadd(a, c);
+    v[2] = csub(a, c);
+    v[1] = cadd(b, d);
+    v[3] = csub(b, d);
+}
+
+// Radix-2 split of an 8-point DFT: even and odd 4-point DFTs, then
+// X_k = E_k + W8^k O_k, X_{k+4} = E_k - W8^k O_k.
+template <int DIR, typename C> __device__ __forceinline__ void dft8(C *v)
+{
+    using T = decltype(v[0].x);
+    C e[4] = {v[0], v[2], v[4], v[6]};
+    C o[4] = {v[1], v[3], v[5], v[7]};
+    dft4<DIR>(e);
+    dft4<DIR>(o);
+    const T r = T(PS_R2_2);
+    C w1 = C{r, DIR * r}, w3 = C{-r, DIR * r};
+    C o1 = cmul(o[1], w1), o2 = cmul_i<DIR>(o[2]), o3 = cmul(o[3], w3);
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft16(C *v)
+{
+    using T = decltype(v[0].x);
+    C e[8], o[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        e[q] = v[2 * q];
+        o[q] = v[2 * q + 1];
+    }
+    dft8<DIR>(e);
+    dft8<DIR>(o);
+    const T c1 = T(PS_C16_1), s1 = T(PS_S16_1), r2 = T(PS_R2_2);
+    const C w[8] = {C{T(1), T(0)}, C{c1, DIR * s1}, C{r2, DIR * r2}, C{s1, DIR * c1},
+                    C{T(0), T(DIR)}, C{-s1, DIR * c1}, C{-r2, DIR * r2}, C{-c1, DIR * s1}};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        C t = q == 0 ? o[0] : cmul(o[q], w[q]);
+        v[q] = cadd(e[q], t);
+        v[q + 8] = csub(e[q], t);
+    }
+}
+
+template <int R, int DIR, typename C> __device__ __forceinline__ void dft(C *v)
+{
+    if constexpr (R == 2) dft2<DIR>(v[0], v[1]);
+    else if constexpr (R == 3) dft3<DIR>(v);
+    else if constexpr (R == 4) dft4<DIR>(v);
+    else if constexpr (R == 8) dft8<DIR>(v);
+    else if constexpr (R == 16) dft16<DIR>(v);
+}
+
+// ---- Stockham radix pass ---------------------------------------------------
+// Factorisation of a transform length L = r_0 r_1 ... ; ns[s] = r_0...r_{s-1}.
+struct StagePlan {
+    int n;        // number of passes
+    int r[16];
+    int ns[16];
+};
+
+// Butterfly j (0 <= j < L/R) of a pass with stride product Ns: reads the R
+// inputs j + q L/R, twiddles input q by W_{Ns R}^{q (j mod Ns)}, applies the
+// R-point DFT and writes output q to (j - j mod Ns) R + j mod Ns + q Ns.
+// After all passes the row is in natural order.  tw holds the forward roots
+// W_L^m = exp(-2 pi i m / L), m in [0, L).
+template <int R, int DIR, typename C>
+__device__ __forceinline__ void stockham_bfly(const C *src, C *dst, int j, int L, int Ns, const C *tw)
+{
+    const int nb = L / R;
+    const int kk = j % Ns;
+    C v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = src[j + q * nb];
+    if (Ns > 1) {
+        const int m = kk * (L / (Ns * R));
+#pragma unroll
+        for (int q = 1; q < R; ++q) v[q] = ctw<DIR>(v[q], tw[q * m]);
+    }
+    dft<R, DIR>(v);
+    const int base = (j - kk) * R + kk;
+#pragma unroll
+    for (int q = 0; q < R; ++q) dst[base + q * Ns] = v[q];
+}
+
+// All passes over nrows rows of length L stored contiguously in LDS at a;
+// b is a second LDS buffer of the same size.  Returns the buffer holding the
+// result.  Every thread of the block must call it.
+template <int DIR, typename C>
+__device__ C *stockham_rows(C *a, C *b, int nrows, int L, const StagePlan &sp, const C *tw)
+{
+    for (int s = 0; s < sp.n; ++s) {
+        const int R = sp.r[s], Ns = sp.ns[s];
+        const int nb = L / R;
+        const int total = nrows * nb;
+        for (int t = threadIdx.x; t < total; t += blockDim.x) {
+            const int row = t / nb;
+            const int j = t - row * nb;
+            const C *src = a + row * L;
+            C *dst = b + row * L;
+            switch (R) {
+            case 2: stockham_bfly<2, DIR>(src, dst, j, L, Ns, tw); break;
+            case 3: stockham_bfly<3, DIR>(src, dst, j, L, Ns, tw); break;
+            case 4: stockham_bfly<4, DIR>(src, dst, j, L, Ns, tw); break;
+            case 8: stockham_bfly<8, DIR>(src, dst, j, L, Ns, tw); break;
+            default: stockham_bfly<16, DIR>(src, dst, j, L, Ns, tw); break;
+            }
+        }
+        __syncthreads();
+        C *t = a;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// Sum over the 64 lanes of a wavefront, fixed butterfly order.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+} // namespace ps

@@ -1,0 +1,536 @@
+// Column solves of the pressure solve (paper Section 2.1: after the forward
+// transform every horizontal wavenumber carries an independent vertical
+// tridiagonal system, solved up and down its column), the singular mean
+// column, and the density gradient.
+//
+// Per wavenumber (kx, ky) != (0, 0), with s = ax[kx] + ay[ky] > 0, the
+// scaled system is M x = r with
+//   M = tridiag(-f_{k-1/2}, s D_k + f_{k-1/2} + f_{k+1/2}, -f_{k+1/2}),
+//   r_k = rs_k * spectrum_k  (rs_k = -D_k/(nx ny) forward, -1/(nx ny) adjoint),
+// and the spectrum is overwritten by os_k * x_k (os_k = 1 forward, D_k adjoint).
+// M is a symmetric, diagonally dominant M-matrix.  It is eliminated from both
+// ends towards the middle row m = nz/2 (a "twisted" factorisation), each half
+// in dominance-excess form (pivot u = e + f_next with
+// e_i = s D_i + f_prev e_{i-1}/u_{i-1}, built from positive terms only).
+#include "ps_internal.h"
+#include "../../include/pressure_solve.h"
+
+namespace ps {
+
+// ----------------------------------------------------------- twisted sweep
+// v holds the thread's half of the right-hand side in elimination order
+// (low half: levels 0..m-1; high half: levels nz-1 down to m+1); on return
+// it holds the solution for those levels.  rm is the middle row's
+// right-hand side.  Both lanes of a column pair (lane and lane ^ 32) return
+// the same x_m.  Pivots are recomputed block by block (CH rows) in the
+// backward pass from checkpoints of the recursion state instead of being
+// kept in registers.
+template <typename T, int NH, int CH>
+__device__ __forceinline__ T twisted_solve(T (&v)[NH], int n, int half, int m, int nz, T s,
+                                           const T *sf, const T *sD, T rm)
+{
+    constexpr int NB = (NH + CH - 1) / CH;
+    T qck[NB];
+    T q = T(0), g = T(0), y = T(0);
+#pragma unroll
+    for (int i = 0; i < NH; ++i) {
+        if (i % CH == 0) qck[i / CH] = q;
+        if (i < n) {
+            const int k = half ? nz - 1 - i : i;
+            const T fp = half ? sf[k + 1] : sf[k];
+            const T fn = half ? sf[k] : sf[k + 1];
+            const T e = s * sD[k] + fp * q;
+            const T gi = T(1) / (e + fn);
+            y = v[i] + (fp * g) * y;
+            v[i] = y;
+            q = e * gi;
+            g = gi;
+        }
+    }
+    T ma = T(0), mb = T(0);
+    if (n > 0) {
+        const int kl = half ? nz - n : n - 1;
+        const T fn = half ? sf[kl] : sf[kl + 1];
+        ma = fn * q;
+        mb = (fn * g) * y;
+    }
+    const T pa = __shfl_xor(ma, 32, 64), pb = __shfl_xor(mb, 32, 64);
+    const T la = half ? pa : ma, lb = half ? pb : mb;
+    const T ha = half ? ma : pa, hb = half ? mb : pb;
+    const T xm = ((rm + lb) + hb) / ((s * sD[m] + la) + ha);
+
+    T xn = xm;
+#pragma unroll
+    for (int bb = NB - 1; bb >= 0; --bb) {
+        if (bb * CH < n) {
+            T gb[CH];
+            T qq = qck[bb];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int i = bb * CH + c;
+                if (i < n && i < NH) {
+                    const int k = half ? nz - 1 - i : i;
+                    const T fp = half ? sf[k + 1] : sf[k];
+                    const T fn = half ? sf[k] : sf[k + 1];
+                    const T e = s * sD[k] + fp * qq;
+                    const T gi = T(1) / (e + fn);
+                    gb[c] = gi;
+                    qq = e * gi;
+                }
+            }
+#pragma unroll
+            for (int c = CH - 1; c >= 0; --c) {
+                const int i = bb * CH + c;
+                if (i < n && i < NH) {
+                    const int k = half ? nz - 1 - i : i;
+                    const T fn = half ? sf[k] : sf[k + 1];
+                    xn = gb[c] * (v[i] + fn * xn);
+                    v[i] = xn;
+                }
+            }
+        }
+    }
+    return xm;
+}
+
+// ----------------------------------------------------------- main columns
+// Four lanes per column: lane = half*32 + 2*c + comp (comp: real/imaginary,
+// half: low/high part of the column).  A wavefront covers 16 consecutive
+// columns (consecutive ky), so each level's load is two contiguous 128-byte
+// runs (FP32).  Columns kx = 0 are left to k_special.  Columns flagged in
+// maskcnt (min(ky, ny-ky) < maskcnt[kx]) are computed but not stored: they
+// are solved in FP64 by k_special.
+// REFINE: one refinement of M x = r with the residual formed in FP64 from the
+// FP64 coefficients (ax64/ay64/f64/D64), solved with the same FP32 sweep.
+template <typename T, int NH, int CH, bool REFINE>
+__global__ __launch_bounds__(256) void k_columns(cx_t<T> *__restrict__ spec, int L, int ny, int nz,
+                                                 const T *__restrict__ ax, const T *__restrict__ ay,
+                                                 const T *__restrict__ fg, const T *__restrict__ Dg,
+                                                 const T *__restrict__ rsg,
+                                                 const T *__restrict__ osg,
+                                                 const int *__restrict__ maskcnt,
+                                                 const double *__restrict__ ax64,
+                                                 const double *__restrict__ ay64,
+                                                 const double *__restrict__ f64,
+                                                 const double *__restrict__ D64,
+                                                 const double *__restrict__ rs64)
+{
+    __shared__ T sf[PS_MAX_NZ + 1], sD[PS_MAX_NZ], srs[PS_MAX_NZ], sos[PS_MAX_NZ];
+    __shared__ double df[REFINE ? PS_MAX_NZ + 1 : 1], dD[REFINE ? PS_MAX_NZ : 1],
+        drs[REFINE ? PS_MAX_NZ : 1];
+    for (int t = threadIdx.x; t <= nz; t += blockDim.x) {
+        sf[t] = fg[t];
+        if (REFINE) df[t] = f64[t];
+        if (t < nz) {
+            sD[t] = Dg[t];
+            srs[t] = rsg[t];
+            sos[t] = osg ? osg[t] : T(1);
+            if (REFINE) {
+                dD[t] = D64[t];
+                drs[t] = rs64[t];
+            }
+        }
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int half = lane >> 5, comp = lane & 1, cl = (lane & 31) >> 1;
+    const long ncol = (long)L * ny;
+    const long col = (long)ny + ((long)blockIdx.x * 4 + wave) * 16 + cl;
+    const bool valid = col < ncol;
+    const int kx = valid ? (int)(col / ny) : 1;
+    const int ky = valid ? (int)(col - (long)kx * ny) : 0;
+    const T s = ax[kx] + ay[ky];
+    bool store = valid;
+    if (maskcnt && valid) {
+        const int d = min(ky, ny - ky);
+        if (d < maskcnt[kx]) store = false;
+    }
+    const size_t ls = (size_t)2 * L * ny;
+    T *cp = reinterpret_cast<T *>(spec) + 2 * (valid ? col : 0) + comp;
+    const int m = nz >> 1;
+    const int n = half ? nz - 1 - m : m;
+
+    T raw[REFINE ? NH : 1];
+    T v[NH];
+#pragma unroll
+    for (int i = 0; i < NH; ++i) {
+        if (i < n) {
+            const int k = half ? nz - 1 - i : i;
+            const T x = valid ? cp[(size_t)k * ls] : T(0);
+            if (REFINE) raw[i] = x;
+            v[i] = x * srs[k];
+        }
+    }
+    const T rawm = valid ? cp[(size_t)m * ls] : T(0);
+    T xm = twisted_solve<T, NH, CH>(v, n, half, m, nz, s, sf, sD, rawm * srs[m]);
+
+    if constexpr (REFINE) {
+        // residual rho = r - M x in FP64, r = rs * spectrum formed in FP64
+        const double s64 = ax64[kx] + ay64[ky];
+        T mylast = T(0); // v[n-1], selected without dynamic indexing
+#pragma unroll
+        for (int i = 0; i < NH; ++i)
+            if (i == n - 1) mylast = v[i];
+        const T other = __shfl_xor(mylast, 32, 64);
+        const double xlo = half ? (double)other : (double)mylast; // x_{m-1}
+        const double xhi = half ? (double)mylast : (double)other; // x_{m+1}
+        // the residual overwrites the stored right-hand side in place
+#pragma unroll
+        for (int i = 0; i < NH; ++i) {
+            if (i < n) {
+                const int k = half ? nz - 1 - i : i;
+                const double fp = half ? df[k + 1] : df[k];
+                const double fn = half ? df[k] : df[k + 1];
+                const double xp = i > 0 ? (double)v[i - 1] : 0.0;
+                const double xnx = i + 1 < n ? (double)v[i + 1] : (double)xm;
+                const double diag = s64 * dD[k] + df[k] + df[k + 1];
+                const double r = drs[k] * (double)raw[i];
+                raw[i] = (T)(r - (diag * (double)v[i] - fp * xp - fn * xnx));
+            }
+        }
+        const double diagm = s64 * dD[m] + df[m] + df[m + 1];
+        const double rmid = drs[m] * (double)rawm;
+        const T dm = (T)(rmid - (diagm * (double)xm - df[m] * xlo - df[m + 1] * xhi));
+        const T em = twisted_solve<T, NH, CH>(raw, n, half, m, nz, s, sf, sD, dm);
+#pragma unroll
+        for (int i = 0; i < NH; ++i)
+            if (i < n) v[i] += raw[i];
+        xm += em;
+    }
+
+    if (store) {
+#pragma unroll
+        for (int i = 0; i < NH; ++i) {
+            if (i < n) {
+                const int k = half ? nz - 1 - i : i;
+                cp[(size_t)k * ls] = v[i] * sos[k];
+            }
+        }
+        if (half) cp[(size_t)m * ls] = xm * sos[m];
+    }
+}
+
+// ----------------------------------------------------------- FP64 columns
+// One thread per task, FP64 throughout, column temporaries in the
+// workspace laid out [quantity][level][task] (consecutive tasks contiguous).
+__device__ void seq_column(int nz, double s, const double *f, const double *D, double *yr,
+                           double *yi, double *gg, size_t st)
+{
+    double q = 0.0, g = 0.0, pr = 0.0, pi = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        const double fp = f[k], fn = f[k + 1];
+        const double e = s * D[k] + fp * q;
+        const double gi = 1.0 / (e + fn);
+        const double r = yr[k * st] + (fp * g) * pr;
+        const double i = yi[k * st] + (fp * g) * pi;
+        yr[k * st] = r;
+        yi[k * st] = i;
+        gg[k * st] = gi;
+        q = e * gi;
+        g = gi;
+        pr = r;
+        pi = i;
+    }
+    double xr = 0.0, xi = 0.0;
+    for (int k = nz - 1; k >= 0; --k) {
+        const double fn = f[k + 1];
+        xr = gg[k * st] * (yr[k * st] + fn * xr);
+        xi = gg[k * st] * (yi[k * st] + fn * xi);
+        yr[k * st] = xr;
+        yi[k * st] = xi;
+    }
+}
+
+// Tasks t in [0, ny/2]: the packed kx = 0 row.  Slot (kx=0, ky) holds
+// Z = A + i B with A = DFT_y of the x-DC coefficients (modes (0, ky)) and
+// B = DFT_y of the x-Nyquist coefficients (modes (nx/2, ky)); both come from
+// real sequences, so A_ky = (Z_ky + conj Z_{-ky})/2 and
+// B_ky = (Z_ky - conj Z_{-ky})/(2i).  The task solves A and B for ky and
+// repacks ky and -ky.  Mode (0,0) is the singular mean column: it is taken
+// from the FP64 level sums S_k instead of the transform (see below).
+// Tasks t > ny/2: near-singular columns kx >= 1 from mlist, in FP64.
+template <typename T>
+__global__ __launch_bounds__(64) void k_special(cx_t<T> *__restrict__ spec, int nx, int ny, int nz,
+                                                int adjoint, const int *__restrict__ mlist,
+                                                int nmask, const double *__restrict__ S,
+                                                double *__restrict__ ws, const double *__restrict__ ax,
+                                                const double *__restrict__ ay,
+                                                const double *__restrict__ fg,
+                                                const double *__restrict__ Dg,
+                                                const double *__restrict__ rs,
+                                                const double *__restrict__ os)
+{
+    __shared__ double f[PS_MAX_NZ + 1], D[PS_MAX_NZ];
+    for (int t = threadIdx.x; t <= nz; t += blockDim.x) {
+        f[t] = fg[t];
+        if (t < nz) D[t] = Dg[t];
+    }
+    __syncthreads();
+    const int L = nx / 2;
+    const int npair = ny / 2 + 1;
+    const int ntask = npair + nmask;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntask) return;
+    const size_t st = (size_t)ntask;
+    double *Ar = ws + (0 * (size_t)nz) * st + t, *Ai = ws + (1 * (size_t)nz) * st + t;
+    double *Br = ws + (2 * (size_t)nz) * st + t, *Bi = ws + (3 * (size_t)nz) * st + t;
+    double *G = ws + (4 * (size_t)nz) * st + t;
+    const size_t lvl = (size_t)L * ny;
+    const double on = 1.0 / ((double)nx * (double)ny);
+
+    if (t < npair) {
+        const int ky = t, kp = (ny - t) % ny;
+        for (int k = 0; k < nz; ++k) {
+            const cx_t<T> z = spec[(size_t)k * lvl + ky];
+            const cx_t<T> w = spec[(size_t)k * lvl + kp];
+            const double zr = z.x, zi = z.y, wr = w.x, wi = -(double)w.y; // w = conj Z_{-ky}
+            Ar[k * st] = rs[k] * 0.5 * (zr + wr);
+            Ai[k * st] = rs[k] * 0.5 * (zi + wi);
+            Br[k * st] = rs[k] * 0.5 * (zi - wi);
+            Bi[k * st] = rs[k] * -0.5 * (zr - wr);
+        }
+        if (ky == 0) {
+            // Mean column from the FP64 level sums.  Forward: level means of
+            // b minus mu (the D-weighted mean); V x = c by flux prefix sums
+            // F_{k+1/2} = sum_{j<=k} D_j c_j, x_{k+1} = x_k + F/f_{k+1/2};
+            // gauge: zero mean over levels.  Adjoint: level means of w minus
+            // the plain mean; V z = c / D; gauge sum D z = 0; output D z.
+            double num = 0.0, den = 0.0, tot = 0.0;
+            for (int k = 0; k < nz; ++k) {
+                num += D[k] * S[k];
+                den += D[k];
+                tot += S[k];
+            }
+            const double mu = adjoint ? tot * on / (double)nz : num * on / den;
+            double F = 0.0, x = 0.0, acc = 0.0, wsum = 0.0;
+            Ar[0] = 0.0;
+            for (int k = 0; k + 1 < nz; ++k) {
+                const double c = S[k] * on - mu;
+                F += adjoint ? c : D[k] * c;
+                x += F / f[k + 1];
+                Ar[(k + 1) * st] = x;
+            }
+            for (int k = 0; k < nz; ++k) {
+                const double wk = adjoint ? D[k] : 1.0;
+                acc += wk * Ar[k * st];
+                wsum += wk;
+            }
+            const double shift = acc / wsum;
+            for (int k = 0; k < nz; ++k) {
+                Ar[k * st] -= shift;
+                Ai[k * st] = 0.0;
+            }
+        } else {
+            seq_column(nz, ay[ky], f, D, Ar, Ai, G, st);
+        }
+        seq_column(nz, ax[L] + ay[ky], f, D, Br, Bi, G, st);
+        for (int k = 0; k < nz; ++k) {
+            const double o = os ? os[k] : 1.0;
+            const double ar = o * Ar[k * st], ai = o * Ai[k * st];
+            const double br = o * Br[k * st], bi = o * Bi[k * st];
+            spec[(size_t)k * lvl + ky] = cx_t<T>{(T)(ar - bi), (T)(ai + br)};
+            if (kp != ky) spec[(size_t)k * lvl + kp] = cx_t<T>{(T)(ar + bi), (T)(br - ai)};
+        }
+    } else {
+        const int c = mlist[t - npair];
+        const int kx = c / ny, ky = c - kx * ny;
+        for (int k = 0; k < nz; ++k) {
+            const cx_t<T> z = spec[(size_t)k * lvl + c];
+            Ar[k * st] = rs[k] * (double)z.x;
+            Ai[k * st] = rs[k] * (double)z.y;
+        }
+        seq_column(nz, ax[kx] + ay[ky], f, D, Ar, Ai, G, st);
+        for (int k = 0; k < nz; ++k) {
+            const double o = os ? os[k] : 1.0;
+            spec[(size_t)k * lvl + c] = cx_t<T>{(T)(o * Ar[k * st]), (T)(o * Ai[k * st])};
+        }
+    }
+}
+
+// ----------------------------------------------------------- level sums
+__global__ __launch_bounds__(256) void k_level_sums(const double *__restrict__ rowsum,
+                                                    double *__restrict__ S, int ny)
+{
+    __shared__ double part[256];
+    const int k = blockIdx.x;
+    double s = 0.0;
+    for (int j = threadIdx.x; j < ny; j += blockDim.x) s += rowsum[(size_t)k * ny + j];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) S[k] = part[0];
+}
+
+hipError_t launch_level_sums(const double *rowsum, double *S, int ny, int nz, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_level_sums, dim3(nz), dim3(256), 0, st, rowsum, S, ny);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------- launchers
+template <typename T, int NH, bool REFINE>
+static hipError_t columns_nh(cx_t<T> *spec, int L, int ny, int nz, const T *rs, const T *os,
+                             const int *maskcnt, const Tables<T> &tb, const double *ax64,
+                             const double *ay64, const double *f64, const double *D64,
+                             const double *rs64, hipStream_t st)
+{
+    constexpr int CH = NH < 8 ? NH : 8;
+    const long ncols = (long)(L - 1) * ny;
+    if (ncols <= 0) return hipSuccess;
+    const long grid = (ncols + 63) / 64;
+    hipLaunchKernelGGL((k_columns<T, NH, CH, REFINE>), dim3((unsigned)grid), dim3(256), 0, st, spec,
+                       L, ny, nz, tb.ax, tb.ay, tb.f, tb.D, rs, os, maskcnt, ax64, ay64, f64, D64,
+                       rs64);
+    return hipGetLastError();
+}
+
+template <typename T, bool REFINE>
+static hipError_t columns_dispatch(cx_t<T> *spec, int L, int ny, int nz, const T *rs, const T *os,
+                                   const int *maskcnt, const Tables<T> &tb, const double *ax64,
+                                   const double *ay64, const double *f64, const double *D64,
+                                   const double *rs64, hipStream_t st)
+{
+    const int need = nz / 2;
+#define PS_NH(N)                                                                                   \
+    if (need <= N)                                                                                 \
+        return columns_nh<T, N, REFINE>(spec, L, ny, nz, rs, os, maskcnt, tb, ax64, ay64, f64,     \
+                                        D64, rs64, st);
+    PS_NH(1) PS_NH(2) PS_NH(4) PS_NH(8) PS_NH(16) PS_NH(32) PS_NH(64) PS_NH(128)
+#undef PS_NH
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_columns_impl(cx_t<T> *spec, int nx, int ny, int nz, int adjoint, int refine,
+                               const int *maskcnt, const Tables<T> &tb, const Tables<double> *t64,
+                               hipStream_t st)
+{
+    const int L = nx / 2;
+    const T *rs = adjoint ? tb.rs_adj : tb.rs_fwd;
+    const T *os = adjoint ? tb.os_adj : nullptr;
+    if constexpr (std::is_same<T, float>::value) {
+        if (refine) {
+            const double *rs64 = adjoint ? t64->rs_adj : t64->rs_fwd;
+            return columns_dispatch<float, true>(spec, L, ny, nz, rs, os, maskcnt, tb, t64->ax,
+                                                 t64->ay, t64->f, t64->D, rs64, st);
+        }
+    }
+    return columns_dispatch<T, false>(spec, L, ny, nz, rs, os, maskcnt, tb, nullptr, nullptr,
+                                      nullptr, nullptr, nullptr, st);
+}
+
+template hipError_t launch_columns_impl<float>(cx_t<float> *, int, int, int, int, int, const int *,
+                                               const Tables<float> &, const Tables<double> *,
+                                               hipStream_t);
+template hipError_t launch_columns_impl<double>(cx_t<double> *, int, int, int, int, int,
+                                                const int *, const Tables<double> &,
+                                                const Tables<double> *, hipStream_t);
+
+template <typename T>
+hipError_t launch_special(cx_t<T> *spec, int nx, int ny, int nz, int adjoint, const int *mlist,
+                          int nmask, const double *S, double *ws, const Tables<double> &tb64,
+                          hipStream_t st)
+{
+    const int ntask = ny / 2 + 1 + nmask;
+    const int grid = (ntask + 63) / 64;
+    hipLaunchKernelGGL(k_special<T>, dim3(grid), dim3(64), 0, st, spec, nx, ny, nz, adjoint, mlist,
+                       nmask, S, ws, tb64.ax, tb64.ay, tb64.f, tb64.D,
+                       adjoint ? tb64.rs_adj : tb64.rs_fwd, adjoint ? tb64.os_adj : nullptr);
+    return hipGetLastError();
+}
+
+template hipError_t launch_special<float>(cx_t<float> *, int, int, int, int, const int *, int,
+                                          const double *, double *, const Tables<double> &,
+                                          hipStream_t);
+template hipError_t launch_special<double>(cx_t<double> *, int, int, int, int, const int *, int,
+                                           const double *, double *, const Tables<double> &,
+                                           hipStream_t);
+
+// ----------------------------------------------------------- density gradient
+// g_k = -sum_ij [ -lam_k (V p)_k / rho_k
+//                 + 1/2 gam_{k+1/2} (lam_k/D_k - lam_{k+1}/D_{k+1})
+//                 + 1/2 gam_{k-1/2} (lam_{k-1}/D_{k-1} - lam_k/D_k) ],
+// gam_{k+1/2} = (p_{k+1} - p_k) / h_{k+1/2}: the derivative of the vertical
+// operator's three rho-dependent ingredients (1/D_k of row k and the face
+// densities on either side of level k).  Thread per horizontal point, a
+// chunk of GK levels per block row; per-level block sums are written in
+// fixed order and reduced by k_grad_reduce (no atomics).
+// gk = [f (nz+1) | D (nz) | rho (nz) | 1/h (nz+1, same indexing as f)].
+constexpr int GK = 16;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_grad_rho(const T *__restrict__ lam, const T *__restrict__ p,
+                                                  int nxy, int nz, const double *__restrict__ gk,
+                                                  double *__restrict__ partial, int nblk)
+{
+    __shared__ double red[4][GK];
+    const double *f = gk, *D = gk + nz + 1, *rho = D + nz, *ih = rho + nz;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k0 = blockIdx.y * GK;
+    const bool ok = c < nxy;
+    auto P = [&](int k) { return ok && k >= 0 && k < nz ? (double)p[(size_t)k * nxy + c] : 0.0; };
+    auto Lm = [&](int k) { return ok && k >= 0 && k < nz ? (double)lam[(size_t)k * nxy + c] : 0.0; };
+    double pm = P(k0 - 1), pc = P(k0), lm = Lm(k0 - 1), lc = Lm(k0);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int kk = 0; kk < GK; ++kk) {
+        const int k = k0 + kk;
+        if (k >= nz) break;
+        const double pp = P(k + 1), lp = Lm(k + 1);
+        double Vp = 0.0, t = 0.0;
+        if (k + 1 < nz) Vp += f[k + 1] * (pp - pc);
+        if (k > 0) Vp -= f[k] * (pc - pm);
+        Vp /= D[k];
+        t = -lc * Vp / rho[k];
+        if (k + 1 < nz) t += 0.5 * (pp - pc) * ih[k + 1] * (lc / D[k] - lp / D[k + 1]);
+        if (k > 0) t += 0.5 * (pc - pm) * ih[k] * (lm / D[k - 1] - lc / D[k]);
+        t = wave_sum(ok ? t : 0.0);
+        if (lane == 0) red[wv][kk] = t;
+        pm = pc;
+        pc = pp;
+        lm = lc;
+        lc = lp;
+    }
+    __syncthreads();
+    if (threadIdx.x < GK && k0 + (int)threadIdx.x < nz) {
+        const int kk = threadIdx.x;
+        partial[(size_t)(k0 + kk) * nblk + blockIdx.x] =
+            ((red[0][kk] + red[1][kk]) + red[2][kk]) + red[3][kk];
+    }
+}
+
+__global__ void k_grad_reduce(const double *__restrict__ partial, int nblk, int nz,
+                              double *__restrict__ g)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nz) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += partial[(size_t)k * nblk + b];
+    g[k] = -s;
+}
+
+int grad_blocks(int nx, int ny) { return (nx * ny + 255) / 256; }
+
+template <typename T>
+hipError_t launch_grad_rho(const T *lam, const T *p, int nx, int ny, int nz, const double *gk,
+                           double *partial, int nblk, double *grho, hipStream_t st)
+{
+    dim3 grid(nblk, (nz + GK - 1) / GK);
+    hipLaunchKernelGGL(k_grad_rho<T>, grid, dim3(256), 0, st, lam, p, nx * ny, nz, gk, partial,
+                       nblk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_grad_reduce, dim3((nz + 63) / 64), dim3(64), 0, st, partial, nblk, nz,
+                       grho);
+    return hipGetLastError();
+}
+
+template hipError_t launch_grad_rho<float>(const float *, const float *, int, int, int,
+                                           const double *, double *, int, double *, hipStream_t);
+template hipError_t launch_grad_rho<double>(const double *, const double *, int, int, int,
+                                            const double *, double *, int, double *, hipStream_t);
+
+} // namespace ps
