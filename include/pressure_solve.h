@@ -152,6 +152,19 @@ int ps_plan_autotune(ps_plan *plan, int reps);
 int ps_tune_cache_save(const char *path);
 int ps_tune_cache_load(const char *path);
 
+/* ---- per-kernel timing ---------------------------------------------------
+ * While enabled, every kernel the plan enqueues is bracketed by a pair of HIP
+ * events recorded on the plan's stream, and the elapsed times are
+ * accumulated per kernel.  ps_plan_profile(plan, 1) clears the totals and
+ * starts recording; ps_plan_profile(plan, 0) stops.  ps_plan_profile_report
+ * synchronises the stream and returns, for kernel index idx = 0, 1, ...,
+ * its name, total milliseconds and number of launches; PS_EINVAL past the
+ * last index.  Profiling adds an event pair per launch, so time steps with it
+ * disabled when the whole-step rate matters. */
+int ps_plan_profile(ps_plan *plan, int enable);
+int ps_plan_profile_report(ps_plan *plan, int idx, const char **name, double *total_ms,
+                           int *launches);
+
 /* ---- stages, for testing each kernel on its own ------------------------
  * spectrum: device buffer of spectrum_elems complex values of the plan's
  * element type (interleaved re, im) in the packed, transposed layout

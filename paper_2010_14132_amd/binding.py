@@ -59,6 +59,10 @@ SIGNATURES = {
                                        ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.c_int, _vp]),
     "ps_batch_solve": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "ps_batch_destroy": (ctypes.c_int, [_vp]),
+    "ps_plan_profile": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "ps_plan_profile_report": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
+                                              ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_int)]),
     "ps_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ps_last_error": (ctypes.c_char_p, []),
 }
@@ -198,6 +202,29 @@ class Plan:
     def autotune(self, reps: int = 5):
         self._sync_stream()
         check(load().ps_plan_autotune(self._h, int(reps)), "ps_plan_autotune")
+
+    def profile(self, enable: bool):
+        """Start (clearing totals) or stop per-kernel event timing."""
+        self._sync_stream()
+        check(load().ps_plan_profile(self._h, int(bool(enable))), "ps_plan_profile")
+
+    def profile_report(self) -> dict:
+        """{kernel name: (total ms, launches)} for kernels launched while
+        profiling was on (synchronises)."""
+        out = {}
+        i = 0
+        lib = load()
+        while True:
+            name = ctypes.c_char_p()
+            ms = ctypes.c_double()
+            n = ctypes.c_int()
+            if lib.ps_plan_profile_report(self._h, i, ctypes.byref(name), ctypes.byref(ms),
+                                          ctypes.byref(n)) != 0:
+                break
+            if n.value:
+                out[name.value.decode()] = (ms.value, n.value)
+            i += 1
+        return out
 
     def spectrum_shape(self):
         return (self.nz, self.nx // 2, self.ny)

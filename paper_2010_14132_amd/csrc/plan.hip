@@ -66,7 +66,46 @@ StagePlan make_stage_plan(int L)
 
 } // namespace ps
 
+// Per-kernel event timing (see ps_plan_profile).
+enum KernelId { K_FWD_X, K_FWD_X_RES, K_LEVEL_SUMS, K_FFT_Y_FWD, K_COLUMNS, K_SPECIAL, K_FFT_Y_INV,
+                K_INV_X, K_GRAD, K_COUNT };
+static const char *const kKernelNames[K_COUNT] = {
+    "fwd_x", "fwd_x_residual", "level_sums", "fft_y_fwd", "columns", "special_fp64",
+    "fft_y_inv", "inv_x", "grad_rho"};
+
+struct Profiler {
+    bool on = false;
+    struct Rec {
+        int id;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    double total_ms[K_COUNT] = {};
+    int launches[K_COUNT] = {};
+    hipEvent_t get()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    ~Profiler()
+    {
+        for (auto &r : recs) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
 struct ps_plan {
+    Profiler prof;
     int nx = 0, ny = 0, nz = 0, L = 0, precision = 0;
     double dx = 0, dy = 0, tau = 0;
     std::vector<double> dz, rho;
@@ -395,6 +434,60 @@ extern "C" int ps_plan_query(const ps_plan *p, ps_plan_info *info)
     return PS_OK;
 }
 
+// ------------------------------------------------------------------ timing
+// Brackets one enqueue with profiling events when profiling is on.
+template <typename F> static hipError_t timed(ps_plan *p, int id, F &&launch)
+{
+    if (!p->prof.on) return launch();
+    hipEvent_t a = p->prof.get(), b = p->prof.get();
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, p->stream);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(b, p->stream);
+    p->prof.recs.push_back({id, a, b});
+    return e;
+}
+
+static int collect_profile(ps_plan *p)
+{
+    PS_HIP(hipStreamSynchronize(p->stream));
+    for (auto &r : p->prof.recs) {
+        float ms = 0.f;
+        PS_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        p->prof.total_ms[r.id] += ms;
+        p->prof.launches[r.id] += 1;
+        p->prof.pool.push_back(r.a);
+        p->prof.pool.push_back(r.b);
+    }
+    p->prof.recs.clear();
+    return PS_OK;
+}
+
+extern "C" int ps_plan_profile(ps_plan *p, int enable)
+{
+    if (!p) return fail(PS_EINVAL, "plan is NULL");
+    PS_TRY(collect_profile(p));
+    if (enable) {
+        for (int i = 0; i < K_COUNT; ++i) {
+            p->prof.total_ms[i] = 0.0;
+            p->prof.launches[i] = 0;
+        }
+    }
+    p->prof.on = enable != 0;
+    return PS_OK;
+}
+
+extern "C" int ps_plan_profile_report(ps_plan *p, int idx, const char **name, double *total_ms,
+                                      int *launches)
+{
+    if (!p || idx < 0 || idx >= K_COUNT) return fail(PS_EINVAL, "bad plan or kernel index");
+    PS_TRY(collect_profile(p));
+    if (name) *name = kKernelNames[idx];
+    if (total_ms) *total_ms = p->prof.total_ms[idx];
+    if (launches) *launches = p->prof.launches[idx];
+    return PS_OK;
+}
+
 // ------------------------------------------------------------------ stages
 template <typename T> static Tables<T> &tables(ps_plan *p);
 template <> Tables<float> &tables<float>(ps_plan *p) { return p->t32; }
@@ -402,38 +495,60 @@ template <> Tables<double> &tables<double>(ps_plan *p) { return p->t64; }
 
 template <typename T> static int fwd(ps_plan *p, const T *rhs, cx_t<T> *spec)
 {
-    PS_HIP(launch_fwd_x<T>(rhs, spec, p->d_rowsum, p->nx, p->ny, p->nz, p->geom, p->spx,
-                           tables<T>(p), p->stream));
-    PS_HIP(launch_level_sums(p->d_rowsum, p->d_S, p->ny, p->nz, p->stream));
-    PS_HIP(launch_fft_y<T>(spec, p->nz * p->L, p->ny, -1, p->geom, p->spy, tables<T>(p), p->stream));
+    PS_HIP(timed(p, K_FWD_X, [&] {
+        return launch_fwd_x<T>(rhs, spec, p->d_rowsum, p->nx, p->ny, p->nz, p->geom, p->spx,
+                               tables<T>(p), p->stream);
+    }));
+    PS_HIP(timed(p, K_LEVEL_SUMS,
+                 [&] { return launch_level_sums(p->d_rowsum, p->d_S, p->ny, p->nz, p->stream); }));
+    PS_HIP(timed(p, K_FFT_Y_FWD, [&] {
+        return launch_fft_y<T>(spec, p->nz * p->L, p->ny, -1, p->geom, p->spy, tables<T>(p),
+                               p->stream);
+    }));
     return PS_OK;
 }
 
 template <typename T> static int fwd_residual(ps_plan *p, const T *b, const T *x, cx_t<T> *spec, int adjoint)
 {
-    PS_HIP(launch_fwd_x_residual<T>(b, x, spec, p->d_rowsum, p->nx, p->ny, p->nz,
-                                    1.0 / (p->dx * p->dx), 1.0 / (p->dy * p->dy), p->t64.f,
-                                    p->t64.D, adjoint, p->geom, p->spx, tables<T>(p), p->stream));
-    PS_HIP(launch_level_sums(p->d_rowsum, p->d_S, p->ny, p->nz, p->stream));
-    PS_HIP(launch_fft_y<T>(spec, p->nz * p->L, p->ny, -1, p->geom, p->spy, tables<T>(p), p->stream));
+    PS_HIP(timed(p, K_FWD_X_RES, [&] {
+        return launch_fwd_x_residual<T>(b, x, spec, p->d_rowsum, p->nx, p->ny, p->nz,
+                                        1.0 / (p->dx * p->dx), 1.0 / (p->dy * p->dy), p->t64.f,
+                                        p->t64.D, adjoint, p->geom, p->spx, tables<T>(p),
+                                        p->stream);
+    }));
+    PS_HIP(timed(p, K_LEVEL_SUMS,
+                 [&] { return launch_level_sums(p->d_rowsum, p->d_S, p->ny, p->nz, p->stream); }));
+    PS_HIP(timed(p, K_FFT_Y_FWD, [&] {
+        return launch_fft_y<T>(spec, p->nz * p->L, p->ny, -1, p->geom, p->spy, tables<T>(p),
+                               p->stream);
+    }));
     return PS_OK;
 }
 
 template <typename T> static int columns(ps_plan *p, cx_t<T> *spec, int adjoint, int refine)
 {
     const int *mc = p->fp64() ? nullptr : p->d_maskcnt;
-    PS_HIP(launch_columns_impl<T>(spec, p->nx, p->ny, p->nz, adjoint, refine, mc, tables<T>(p),
-                                  &p->t64, p->stream));
-    PS_HIP(launch_special<T>(spec, p->nx, p->ny, p->nz, adjoint, p->d_mlist, p->nmask, p->d_S,
-                             p->d_ws, p->t64, p->stream));
+    PS_HIP(timed(p, K_COLUMNS, [&] {
+        return launch_columns_impl<T>(spec, p->nx, p->ny, p->nz, adjoint, refine, mc,
+                                      tables<T>(p), &p->t64, p->stream);
+    }));
+    PS_HIP(timed(p, K_SPECIAL, [&] {
+        return launch_special<T>(spec, p->nx, p->ny, p->nz, adjoint, p->d_mlist, p->nmask,
+                                 p->d_S, p->d_ws, p->t64, p->stream);
+    }));
     return PS_OK;
 }
 
 template <typename T> static int inv(ps_plan *p, cx_t<T> *spec, T *out, int accumulate)
 {
-    PS_HIP(launch_fft_y<T>(spec, p->nz * p->L, p->ny, 1, p->geom, p->spy, tables<T>(p), p->stream));
-    PS_HIP(launch_inv_x<T>(spec, out, p->nx, p->ny, p->nz, accumulate, p->geom, p->spx,
-                           tables<T>(p), p->stream));
+    PS_HIP(timed(p, K_FFT_Y_INV, [&] {
+        return launch_fft_y<T>(spec, p->nz * p->L, p->ny, 1, p->geom, p->spy, tables<T>(p),
+                               p->stream);
+    }));
+    PS_HIP(timed(p, K_INV_X, [&] {
+        return launch_inv_x<T>(spec, out, p->nx, p->ny, p->nz, accumulate, p->geom, p->spx,
+                               tables<T>(p), p->stream);
+    }));
     return PS_OK;
 }
 
@@ -471,12 +586,13 @@ extern "C" int ps_solve_adjoint(ps_plan *p, const void *gp, void *grhs)
 extern "C" int ps_grad_coeffs(ps_plan *p, const void *lam, const void *x, double *grho)
 {
     if (!p || !lam || !x || !grho) return fail(PS_EINVAL, "arguments must not be NULL");
-    if (p->fp64())
-        PS_HIP(launch_grad_rho<double>((const double *)lam, (const double *)x, p->nx, p->ny, p->nz,
-                                       p->d_gk, p->d_partial, p->nblk, grho, p->stream));
-    else
-        PS_HIP(launch_grad_rho<float>((const float *)lam, (const float *)x, p->nx, p->ny, p->nz,
-                                      p->d_gk, p->d_partial, p->nblk, grho, p->stream));
+    PS_HIP(timed(p, K_GRAD, [&] {
+        if (p->fp64())
+            return launch_grad_rho<double>((const double *)lam, (const double *)x, p->nx, p->ny,
+                                           p->nz, p->d_gk, p->d_partial, p->nblk, grho, p->stream);
+        return launch_grad_rho<float>((const float *)lam, (const float *)x, p->nx, p->ny, p->nz,
+                                      p->d_gk, p->d_partial, p->nblk, grho, p->stream);
+    }));
     return PS_OK;
 }
 

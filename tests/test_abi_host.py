@@ -78,6 +78,8 @@ def test_null_arguments(lib):
     assert lib.ps_inverse_transform(None, None, None) == 1
     assert lib.ps_plan_destroy(None) == 0
     assert lib.ps_workspace_bytes(None) == 0
+    assert lib.ps_plan_profile(None, 1) == 1
+    assert lib.ps_plan_profile_report(None, 0, None, None, None) == 1
 
 
 def test_status_strings(lib):

@@ -43,7 +43,9 @@ def run(g, rhs, precision, adjoint=False, tau=0.0):
 
 def stretched(nx, ny, nz, seed):
     r = np.random.default_rng(seed)
-    g = wl.stretched_grid(nx, ny, nz)
+    # 1.03**k stretching over more than 128 levels gives a ~40 km top level
+    # and densities near 1e-130: keep tall columns physical.
+    g = wl.stretched_grid(nx, ny, nz, stretch=1.03 if nz <= 128 else 1.01)
     g.dz = g.dz * r.uniform(0.7, 1.3, nz)
     g.rho = g.rho * r.uniform(0.8, 1.2, nz)
     g.dy = 37.0
