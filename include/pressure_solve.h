@@ -140,14 +140,20 @@ typedef struct ps_plan_info {
     int fft_variant_x;    /* transform kernels chosen by planning / autotuning */
     int fft_variant_y;
     size_t spectrum_elems;/* complex elements of the spectral layout, nz*(nx/2)*ny */
+    int column_variant;   /* column-solve kernel chosen by planning / autotuning */
 } ps_plan_info;
 
 int ps_plan_query(const ps_plan *plan, ps_plan_info *info);
 
-/* Time the implemented transform variants for this plan's sizes on its
- * stream (reps timed runs each) and keep the fastest; results are cached per
- * device architecture, length and precision for the life of the process and
- * can be saved/loaded as text.  Synchronises. */
+/* Time the implemented kernel variants (x transform, y transform, column
+ * solve) for this plan on its stream, reps timed solves per candidate, by
+ * coordinate descent, and keep the fastest.  Uses two temporary device fields
+ * of the plan's size.  Choices are cached per (device architecture, nx, ny,
+ * nz, precision) for the life of the process -- a later autotune of an equal
+ * plan just applies them -- and can be saved to / loaded from a text file
+ * (one line per entry: arch nx ny nz precision x_variant y_variant
+ * column_variant [fp64_beside], the last 1 when the FP64 columns run on a
+ * second stream beside the main column kernel).  Synchronises. */
 int ps_plan_autotune(ps_plan *plan, int reps);
 int ps_tune_cache_save(const char *path);
 int ps_tune_cache_load(const char *path);

@@ -33,7 +33,8 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("precision", ctypes.c_int), ("fp64_columns", ctypes.c_int),
                 ("tau", ctypes.c_double), ("fft_variant_x", ctypes.c_int),
-                ("fft_variant_y", ctypes.c_int), ("spectrum_elems", ctypes.c_size_t)]
+                ("fft_variant_y", ctypes.c_int), ("spectrum_elems", ctypes.c_size_t),
+                ("column_variant", ctypes.c_int)]
 
 
 # name -> (restype, argtypes); mirrors include/pressure_solve.h
@@ -200,8 +201,11 @@ class Plan:
         return int(load().ps_workspace_bytes(self._h))
 
     def autotune(self, reps: int = 5):
+        """Time the kernel variants for this plan and keep the fastest (or
+        apply an earlier choice for an equal plan from the tune cache)."""
         self._sync_stream()
         check(load().ps_plan_autotune(self._h, int(reps)), "ps_plan_autotune")
+
 
     def profile(self, enable: bool):
         """Start (clearing totals) or stop per-kernel event timing."""
@@ -308,3 +312,11 @@ def poisson_solve(b, rho, plan: Plan):
     if _poisson is None:
         _poisson = _solve_fn()
     return _poisson.apply(b, rho, plan)
+
+
+def tune_cache_save(path: str):
+    check(load().ps_tune_cache_save(os.fsencode(path)), "ps_tune_cache_save")
+
+
+def tune_cache_load(path: str):
+    check(load().ps_tune_cache_load(os.fsencode(path)), "ps_tune_cache_load")

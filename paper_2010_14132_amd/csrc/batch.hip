@@ -1,23 +1,7 @@
-// Batched solves and transform autotuning (placeholders until implemented).
+// Batched solves (placeholders until implemented).
 #include "ps_internal.h"
 #include "../../include/pressure_solve.h"
 
-extern "C" int ps_plan_autotune(ps_plan *plan, int reps)
-{
-    (void)plan;
-    (void)reps;
-    return PS_EUNSUPPORTED;
-}
-extern "C" int ps_tune_cache_save(const char *path)
-{
-    (void)path;
-    return PS_EUNSUPPORTED;
-}
-extern "C" int ps_tune_cache_load(const char *path)
-{
-    (void)path;
-    return PS_EUNSUPPORTED;
-}
 extern "C" int ps_batch_create(ps_batch **out, int count, const int *nx, const int *ny,
                                const int *nz, const double *dx, const double *dy,
                                const double *const *dz, const double *const *rho, int precision,

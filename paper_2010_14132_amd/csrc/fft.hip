@@ -167,11 +167,14 @@ __global__ __launch_bounds__(256) void k_fwd_x_residual(
 }
 
 // ---------------------------------------------------------------- y pass
-// In-place complex transform of contiguous rows of length ny.
+// In-place complex transform of contiguous rows of length ny.  The rows
+// transformed are (level, kx) for kx in [kxlo, kxlo + kxcnt) of a spectrum
+// with L rows per level: row r maps to (r / kxcnt) L + kxlo + r % kxcnt.
 template <typename T, int DIR>
 __global__ __launch_bounds__(256) void k_fft_y(cx_t<T> *__restrict__ spec, int nrows_total, int ny,
                                                int rows, StagePlan sp,
-                                               const cx_t<T> *__restrict__ twy)
+                                               const cx_t<T> *__restrict__ twy, int L, int kxlo,
+                                               int kxcnt)
 {
     using C = cx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -181,11 +184,18 @@ __global__ __launch_bounds__(256) void k_fft_y(cx_t<T> *__restrict__ spec, int n
     const int row0 = blockIdx.x * rows;
     const int nr = min(rows, nrows_total - row0);
     for (int t = threadIdx.x; t < ny; t += blockDim.x) stw[t] = twy[t];
-    C *base = spec + (size_t)row0 * ny;
-    for (int t = threadIdx.x; t < nr * ny; t += blockDim.x) a[t] = base[t];
+    for (int t = threadIdx.x; t < nr * ny; t += blockDim.x) {
+        const int rr = row0 + t / ny, e = t - (t / ny) * ny;
+        const long row = (long)(rr / kxcnt) * L + kxlo + rr % kxcnt;
+        a[t] = spec[row * ny + e];
+    }
     __syncthreads();
     C *Z = stockham_rows<DIR>(a, b, nr, ny, sp, stw);
-    for (int t = threadIdx.x; t < nr * ny; t += blockDim.x) base[t] = Z[t];
+    for (int t = threadIdx.x; t < nr * ny; t += blockDim.x) {
+        const int rr = row0 + t / ny, e = t - (t / ny) * ny;
+        const long row = (long)(rr / kxcnt) * L + kxlo + rr % kxcnt;
+        spec[row * ny + e] = Z[t];
+    }
 }
 
 // ---------------------------------------------------------------- x backward
@@ -275,17 +285,20 @@ hipError_t launch_fwd_x_residual(const T *b, const T *p, cx_t<T> *spec, double *
 }
 
 template <typename T>
-hipError_t launch_fft_y(cx_t<T> *spec, int nrows, int ny, int dir, const FftGeom &g,
-                        const StagePlan &spy, const Tables<T> &tb, hipStream_t st)
+hipError_t launch_fft_y(cx_t<T> *spec, int nz, int L, int kxlo, int kxcnt, int ny, int dir,
+                        const FftGeom &g, const StagePlan &spy, const Tables<T> &tb,
+                        hipStream_t st)
 {
+    const int nrows = nz * kxcnt;
+    if (nrows <= 0) return hipSuccess;
     const int grid = (nrows + g.rows_y - 1) / g.rows_y;
     const size_t lds = lds_y(g.rows_y, ny, sizeof(cx_t<T>));
     if (dir < 0)
         hipLaunchKernelGGL((k_fft_y<T, -1>), dim3(grid), dim3(256), lds, st, spec, nrows, ny,
-                           g.rows_y, spy, tb.tw_y);
+                           g.rows_y, spy, tb.tw_y, L, kxlo, kxcnt);
     else
         hipLaunchKernelGGL((k_fft_y<T, 1>), dim3(grid), dim3(256), lds, st, spec, nrows, ny,
-                           g.rows_y, spy, tb.tw_y);
+                           g.rows_y, spy, tb.tw_y, L, kxlo, kxcnt);
     return hipGetLastError();
 }
 
@@ -310,8 +323,9 @@ hipError_t launch_inv_x(const cx_t<T> *spec, T *out, int nx, int ny, int nz, int
                                                  const double *, int, const FftGeom &,           \
                                                  const StagePlan &, const Tables<T> &,           \
                                                  hipStream_t);                                    \
-    template hipError_t launch_fft_y<T>(cx_t<T> *, int, int, int, const FftGeom &,                \
-                                        const StagePlan &, const Tables<T> &, hipStream_t);       \
+    template hipError_t launch_fft_y<T>(cx_t<T> *, int, int, int, int, int, int,                 \
+                                        const FftGeom &, const StagePlan &, const Tables<T> &,    \
+                                        hipStream_t);                                             \
     template hipError_t launch_inv_x<T>(const cx_t<T> *, T *, int, int, int, int, const FftGeom &, \
                                         const StagePlan &, const Tables<T> &, hipStream_t);
 PS_INST(float)

@@ -1,0 +1,402 @@
+// Register-resident transform kernels for power-of-two lengths L = R1 R2
+// (R1 divides R2): same layouts and results as the Stockham kernels in
+// fft.hip, with each row held by R1 lanes in registers (four_step), global
+// loads and stores straight to and from registers, and LDS used only for the
+// one transposition inside the row transform and, in the x passes, for the
+// [row][kx] <-> [kx][row] transposition of the spectral layout.
+#include "ps_internal.h"
+#include "../../include/pressure_solve.h"
+
+namespace ps {
+
+// ---------------------------------------------------------------- y pass
+// In place over contiguous rows of length L (= ny); NT threads = NT / R1
+// rows.  Row r of the launch is spectrum row (r / kxcnt) nkx + kxlo +
+// r % kxcnt (nkx rows per level).
+template <typename T, int R1, int R2, int DIR, int NT>
+__global__ __launch_bounds__(NT) void k_fft_y_fast(cx_t<T> *__restrict__ spec, int nrows,
+                                                   const cx_t<T> *__restrict__ tw4, int nkx,
+                                                   int kxlo, int kxcnt)
+{
+    using C = cx_t<T>;
+    constexpr int L = R1 * R2, RB = NT / R1;
+    __shared__ T lds[RB * R2 * (R1 + 1)];
+    const int r = threadIdx.x / R1, t = threadIdx.x - r * R1;
+    const long rr = (long)blockIdx.x * RB + r;
+    const bool ok = rr < nrows;
+    const long row = ok ? (rr / kxcnt) * nkx + kxlo + rr % kxcnt : 0;
+    C *base = spec + row * (long)L;
+    C v[R2], w[R2];
+#pragma unroll
+    for (int q = 0; q < R2; ++q) v[q] = ok ? base[t + R1 * q] : C{T(0), T(0)};
+    four_step<R1, R2, DIR>(v, w, t, lds + r * R2 * (R1 + 1), tw4);
+    if (ok) {
+#pragma unroll
+        for (int j = 0; j < R2 / R1; ++j)
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) base[(t + R1 * j) + R2 * k1] = w[j * R1 + k1];
+    }
+}
+
+// ---------------------------------------------------------------- x forward
+// ROWS rows per block, R1 lanes per row.  Loads z_n = x_{2n} + i x_{2n+1},
+// records FP64 row sums, transforms, applies the even/odd split with one
+// shuffle per value (the partner of slot (t, j, k1), index L - k, sits in lane
+// R1 - t of the same row, or in lane 0's own registers for t = 0), and stores
+// the block's rows transposed through LDS (one real component at a time).
+// RES: the transformed row is the residual r = b - A p (b = in) formed with
+// FP64 arithmetic from the stored b and p, rounded once to T.  The vertical
+// term of row k is a_up p_{k+1} + a_dn p_{k-1} - a_c p_k with per-level
+// coefficients rc[3k..3k+2] (forward: f_{k+1/2}/D_k, f_{k-1/2}/D_k,
+// (f_{k+1/2}+f_{k-1/2})/D_k; adjoint, A^T = D A D^{-1}: f_{k+1/2}/D_{k+1},
+// f_{k-1/2}/D_{k-1}, (f_{k+1/2}+f_{k-1/2})/D_k); zero at the ends.  The x
+// neighbours x_{2n-1} and x_{2n+2} of the pair z_n = (x_{2n}, x_{2n+1}) come
+// from the neighbouring lanes of the row.
+template <typename T, int R1, int R2, int ROWS, bool RES>
+__global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
+                                                      cx_t<T> *__restrict__ spec,
+                                                      double *__restrict__ rowsum, int ny,
+                                                      int nrows, const cx_t<T> *__restrict__ tw4,
+                                                      const cx_t<T> *__restrict__ tws,
+                                                      const T *__restrict__ pres, int nz,
+                                                      double idx2, double idy2,
+                                                      const double *__restrict__ rc)
+{
+    using C = cx_t<T>;
+    constexpr int L = R1 * R2, NT = ROWS * R1, J = R2 / R1;
+    constexpr int A = ROWS * R2 * (R1 + 1), B = L * (ROWS + 1);
+    __shared__ T lds[A > B ? A : B];
+    const int r = threadIdx.x / R1, t = threadIdx.x - r * R1;
+    const long g = (long)blockIdx.x * ROWS + r;
+    const bool ok = g < nrows;
+    const C *src = reinterpret_cast<const C *>(in) + (ok ? g : 0) * (long)L;
+    C v[R2], w[R2];
+    double s = 0.0;
+    if constexpr (RES) {
+        const long gg = ok ? g : 0;
+        const int lev = (int)(gg / ny), j = (int)(gg - (long)lev * ny);
+        const double au = rc[3 * lev], ad = rc[3 * lev + 1], ac = rc[3 * lev + 2];
+        const C *P = reinterpret_cast<const C *>(pres);
+        const C *pc_row = P + gg * L;
+        const C *pn_row = P + ((long)lev * ny + (j + 1 == ny ? 0 : j + 1)) * L;
+        const C *ps_row = P + ((long)lev * ny + (j == 0 ? ny - 1 : j - 1)) * L;
+        const bool has_up = lev + 1 < nz, has_dn = lev > 0;
+        const C *pu_row = pc_row + (has_up ? (long)ny * L : 0);
+        const C *pd_row = pc_row - (has_dn ? (long)ny * L : 0);
+        C pc[R2];
+#pragma unroll
+        for (int q = 0; q < R2; ++q) pc[q] = pc_row[t + R1 * q];
+        const int lane = threadIdx.x & 63, base = lane - t;
+        const int left = base + (t == 0 ? R1 - 1 : t - 1);
+        const int right = base + (t == R1 - 1 ? 0 : t + 1);
+#pragma unroll
+        for (int q = 0; q < R2; ++q) {
+            const int n = t + R1 * q;
+            // x_{2n-1}: lane t-1 slot q, or for t = 0 lane R1-1 slot q-1 (mod R2)
+            const T wl_a = __shfl(pc[q].y, left, 64);
+            const T wl_b = __shfl(pc[(q + R2 - 1) % R2].y, left, 64);
+            const T xw = t == 0 ? wl_b : wl_a;
+            // x_{2n+2}: lane t+1 slot q, or for t = R1-1 lane 0 slot q+1 (mod R2)
+            const T er_a = __shfl(pc[q].x, right, 64);
+            const T er_b = __shfl(pc[(q + 1) % R2].x, right, 64);
+            const T xe = t == R1 - 1 ? er_b : er_a;
+            const C bv = src[n], pn = pn_row[n], psd = ps_row[n];
+            const C pu = has_up ? pu_row[n] : C{T(0), T(0)};
+            const C pd = has_dn ? pd_row[n] : C{T(0), T(0)};
+            const double c0 = pc[q].x, c1 = pc[q].y;
+            const double lap0 = ((double)c1 - 2.0 * c0 + (double)xw) * idx2 +
+                                ((double)pn.x - 2.0 * c0 + (double)psd.x) * idy2 +
+                                au * (double)pu.x + ad * (double)pd.x - ac * c0;
+            const double lap1 = ((double)xe - 2.0 * c1 + c0) * idx2 +
+                                ((double)pn.y - 2.0 * c1 + (double)psd.y) * idy2 +
+                                au * (double)pu.y + ad * (double)pd.y - ac * c1;
+            v[q] = ok ? C{(T)((double)bv.x - lap0), (T)((double)bv.y - lap1)} : C{T(0), T(0)};
+            (void)n;
+            s += (double)v[q].x + (double)v[q].y;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < R2; ++q) {
+            v[q] = ok ? src[t + R1 * q] : C{T(0), T(0)};
+            s += (double)v[q].x + (double)v[q].y;
+        }
+    }
+#pragma unroll
+    for (int o = R1 / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (ok && t == 0) rowsum[g] = s;
+
+    four_step<R1, R2, -1>(v, w, t, lds + r * R2 * (R1 + 1), tw4);
+
+    // split: X_k = (Z_k + Zc)/2 + W_nx^k (Z_k - Zc)/(2i), Zc = conj Z_{L-k}
+    const int lane = threadIdx.x & 63;
+    const int src_lane = lane - t + ((R1 - t) & (R1 - 1));
+    C X[R2];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            const int other = (J - 1 - j) * R1 + (R1 - 1 - k1);
+            const int own = j == 0 ? ((R1 - k1) & (R1 - 1)) : (J - j) * R1 + (R1 - 1 - k1);
+            C zp;
+            zp.x = __shfl(w[other].x, src_lane, 64);
+            zp.y = __shfl(w[other].y, src_lane, 64);
+            if (t == 0) zp = w[own];
+            const C zk = w[j * R1 + k1];
+            const int k = (t + R1 * j) + R2 * k1;
+            const C zc = cconj(zp);
+            if (k == 0) {
+                X[j * R1 + k1] = C{zk.x + zk.y, zk.x - zk.y};
+            } else {
+                const C e = C{T(0.5) * (zk.x + zc.x), T(0.5) * (zk.y + zc.y)};
+                const C d = csub(zk, zc);
+                const C o = C{T(0.5) * d.y, T(-0.5) * d.x};
+                X[j * R1 + k1] = cadd(e, cmul(o, tws[k]));
+            }
+        }
+    }
+
+    // transposed store: [row][kx] -> spec[level][kx][j]
+    constexpr int P = ROWS + 1;
+    T outr[R2], outi[R2];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) lds[((t + R1 * j) + R2 * k1) * P + r] = X[j * R1 + k1].x;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < R2; ++i) {
+        const int e = threadIdx.x + NT * i;
+        outr[i] = lds[(e / ROWS) * P + (e % ROWS)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) lds[((t + R1 * j) + R2 * k1) * P + r] = X[j * R1 + k1].y;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < R2; ++i) {
+        const int e = threadIdx.x + NT * i;
+        outi[i] = lds[(e / ROWS) * P + (e % ROWS)];
+    }
+#pragma unroll
+    for (int i = 0; i < R2; ++i) {
+        const int e = threadIdx.x + NT * i;
+        const int kx = e / ROWS, rr = e % ROWS;
+        const long g2 = (long)blockIdx.x * ROWS + rr;
+        if (g2 < nrows) {
+            const long lev = g2 / ny, jj = g2 - lev * ny;
+            spec[(lev * L + kx) * (long)ny + jj] = C{outr[i], outi[i]};
+        }
+    }
+}
+
+// ---------------------------------------------------------------- x backward
+// Gathers ROWS rows of the transposed spectrum through LDS, undoes the
+// packing, Z_k = (X_k + conj X_{L-k}) + i W_nx^{-k} (X_k - conj X_{L-k}),
+// transforms backwards and stores real rows (optionally accumulated).
+template <typename T, int R1, int R2, int ROWS>
+__global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict__ spec,
+                                                      T *__restrict__ out, int ny, int nrows,
+                                                      int accumulate,
+                                                      const cx_t<T> *__restrict__ tw4,
+                                                      const cx_t<T> *__restrict__ tws)
+{
+    using C = cx_t<T>;
+    constexpr int L = R1 * R2, NT = ROWS * R1, J = R2 / R1;
+    constexpr int A = ROWS * R2 * (R1 + 1), B = L * (ROWS + 1);
+    constexpr int P = ROWS + 1;
+    __shared__ T lds[A > B ? A : B];
+    const int r = threadIdx.x / R1, t = threadIdx.x - r * R1;
+    const long g = (long)blockIdx.x * ROWS + r;
+    const bool ok = g < nrows;
+
+    T inr[R2], ini[R2];
+#pragma unroll
+    for (int i = 0; i < R2; ++i) {
+        const int e = threadIdx.x + NT * i;
+        const int kx = e / ROWS, rr = e % ROWS;
+        const long g2 = (long)blockIdx.x * ROWS + rr;
+        C x = C{T(0), T(0)};
+        if (g2 < nrows) {
+            const long lev = g2 / ny, jj = g2 - lev * ny;
+            x = spec[(lev * L + kx) * (long)ny + jj];
+        }
+        inr[i] = x.x;
+        ini[i] = x.y;
+    }
+    C xa[R2], xb[R2];
+#pragma unroll
+    for (int i = 0; i < R2; ++i) {
+        const int e = threadIdx.x + NT * i;
+        lds[(e / ROWS) * P + (e % ROWS)] = inr[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < R2; ++q) {
+        const int k = t + R1 * q;
+        xa[q].x = lds[k * P + r];
+        xb[q].x = lds[((L - k) & (L - 1)) * P + r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < R2; ++i) {
+        const int e = threadIdx.x + NT * i;
+        lds[(e / ROWS) * P + (e % ROWS)] = ini[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < R2; ++q) {
+        const int k = t + R1 * q;
+        xa[q].y = lds[k * P + r];
+        xb[q].y = lds[((L - k) & (L - 1)) * P + r];
+    }
+    C v[R2], w[R2];
+#pragma unroll
+    for (int q = 0; q < R2; ++q) {
+        const int k = t + R1 * q;
+        if (k == 0) {
+            const T x0 = xa[q].x, xl = xa[q].y;
+            v[q] = C{x0 + xl, x0 - xl};
+        } else {
+            const C xc = cconj(xb[q]);
+            const C sm = cadd(xa[q], xc);
+            const C dw = cmul(csub(xa[q], xc), cconj(tws[k]));
+            v[q] = C{sm.x - dw.y, sm.y + dw.x};
+        }
+    }
+    __syncthreads();
+    four_step<R1, R2, 1>(v, w, t, lds + r * R2 * (R1 + 1), tw4);
+    if (ok) {
+        C *dst = reinterpret_cast<C *>(out) + g * (long)L;
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) {
+                const int n = (t + R1 * j) + R2 * k1;
+                C val = w[j * R1 + k1];
+                if (accumulate) val = cadd(val, dst[n]);
+                dst[n] = val;
+            }
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+// Rows per block of the x passes: 128-byte runs of the transposed layout
+// (16 FP32 or 8 FP64 complex values), halved until the LDS buffer fits 64 KiB.
+template <typename T, int R1, int R2> constexpr int x_rows()
+{
+    int rows = sizeof(T) == 8 ? 8 : 16;
+    while (rows > 1) {
+        const int a = rows * R2 * (R1 + 1), b = R1 * R2 * (rows + 1);
+        if ((a > b ? a : b) * (int)sizeof(T) <= 65536) break;
+        rows /= 2;
+    }
+    return rows;
+}
+
+// Returns hipErrorNotSupported when L has no register-resident kernel.
+template <typename T, int R1, int R2>
+static hipError_t y_fast(cx_t<T> *spec, int nrows, int dir, const cx_t<T> *tw4, int nkx, int kxlo,
+                         int kxcnt, hipStream_t st)
+{
+    constexpr int NT = sizeof(T) == 8 && R1 * R2 >= 512 ? 128 : 256;
+    constexpr int RB = NT / R1;
+    if (nrows <= 0) return hipSuccess;
+    const int grid = (nrows + RB - 1) / RB;
+    if (dir < 0)
+        hipLaunchKernelGGL((k_fft_y_fast<T, R1, R2, -1, NT>), dim3(grid), dim3(NT), 0, st, spec,
+                           nrows, tw4, nkx, kxlo, kxcnt);
+    else
+        hipLaunchKernelGGL((k_fft_y_fast<T, R1, R2, 1, NT>), dim3(grid), dim3(NT), 0, st, spec,
+                           nrows, tw4, nkx, kxlo, kxcnt);
+    return hipGetLastError();
+}
+
+bool fast_length(int L) { return L == 16 || L == 32 || L == 64 || L == 128 || L == 256 || L == 512 || L == 1024; }
+int fast_r1(int L) { return L <= 32 ? 4 : L <= 128 ? 8 : L <= 512 ? 16 : 32; }
+
+#define PS_FAST_SWITCH(L, F)                                                                       \
+    switch (L) {                                                                                   \
+    case 16: return F(4, 4);                                                                       \
+    case 32: return F(4, 8);                                                                       \
+    case 64: return F(8, 8);                                                                       \
+    case 128: return F(8, 16);                                                                     \
+    case 256: return F(16, 16);                                                                    \
+    case 512: return F(16, 32);                                                                    \
+    case 1024: return F(32, 32);                                                                   \
+    default: return hipErrorNotSupported;                                                          \
+    }
+
+template <typename T>
+hipError_t launch_fft_y_fast(cx_t<T> *spec, int nz, int nkx, int kxlo, int kxcnt, int ny, int dir,
+                             const cx_t<T> *tw4, hipStream_t st)
+{
+    const int nrows = nz * kxcnt;
+#define PS_Y(a, b) y_fast<T, a, b>(spec, nrows, dir, tw4, nkx, kxlo, kxcnt, st)
+    PS_FAST_SWITCH(ny, PS_Y)
+#undef PS_Y
+}
+
+template <typename T, int R1, int R2>
+static hipError_t r2c_fast(const T *in, cx_t<T> *spec, double *rowsum, int ny, int nz,
+                           const cx_t<T> *tw4, const cx_t<T> *tws, const T *pres, double idx2,
+                           double idy2, const double *rc, hipStream_t st)
+{
+    constexpr int ROWS = x_rows<T, R1, R2>();
+    const int nrows = ny * nz;
+    const int grid = (nrows + ROWS - 1) / ROWS;
+    if (pres)
+        hipLaunchKernelGGL((k_r2c_fast<T, R1, R2, ROWS, true>), dim3(grid), dim3(ROWS * R1), 0, st,
+                           in, spec, rowsum, ny, nrows, tw4, tws, pres, nz, idx2, idy2, rc);
+    else
+        hipLaunchKernelGGL((k_r2c_fast<T, R1, R2, ROWS, false>), dim3(grid), dim3(ROWS * R1), 0,
+                           st, in, spec, rowsum, ny, nrows, tw4, tws, pres, nz, idx2, idy2, rc);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_r2c_fast(const T *in, cx_t<T> *spec, double *rowsum, int nx, int ny, int nz,
+                           const cx_t<T> *tw4, const cx_t<T> *tws, hipStream_t st,
+                           const T *pres, double idx2, double idy2, const double *rc)
+{
+#define PS_X(a, b) r2c_fast<T, a, b>(in, spec, rowsum, ny, nz, tw4, tws, pres, idx2, idy2, rc, st)
+    PS_FAST_SWITCH(nx / 2, PS_X)
+#undef PS_X
+}
+
+template <typename T, int R1, int R2>
+static hipError_t c2r_fast(const cx_t<T> *spec, T *out, int ny, int nrows, int accumulate,
+                           const cx_t<T> *tw4, const cx_t<T> *tws, hipStream_t st)
+{
+    constexpr int ROWS = x_rows<T, R1, R2>();
+    const int grid = (nrows + ROWS - 1) / ROWS;
+    hipLaunchKernelGGL((k_c2r_fast<T, R1, R2, ROWS>), dim3(grid), dim3(ROWS * R1), 0, st, spec, out,
+                       ny, nrows, accumulate, tw4, tws);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_c2r_fast(const cx_t<T> *spec, T *out, int nx, int ny, int nz, int accumulate,
+                           const cx_t<T> *tw4, const cx_t<T> *tws, hipStream_t st)
+{
+    const int nrows = ny * nz;
+#define PS_X(a, b) c2r_fast<T, a, b>(spec, out, ny, nrows, accumulate, tw4, tws, st)
+    PS_FAST_SWITCH(nx / 2, PS_X)
+#undef PS_X
+}
+
+#define PS_INST(T)                                                                                 \
+    template hipError_t launch_fft_y_fast<T>(cx_t<T> *, int, int, int, int, int, int,            \
+                                             const cx_t<T> *, hipStream_t);                       \
+    template hipError_t launch_r2c_fast<T>(const T *, cx_t<T> *, double *, int, int, int,        \
+                                           const cx_t<T> *, const cx_t<T> *, hipStream_t,         \
+                                           const T *, double, double, const double *);            \
+    template hipError_t launch_c2r_fast<T>(const cx_t<T> *, T *, int, int, int, int,             \
+                                           const cx_t<T> *, const cx_t<T> *, hipStream_t);
+PS_INST(float)
+PS_INST(double)
+#undef PS_INST
+
+} // namespace ps

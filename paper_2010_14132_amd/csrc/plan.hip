@@ -5,6 +5,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -29,6 +33,14 @@ static int fail(int code, const std::string &msg)
     } while (0)
 
 namespace ps {
+
+// Register capacity (levels per half column) of the column kernels for nz.
+int column_capacity(int nz)
+{
+    int nh = 1;
+    while (nh < nz / 2) nh *= 2;
+    return nh;
+}
 
 bool is_2a3b(int n)
 {
@@ -110,6 +122,8 @@ struct ps_plan {
     double dx = 0, dy = 0, tau = 0;
     std::vector<double> dz, rho;
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;        // the FP64 column kernel runs here, beside the main one
+    hipEvent_t fork = nullptr, join = nullptr;
     int device = 0;
     std::vector<double> ax, ay, f, D;
     StagePlan spx{}, spy{};
@@ -119,12 +133,14 @@ struct ps_plan {
     int *d_maskcnt = nullptr;
     int *d_mlist = nullptr;
     int nmask = 0;
+    int kmask = 1; // rows kx < kmask hold every column solved in FP64
     void *d_spec = nullptr;
     double *d_rowsum = nullptr;
     double *d_S = nullptr;
     double *d_ws = nullptr;
     double *d_gk = nullptr;
     double *d_partial = nullptr;
+    double *d_rc = nullptr; // residual vertical coefficients [fwd: 3 nz][adj: 3 nz]
     int nblk = 0;
     size_t bytes = 0;
     std::vector<void *> allocs;
@@ -225,6 +241,15 @@ template <typename T> static int alloc_tables(ps_plan *p, Tables<T> &t)
     PS_TRY(dev_alloc(p, &t.tw_x, p->L));
     PS_TRY(dev_alloc(p, &t.tw_s, p->L));
     PS_TRY(dev_alloc(p, &t.tw_y, p->ny));
+    PS_TRY(dev_alloc(p, &t.tw4_x, p->L));
+    PS_TRY(dev_alloc(p, &t.tw4_y, p->ny));
+    const int nh = column_capacity(p->nz);
+    const size_t entry = sizeof(LevelCoef<T>);
+    char *cf = nullptr, *ca = nullptr;
+    PS_TRY(dev_alloc(p, &cf, entry * (size_t)(2 * nh + 1)));
+    PS_TRY(dev_alloc(p, &ca, entry * (size_t)(2 * nh + 1)));
+    t.coef_fwd = cf;
+    t.coef_adj = ca;
     return PS_OK;
 }
 
@@ -238,6 +263,37 @@ template <typename T> static int upload_coeff_tables(ps_plan *p, Tables<T> &t)
     PS_TRY(upload(t.rs_fwd, rsf));
     PS_TRY(upload(t.rs_adj, rsa));
     PS_TRY(upload(t.os_adj, p->D));
+    // Per-slot coefficients in elimination order for the uniform-half column
+    // kernel: [low slots][high slots][middle]; each half's n real levels sit in
+    // its last n slots, dummies in front.
+    const int nz = p->nz, nh = column_capacity(nz), m = nz / 2;
+    const long long lvl_bytes = (long long)p->L * p->ny * 2 * (long long)sizeof(T);
+    using Coef = LevelCoef<T>;
+    for (int adj = 0; adj < 2; ++adj) {
+        std::vector<Coef> c(2 * (size_t)nh + 1);
+        auto put = [&](int slot, int k, double fp, double fn) {
+            Coef &e = c[slot];
+            e.fp = (T)fp;
+            e.fn = (T)fn;
+            e.D = (T)p->D[k];
+            e.rs = (T)(adj ? -on : rsf[k]);
+            e.os = (T)(adj ? p->D[k] : 1.0);
+            e.pad = 0;
+            e.off = (long long)k * lvl_bytes;
+        };
+        for (int i = 0; i < 2 * nh + 1; ++i) {
+            c[i] = Coef{T(0), T(0), T(1), T(0), T(0), T(0), -1};
+        }
+        const int nlo = m, nhi = nz - 1 - m;
+        for (int i = 0; i < nlo; ++i) put(nh - nlo + i, i, p->f[i], p->f[i + 1]);
+        for (int i = 0; i < nhi; ++i) {
+            const int k = nz - 1 - i;
+            put(2 * nh - nhi + i, k, p->f[k + 1], p->f[k]);
+        }
+        put(2 * nh, m, p->f[m], p->f[m + 1]);
+        void *dst = adj ? t.coef_adj : t.coef_fwd;
+        PS_HIP(hipMemcpy(dst, c.data(), c.size() * sizeof(Coef), hipMemcpyHostToDevice));
+    }
     return PS_OK;
 }
 
@@ -260,7 +316,42 @@ template <typename T> static int upload_tables(ps_plan *p, Tables<T> &t)
     PS_TRY(roots(t.tw_x, p->L, p->L));
     PS_TRY(roots(t.tw_s, p->L, p->nx));
     PS_TRY(roots(t.tw_y, p->ny, p->ny));
+    // four-step twiddles W_n^{t k2} at [k2 R1 + t] for the register kernels
+    auto four = [&](C *dst, int n) -> int {
+        if (!fast_length(n)) return PS_OK;
+        const int r1 = fast_r1(n), r2 = n / r1;
+        std::vector<C> h(n);
+        for (int k2 = 0; k2 < r2; ++k2)
+            for (int t = 0; t < r1; ++t) {
+                double c, s;
+                root(t * k2, n, c, s);
+                h[k2 * r1 + t] = C{(T)c, (T)s};
+            }
+        PS_HIP(hipMemcpy(dst, h.data(), h.size() * sizeof(C), hipMemcpyHostToDevice));
+        return PS_OK;
+    };
+    PS_TRY(four(t.tw4_x, p->L));
+    PS_TRY(four(t.tw4_y, p->ny));
     return PS_OK;
+}
+
+// Vertical coefficients of the residual kernel: row k's vertical term is
+// a_up p_{k+1} + a_dn p_{k-1} - a_c p_k; forward A, then adjoint A^T.
+static int upload_residual_table(ps_plan *p)
+{
+    const int nz = p->nz;
+    std::vector<double> rc(6 * (size_t)nz, 0.0);
+    for (int k = 0; k < nz; ++k) {
+        const double fu = p->f[k + 1], fd = p->f[k], Dk = p->D[k];
+        rc[3 * k] = fu / Dk;
+        rc[3 * k + 1] = fd / Dk;
+        rc[3 * k + 2] = (fu + fd) / Dk;
+        double *a = &rc[3 * (size_t)nz + 3 * k];
+        a[0] = k + 1 < nz ? fu / p->D[k + 1] : 0.0;
+        a[1] = k > 0 ? fd / p->D[k - 1] : 0.0;
+        a[2] = (fu + fd) / Dk;
+    }
+    return upload(p->d_rc, rc);
 }
 
 static int upload_grad_table(ps_plan *p)
@@ -288,6 +379,9 @@ static void choose_geometry(ps_plan *p)
     ry = std::max(1, std::min(64, ry));
     p->geom.rows_x = std::min(rx, p->ny * p->nz);
     p->geom.rows_y = std::min(ry, p->nz * p->L);
+    // register-resident kernels where the length has one (variant 1)
+    p->geom.variant_x = fast_length(p->L) ? 1 : 0;
+    p->geom.variant_y = fast_length(p->ny) ? 1 : 0;
 }
 
 // Near-singular columns of the FP32 forms: lateral eigenvalue
@@ -314,6 +408,9 @@ static void free_plan(ps_plan *p)
 {
     for (void *q : p->allocs) (void)hipFree(q);
     p->allocs.clear();
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    if (p->join) (void)hipEventDestroy(p->join);
+    if (p->side) (void)hipStreamDestroy(p->side);
     delete p;
 }
 
@@ -344,6 +441,8 @@ extern "C" int ps_plan_create(ps_plan **out, int nx, int ny, int nz, double dx, 
     std::vector<int> cnt, list;
     choose_mask(p, cnt, list);
     p->nmask = (int)list.size();
+    for (int kx = 1; kx < p->L; ++kx)
+        if (cnt[kx] > 0) p->kmask = kx + 1;
     p->nblk = grad_blocks(nx, ny);
 
     int rc = PS_OK;
@@ -354,6 +453,12 @@ extern "C" int ps_plan_create(ps_plan **out, int nx, int ny, int nz, double dx, 
     if (e != hipSuccess) {
         free_plan(p);
         return fail(PS_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->join, hipEventDisableTiming) != hipSuccess) {
+        free_plan(p);
+        return fail(PS_EHIP, "stream or event creation failed");
     }
     step(alloc_tables(p, p->t64));
     if (!p->fp64()) step(alloc_tables(p, p->t32));
@@ -369,9 +474,10 @@ extern "C" int ps_plan_create(ps_plan **out, int nx, int ny, int nz, double dx, 
     }
     step(dev_alloc(p, &p->d_rowsum, (size_t)ny * nz));
     step(dev_alloc(p, &p->d_S, (size_t)nz));
-    step(dev_alloc(p, &p->d_ws, 5 * (size_t)nz * ntask));
+    step(dev_alloc(p, &p->d_ws, 6 * (size_t)nz * ntask));
     step(dev_alloc(p, &p->d_gk, 4 * (size_t)nz + 2));
     step(dev_alloc(p, &p->d_partial, (size_t)nz * p->nblk));
+    step(dev_alloc(p, &p->d_rc, 6 * (size_t)nz));
     step(dev_alloc(p, &p->d_maskcnt, (size_t)p->L));
     step(dev_alloc(p, &p->d_mlist, list.size()));
     if (rc == PS_OK) step(upload_tables(p, p->t64));
@@ -379,6 +485,7 @@ extern "C" int ps_plan_create(ps_plan **out, int nx, int ny, int nz, double dx, 
     if (rc == PS_OK) step(upload(p->d_maskcnt, cnt));
     if (rc == PS_OK && !list.empty()) step(upload(p->d_mlist, list));
     if (rc == PS_OK) step(upload_grad_table(p));
+    if (rc == PS_OK) step(upload_residual_table(p));
     if (rc != PS_OK) {
         free_plan(p);
         return rc;
@@ -391,6 +498,7 @@ extern "C" int ps_plan_destroy(ps_plan *p)
 {
     if (!p) return PS_OK;
     hipError_t e = hipStreamSynchronize(p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->side);
     free_plan(p);
     if (e != hipSuccess) return fail(PS_EHIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
     return PS_OK;
@@ -414,6 +522,7 @@ extern "C" int ps_plan_set_coeffs(ps_plan *p, const double *rho)
     PS_TRY(upload_coeff_tables(p, p->t64));
     if (!p->fp64()) PS_TRY(upload_coeff_tables(p, p->t32));
     PS_TRY(upload_grad_table(p));
+    PS_TRY(upload_residual_table(p));
     return PS_OK;
 }
 
@@ -431,19 +540,22 @@ extern "C" int ps_plan_query(const ps_plan *p, ps_plan_info *info)
     info->fft_variant_x = p->geom.variant_x;
     info->fft_variant_y = p->geom.variant_y;
     info->spectrum_elems = p->spec_elems();
+    info->column_variant = p->precision == PS_FP32_R2 ? 0 : p->geom.columns;
     return PS_OK;
 }
 
 // ------------------------------------------------------------------ timing
 // Brackets one enqueue with profiling events when profiling is on.
-template <typename F> static hipError_t timed(ps_plan *p, int id, F &&launch)
+template <typename F> static hipError_t timed(ps_plan *p, int id, F &&launch,
+                                              hipStream_t st = nullptr)
 {
     if (!p->prof.on) return launch();
+    if (!st) st = p->stream;
     hipEvent_t a = p->prof.get(), b = p->prof.get();
     if (!a || !b) return hipErrorOutOfMemory;
-    hipError_t e = hipEventRecord(a, p->stream);
+    hipError_t e = hipEventRecord(a, st);
     if (e == hipSuccess) e = launch();
-    if (e == hipSuccess) e = hipEventRecord(b, p->stream);
+    if (e == hipSuccess) e = hipEventRecord(b, st);
     p->prof.recs.push_back({id, a, b});
     return e;
 }
@@ -451,6 +563,7 @@ template <typename F> static hipError_t timed(ps_plan *p, int id, F &&launch)
 static int collect_profile(ps_plan *p)
 {
     PS_HIP(hipStreamSynchronize(p->stream));
+    PS_HIP(hipStreamSynchronize(p->side));
     for (auto &r : p->prof.recs) {
         float ms = 0.f;
         PS_HIP(hipEventElapsedTime(&ms, r.a, r.b));
@@ -493,24 +606,52 @@ template <typename T> static Tables<T> &tables(ps_plan *p);
 template <> Tables<float> &tables<float>(ps_plan *p) { return p->t32; }
 template <> Tables<double> &tables<double>(ps_plan *p) { return p->t64; }
 
-template <typename T> static int fwd(ps_plan *p, const T *rhs, cx_t<T> *spec)
+template <typename T>
+static hipError_t y_pass(ps_plan *p, cx_t<T> *spec, int dir, int kxlo = 0, int kxcnt = -1)
 {
+    const Tables<T> &tb = tables<T>(p);
+    if (kxcnt < 0) kxcnt = p->L - kxlo;
+    if (kxcnt <= 0) return hipSuccess;
+    return timed(p, dir < 0 ? K_FFT_Y_FWD : K_FFT_Y_INV, [&] {
+        if (p->geom.variant_y == 1)
+            return launch_fft_y_fast<T>(spec, p->nz, p->L, kxlo, kxcnt, p->ny, dir, tb.tw4_y,
+                                        p->stream);
+        return launch_fft_y<T>(spec, p->nz, p->L, kxlo, kxcnt, p->ny, dir, p->geom, p->spy, tb,
+                               p->stream);
+    });
+}
+
+// Forward x transform and level sums (no y pass).
+template <typename T> static int fwd_x(ps_plan *p, const T *rhs, cx_t<T> *spec)
+{
+    const Tables<T> &tb = tables<T>(p);
     PS_HIP(timed(p, K_FWD_X, [&] {
-        return launch_fwd_x<T>(rhs, spec, p->d_rowsum, p->nx, p->ny, p->nz, p->geom, p->spx,
-                               tables<T>(p), p->stream);
+        if (p->geom.variant_x == 1)
+            return launch_r2c_fast<T>(rhs, spec, p->d_rowsum, p->nx, p->ny, p->nz, tb.tw4_x,
+                                      tb.tw_s, p->stream);
+        return launch_fwd_x<T>(rhs, spec, p->d_rowsum, p->nx, p->ny, p->nz, p->geom, p->spx, tb,
+                               p->stream);
     }));
     PS_HIP(timed(p, K_LEVEL_SUMS,
                  [&] { return launch_level_sums(p->d_rowsum, p->d_S, p->ny, p->nz, p->stream); }));
-    PS_HIP(timed(p, K_FFT_Y_FWD, [&] {
-        return launch_fft_y<T>(spec, p->nz * p->L, p->ny, -1, p->geom, p->spy, tables<T>(p),
-                               p->stream);
-    }));
     return PS_OK;
 }
 
-template <typename T> static int fwd_residual(ps_plan *p, const T *b, const T *x, cx_t<T> *spec, int adjoint)
+template <typename T> static int fwd(ps_plan *p, const T *rhs, cx_t<T> *spec)
+{
+    PS_TRY(fwd_x<T>(p, rhs, spec));
+    PS_HIP(y_pass<T>(p, spec, -1));
+    return PS_OK;
+}
+
+template <typename T> static int fwd_residual_x(ps_plan *p, const T *b, const T *x, cx_t<T> *spec, int adjoint)
 {
     PS_HIP(timed(p, K_FWD_X_RES, [&] {
+        if (p->geom.variant_x == 1)
+            return launch_r2c_fast<T>(b, spec, p->d_rowsum, p->nx, p->ny, p->nz,
+                                      tables<T>(p).tw4_x, tables<T>(p).tw_s, p->stream, x,
+                                      1.0 / (p->dx * p->dx), 1.0 / (p->dy * p->dy),
+                                      p->d_rc + (adjoint ? 3 * (size_t)p->nz : 0));
         return launch_fwd_x_residual<T>(b, x, spec, p->d_rowsum, p->nx, p->ny, p->nz,
                                         1.0 / (p->dx * p->dx), 1.0 / (p->dy * p->dy), p->t64.f,
                                         p->t64.D, adjoint, p->geom, p->spx, tables<T>(p),
@@ -518,36 +659,80 @@ template <typename T> static int fwd_residual(ps_plan *p, const T *b, const T *x
     }));
     PS_HIP(timed(p, K_LEVEL_SUMS,
                  [&] { return launch_level_sums(p->d_rowsum, p->d_S, p->ny, p->nz, p->stream); }));
-    PS_HIP(timed(p, K_FFT_Y_FWD, [&] {
-        return launch_fft_y<T>(spec, p->nz * p->L, p->ny, -1, p->geom, p->spy, tables<T>(p),
-                               p->stream);
-    }));
     return PS_OK;
 }
 
-template <typename T> static int columns(ps_plan *p, cx_t<T> *spec, int adjoint, int refine)
+// The FP64 columns (packed kx = 0 row, mean column, near-singular columns)
+// and the main column kernel touch disjoint columns.  When the forward y
+// pass is part of the call (ypass != 0) and the FP64 kernel runs beside the
+// main one, the y pass first transforms only the rows kx < kmask (which hold
+// every FP64 column), the FP64 kernel is forked onto the plan's side stream,
+// and the remaining y pass and the main column kernel run meanwhile; the
+// streams join before the backward transform.
+template <typename T>
+static int columns(ps_plan *p, cx_t<T> *spec, int adjoint, int refine, int ypass = 0)
 {
     const int *mc = p->fp64() ? nullptr : p->d_maskcnt;
+    if (ypass && p->geom.special_side) {
+        PS_HIP(y_pass<T>(p, spec, -1, 0, p->kmask));
+        PS_HIP(hipEventRecord(p->fork, p->stream));
+        PS_HIP(hipStreamWaitEvent(p->side, p->fork, 0));
+        PS_HIP(timed(
+            p, K_SPECIAL,
+            [&] {
+                return launch_special<T>(spec, p->nx, p->ny, p->nz, adjoint, p->d_mlist, p->nmask,
+                                         p->d_S, p->d_ws, p->t64, p->side, p->geom.special_par);
+            },
+            p->side));
+        PS_HIP(hipEventRecord(p->join, p->side));
+        PS_HIP(y_pass<T>(p, spec, -1, p->kmask));
+        PS_HIP(timed(p, K_COLUMNS, [&] {
+            return launch_columns_impl<T>(spec, p->nx, p->ny, p->nz, adjoint, refine, mc,
+                                          tables<T>(p), &p->t64, p->stream, p->geom.columns);
+        }));
+        PS_HIP(hipStreamWaitEvent(p->stream, p->join, 0));
+        return PS_OK;
+    }
+    if (ypass) PS_HIP(y_pass<T>(p, spec, -1));
+    if (!p->geom.special_side) {
+        PS_HIP(timed(p, K_SPECIAL, [&] {
+            return launch_special<T>(spec, p->nx, p->ny, p->nz, adjoint, p->d_mlist, p->nmask,
+                                     p->d_S, p->d_ws, p->t64, p->stream, p->geom.special_par);
+        }));
+        PS_HIP(timed(p, K_COLUMNS, [&] {
+            return launch_columns_impl<T>(spec, p->nx, p->ny, p->nz, adjoint, refine, mc,
+                                          tables<T>(p), &p->t64, p->stream, p->geom.columns);
+        }));
+        return PS_OK;
+    }
+    PS_HIP(hipEventRecord(p->fork, p->stream));
+    PS_HIP(hipStreamWaitEvent(p->side, p->fork, 0));
+    PS_HIP(timed(
+        p, K_SPECIAL,
+        [&] {
+            return launch_special<T>(spec, p->nx, p->ny, p->nz, adjoint, p->d_mlist, p->nmask,
+                                     p->d_S, p->d_ws, p->t64, p->side, p->geom.special_par);
+        },
+        p->side));
+    PS_HIP(hipEventRecord(p->join, p->side));
     PS_HIP(timed(p, K_COLUMNS, [&] {
         return launch_columns_impl<T>(spec, p->nx, p->ny, p->nz, adjoint, refine, mc,
-                                      tables<T>(p), &p->t64, p->stream);
+                                      tables<T>(p), &p->t64, p->stream, p->geom.columns);
     }));
-    PS_HIP(timed(p, K_SPECIAL, [&] {
-        return launch_special<T>(spec, p->nx, p->ny, p->nz, adjoint, p->d_mlist, p->nmask,
-                                 p->d_S, p->d_ws, p->t64, p->stream);
-    }));
+    PS_HIP(hipStreamWaitEvent(p->stream, p->join, 0));
     return PS_OK;
 }
 
 template <typename T> static int inv(ps_plan *p, cx_t<T> *spec, T *out, int accumulate)
 {
-    PS_HIP(timed(p, K_FFT_Y_INV, [&] {
-        return launch_fft_y<T>(spec, p->nz * p->L, p->ny, 1, p->geom, p->spy, tables<T>(p),
-                               p->stream);
-    }));
+    const Tables<T> &tb = tables<T>(p);
+    PS_HIP(y_pass<T>(p, spec, 1));
     PS_HIP(timed(p, K_INV_X, [&] {
-        return launch_inv_x<T>(spec, out, p->nx, p->ny, p->nz, accumulate, p->geom, p->spx,
-                               tables<T>(p), p->stream);
+        if (p->geom.variant_x == 1)
+            return launch_c2r_fast<T>(spec, out, p->nx, p->ny, p->nz, accumulate, tb.tw4_x,
+                                      tb.tw_s, p->stream);
+        return launch_inv_x<T>(spec, out, p->nx, p->ny, p->nz, accumulate, p->geom, p->spx, tb,
+                               p->stream);
     }));
     return PS_OK;
 }
@@ -556,12 +741,12 @@ template <typename T> static int run(ps_plan *p, const T *in, T *out, int adjoin
 {
     auto *spec = reinterpret_cast<cx_t<T> *>(p->d_spec);
     const int refine = p->precision == PS_FP32_R2;
-    PS_TRY(fwd<T>(p, in, spec));
-    PS_TRY(columns<T>(p, spec, adjoint, refine));
+    PS_TRY(fwd_x<T>(p, in, spec));
+    PS_TRY(columns<T>(p, spec, adjoint, refine, 1));
     PS_TRY(inv<T>(p, spec, out, 0));
     if (p->precision == PS_FP32_R1) {
-        PS_TRY(fwd_residual<T>(p, in, out, spec, adjoint));
-        PS_TRY(columns<T>(p, spec, adjoint, 0));
+        PS_TRY(fwd_residual_x<T>(p, in, out, spec, adjoint));
+        PS_TRY(columns<T>(p, spec, adjoint, 0, 1));
         PS_TRY(inv<T>(p, spec, out, 1));
     }
     return PS_OK;
@@ -620,6 +805,147 @@ extern "C" int ps_inverse_transform(ps_plan *p, const void *spectrum, void *out)
         PS_HIP(hipMemcpyAsync(p->d_spec, spectrum, bytes, hipMemcpyDeviceToDevice, p->stream));
     if (p->fp64()) return inv<double>(p, (double2 *)p->d_spec, (double *)out, 0);
     return inv<float>(p, (float2 *)p->d_spec, (float *)out, 0);
+}
+
+// ------------------------------------------------------------------ autotuning
+// Planning chooses kernels from the sizes alone; ps_plan_autotune instead
+// times the implemented variants on the device (the measured planning that
+// FFTW offers, done here for this library's own kernels): coordinate descent
+// over the x-transform kernel, the y-transform kernel and the column-solve
+// variant, each candidate timed over `reps` solves with events on the plan's
+// stream.  Choices are cached per (device architecture, nx, ny, nz,
+// precision) for the life of the process and can be saved and loaded as text.
+static std::mutex g_tune_mu;
+static std::map<std::string, FftGeom> g_tune;
+
+static std::string tune_key(const ps_plan *p)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    std::ostringstream k;
+    k << arch << ' ' << p->nx << ' ' << p->ny << ' ' << p->nz << ' ' << p->precision;
+    return k.str();
+}
+
+static int time_solves(ps_plan *p, const void *in, void *out, int reps, float *ms)
+{
+    hipEvent_t a, b;
+    PS_HIP(hipEventCreate(&a));
+    PS_HIP(hipEventCreate(&b));
+    int rc = solve_common(p, in, out, 0); // warm-up
+    if (rc == PS_OK && hipEventRecord(a, p->stream) != hipSuccess) rc = PS_EHIP;
+    for (int i = 0; i < reps && rc == PS_OK; ++i) rc = solve_common(p, in, out, 0);
+    if (rc == PS_OK && hipEventRecord(b, p->stream) != hipSuccess) rc = PS_EHIP;
+    if (rc == PS_OK && hipEventSynchronize(b) != hipSuccess) rc = PS_EHIP;
+    if (rc == PS_OK && hipEventElapsedTime(ms, a, b) != hipSuccess) rc = PS_EHIP;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc == PS_EHIP) g_last_error = "autotune timing failed";
+    return rc;
+}
+
+extern "C" int ps_plan_autotune(ps_plan *p, int reps)
+{
+    if (!p) return fail(PS_EINVAL, "plan is NULL");
+    if (reps < 1) reps = 1;
+    if (reps > 100) reps = 100;
+    const std::string key = tune_key(p);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            p->geom = it->second;
+            return PS_OK;
+        }
+    }
+    const size_t bytes = (size_t)p->nx * p->ny * p->nz * p->elem();
+    void *in = nullptr, *out = nullptr;
+    PS_HIP(hipMalloc(&in, bytes));
+    if (hipMalloc(&out, bytes) != hipSuccess) {
+        (void)hipFree(in);
+        return fail(PS_ENOMEM, "autotune buffers");
+    }
+    int rc = PS_OK;
+    if (hipMemsetAsync(in, 0, bytes, p->stream) != hipSuccess) rc = fail(PS_EHIP, "memset");
+    const bool prof = p->prof.on;
+    p->prof.on = false;
+    auto pick = [&](int FftGeom::*knob, const std::vector<int> &opts) {
+        if (rc != PS_OK || opts.size() < 2) return;
+        int best = p->geom.*knob;
+        float best_ms = 1e30f;
+        for (int o : opts) {
+            p->geom.*knob = o;
+            float ms = 0.f;
+            rc = time_solves(p, in, out, reps, &ms);
+            if (rc != PS_OK) return;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = o;
+            }
+        }
+        p->geom.*knob = best;
+    };
+    std::vector<int> vx{0}, vy{0};
+    if (fast_length(p->L)) vx.push_back(1);
+    if (fast_length(p->ny)) vy.push_back(1);
+    pick(&FftGeom::variant_x, vx);
+    pick(&FftGeom::variant_y, vy);
+    if (p->precision != PS_FP32_R2) pick(&FftGeom::columns, {0, 1, 2, 3, 4});
+    pick(&FftGeom::special_side, {0, 1});
+    p->prof.on = prof;
+    (void)hipStreamSynchronize(p->stream);
+    (void)hipFree(in);
+    (void)hipFree(out);
+    if (rc != PS_OK) return rc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = p->geom;
+    return PS_OK;
+}
+
+// Text format, one line per entry: arch nx ny nz precision variant_x
+// variant_y columns
+extern "C" int ps_tune_cache_save(const char *path)
+{
+    if (!path) return fail(PS_EINVAL, "path is NULL");
+    std::ofstream f(path);
+    if (!f) return fail(PS_EINVAL, std::string("cannot write ") + path);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto &kv : g_tune)
+        f << kv.first << ' ' << kv.second.variant_x << ' ' << kv.second.variant_y << ' '
+          << kv.second.columns << ' ' << kv.second.special_side << '\n';
+    return f.good() ? PS_OK : fail(PS_EINVAL, "write failed");
+}
+
+extern "C" int ps_tune_cache_load(const char *path)
+{
+    if (!path) return fail(PS_EINVAL, "path is NULL");
+    std::ifstream f(path);
+    if (!f) return fail(PS_EINVAL, std::string("cannot read ") + path);
+    std::string line;
+    std::map<std::string, FftGeom> got;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string arch;
+        int nx, ny, nz, prec, vx, vy, col, side = 1;
+        if (!(is >> arch >> nx >> ny >> nz >> prec >> vx >> vy >> col)) continue;
+        if (!(is >> side)) side = 1;
+        if (vx < 0 || vx > 1 || vy < 0 || vy > 1 || col < 0 || col > 4 || side < 0 || side > 1)
+            continue;
+        std::ostringstream k;
+        k << arch << ' ' << nx << ' ' << ny << ' ' << nz << ' ' << prec;
+        FftGeom g;
+        g.variant_x = vx && fast_length(nx / 2) ? 1 : 0;
+        g.variant_y = vy && fast_length(ny) ? 1 : 0;
+        g.columns = col;
+        g.special_side = side;
+        got[k.str()] = g;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto &kv : got) g_tune[kv.first] = kv.second;
+    return PS_OK;
 }
 
 extern "C" const char *ps_status_string(int s)

@@ -111,13 +111,82 @@ template <int DIR, typename C> __device__ __forceinline__ void dft16(C *v)
     }
 }
 
+// cos and sin of pi m / 16, m = 1..3.
+#define PS_C32_1 0.98078528040323044913
+#define PS_S32_1 0.19509032201612826785
+#define PS_C32_3 0.83146961230254523708
+#define PS_S32_3 0.55557023301960222474
+
+template <int DIR, typename C> __device__ __forceinline__ void dft32(C *v)
+{
+    using T = decltype(v[0].x);
+    C e[16], o[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        e[q] = v[2 * q];
+        o[q] = v[2 * q + 1];
+    }
+    dft16<DIR>(e);
+    dft16<DIR>(o);
+    const T c1 = T(PS_C32_1), s1 = T(PS_S32_1), c2 = T(PS_C16_1), s2 = T(PS_S16_1);
+    const T c3 = T(PS_C32_3), s3 = T(PS_S32_3), r = T(PS_R2_2);
+    // W32^q = cos(pi q/16) + DIR i sin(pi q/16), q = 0..15
+    const T wc[16] = {T(1), c1, c2, c3, r, s3, s2, s1, T(0), -s1, -s2, -s3, -r, -c3, -c2, -c1};
+    const T ws[16] = {T(0), s1, s2, s3, r, c3, c2, c1, T(1), c1, c2, c3, r, s3, s2, s1};
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        C t = q == 0 ? o[0] : cmul(o[q], C{wc[q], DIR * ws[q]});
+        v[q] = cadd(e[q], t);
+        v[q + 16] = csub(e[q], t);
+    }
+}
+
 template <int R, int DIR, typename C> __device__ __forceinline__ void dft(C *v)
 {
-    if constexpr (R == 2) dft2<DIR>(v[0], v[1]);
+    if constexpr (R == 1) {
+    } else if constexpr (R == 2) dft2<DIR>(v[0], v[1]);
     else if constexpr (R == 3) dft3<DIR>(v);
     else if constexpr (R == 4) dft4<DIR>(v);
     else if constexpr (R == 8) dft8<DIR>(v);
     else if constexpr (R == 16) dft16<DIR>(v);
+    else if constexpr (R == 32) dft32<DIR>(v);
+}
+
+// ---- four-step row transform in registers ----------------------------------
+// A row of length L = R1 R2 (R1 divides R2) is held by R1 lanes of one
+// wavefront (lane t in [0, R1)).  On entry v[q] = x[t + R1 q].  Step A: an
+// R2-point DFT over q, then the twiddle W_L^{t k2}; the [t][k2] -> [k2][t]
+// exchange goes through LDS one real component at a time (row stride R1 + 1
+// words, so the transposed reads do not conflict); step B: R1-point DFTs.
+// On exit w[j R1 + k1] = X[(t + R1 j) + R2 k1], j in [0, R2/R1).
+// tw4[k2 R1 + t] = W_L^{t k2} (forward roots; conjugated for DIR > 0).
+// lds is this row's scratch of R2 (R1 + 1) values; every thread of the block
+// must call this together (it synchronises the block).
+template <int R1, int R2, int DIR, typename C, typename T>
+__device__ __forceinline__ void four_step(C (&v)[R2], C (&w)[R2], int t, T *lds,
+                                          const C *__restrict__ tw4)
+{
+    constexpr int P = R1 + 1;
+    dft<R2, DIR>(v);
+#pragma unroll
+    for (int k2 = 1; k2 < R2; ++k2) v[k2] = ctw<DIR>(v[k2], tw4[k2 * R1 + t]);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) lds[k2 * P + t] = v[k2].x;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < R2 / R1; ++j)
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) w[j * R1 + n1].x = lds[(t + R1 * j) * P + n1];
+    __syncthreads();
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) lds[k2 * P + t] = v[k2].y;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < R2 / R1; ++j)
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) w[j * R1 + n1].y = lds[(t + R1 * j) * P + n1];
+#pragma unroll
+    for (int j = 0; j < R2 / R1; ++j) dft<R1, DIR>(&w[j * R1]);
 }
 
 // ---- Stockham radix pass ---------------------------------------------------

@@ -10,6 +10,15 @@
 
 namespace ps {
 
+// One slot of the uniform-half column kernel's coefficient table (see
+// k_columns3): coupling to the previous and next row of the elimination,
+// D_k, right-hand-side and output factors, and the level's byte offset in
+// the spectrum (-1 for a dummy slot).
+template <typename T> struct LevelCoef {
+    T fp, fn, D, rs, os, pad;
+    long long off;
+};
+
 // Device tables of one precision T.
 template <typename T> struct Tables {
     T *ax = nullptr;      // [L+1]  4 sin^2(pi kx/nx)/dx^2
@@ -22,6 +31,13 @@ template <typename T> struct Tables {
     cx_t<T> *tw_x = nullptr;  // [L]   W_L^m
     cx_t<T> *tw_s = nullptr;  // [L]   W_nx^k (real-to-complex split)
     cx_t<T> *tw_y = nullptr;  // [ny]  W_ny^m
+    cx_t<T> *tw4_x = nullptr; // [L]   four-step twiddles W_L^{t k2} at [k2 R1 + t]
+    cx_t<T> *tw4_y = nullptr; // [ny]  same for the y length
+    // per-slot coefficients in elimination order for the uniform-half column
+    // kernel (forward and adjoint): [2 NH + 1] entries of LevelCoef<T>, NH =
+    // column_capacity(nz)
+    void *coef_fwd = nullptr;
+    void *coef_adj = nullptr;
 };
 
 // Launch geometry of the transform kernels chosen at planning time.
@@ -30,6 +46,9 @@ struct FftGeom {
     int rows_y = 1;   // rows per block of the y passes
     int variant_x = 0;
     int variant_y = 0;
+    int special_par = 2; // FP64 columns: 2 = compact prefetched loop (k_special_seq)
+    int special_side = 1; // 1: FP64 columns on the side stream beside the main kernel
+    int columns = 2;     // column-solve kernel variant (see launch_columns_impl)
 };
 
 struct Launch {
@@ -45,25 +64,44 @@ hipError_t launch_fwd_x_residual(const T *b, const T *p, cx_t<T> *spec, double *
                                  int ny, int nz, double idx2, double idy2, const double *f,
                                  const double *D, int adjoint, const FftGeom &g,
                                  const StagePlan &spx, const Tables<T> &tb, hipStream_t st);
+// y transforms of the spectrum rows (level, kx), kx in [kxlo, kxlo + kxcnt),
+// L rows per level.
 template <typename T>
-hipError_t launch_fft_y(cx_t<T> *spec, int nrows, int ny, int dir, const FftGeom &g,
-                        const StagePlan &spy, const Tables<T> &tb, hipStream_t st);
+hipError_t launch_fft_y(cx_t<T> *spec, int nz, int L, int kxlo, int kxcnt, int ny, int dir,
+                        const FftGeom &g, const StagePlan &spy, const Tables<T> &tb,
+                        hipStream_t st);
 template <typename T>
 hipError_t launch_inv_x(const cx_t<T> *spec, T *out, int nx, int ny, int nz, int accumulate,
                         const FftGeom &g, const StagePlan &spx, const Tables<T> &tb,
                         hipStream_t st);
+
+bool fast_length(int L);
+int fast_r1(int L); // lanes per row of the register-resident kernels
+template <typename T>
+hipError_t launch_fft_y_fast(cx_t<T> *spec, int nz, int L, int kxlo, int kxcnt, int ny, int dir,
+                             const cx_t<T> *tw4, hipStream_t st);
+// pres != nullptr: transform the residual in - A pres (or in - A^T pres),
+// with the per-level vertical coefficients rc (see k_r2c_fast).
+template <typename T>
+hipError_t launch_r2c_fast(const T *in, cx_t<T> *spec, double *rowsum, int nx, int ny, int nz,
+                           const cx_t<T> *tw4, const cx_t<T> *tws, hipStream_t st,
+                           const T *pres = nullptr, double idx2 = 0, double idy2 = 0,
+                           const double *rc = nullptr);
+template <typename T>
+hipError_t launch_c2r_fast(const cx_t<T> *spec, T *out, int nx, int ny, int nz, int accumulate,
+                           const cx_t<T> *tw4, const cx_t<T> *tws, hipStream_t st);
 
 hipError_t launch_level_sums(const double *rowsum, double *S, int ny, int nz, hipStream_t st);
 
 template <typename T>
 hipError_t launch_columns_impl(cx_t<T> *spec, int nx, int ny, int nz, int adjoint, int refine,
                                const int *maskcnt, const Tables<T> &tb, const Tables<double> *t64,
-                               hipStream_t st);
+                               hipStream_t st, int variant);
 
 template <typename T>
 hipError_t launch_special(cx_t<T> *spec, int nx, int ny, int nz, int adjoint, const int *mlist,
                           int nmask, const double *S, double *ws, const Tables<double> &tb64,
-                          hipStream_t st);
+                          hipStream_t st, int parallel);
 
 template <typename T>
 hipError_t launch_grad_rho(const T *lam, const T *p, int nx, int ny, int nz, const double *gk,
@@ -72,6 +110,7 @@ hipError_t launch_grad_rho(const T *lam, const T *p, int nx, int ny, int nz, con
 int grad_blocks(int nx, int ny);
 
 StagePlan make_stage_plan(int L);
+int column_capacity(int nz);
 bool is_2a3b(int n);
 
 } // namespace ps

@@ -272,3 +272,57 @@ def test_full_size_precision_1024_spectral_samples():
         assert np.abs(got_mean - ref_mean).max() < tol * np.abs(p).max()
         assert abs(p.mean()) < tol * np.abs(p).max()
         del p
+
+
+# ----------------------------------------------------------------- variants
+def _arch():
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+VARIANTS = [(0, 0, 0), (1, 1, 1), (1, 1, 2), (0, 1, 2), (1, 0, 1), (1, 1, 3), (0, 0, 4)]
+
+
+@pytest.mark.parametrize("var", VARIANTS, ids=lambda v: "x%d-y%d-c%d" % v)
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_r1"])
+def test_kernel_variants_via_tune_cache(tmp_path, precision, var):
+    """Every transform and column-kernel variant, forced through the public
+    tune-cache file, reproduces the oracle."""
+    from paper_2010_14132_amd.binding import PRECISIONS, tune_cache_load
+    nz, ny, nx = 20, 64, 128
+    announce("variants %s %s" % (precision, var))
+    g = stretched(nx, ny, nz, seed=21)
+    f = tmp_path / "tune.txt"
+    f.write_text("%s %d %d %d %d %d %d %d\n" % ((_arch(), nx, ny, nz, PRECISIONS[precision]) + var))
+    tune_cache_load(str(f))
+    plan = make_plan(g, precision)
+    plan.autotune()
+    info = plan.info()
+    assert (info["fft_variant_x"], info["fft_variant_y"], info["column_variant"]) == var
+    b = np.random.default_rng(8).standard_normal((nz, ny, nx)) + 0.1
+    if precision != "fp64":
+        b = b.astype(np.float32).astype(np.float64)
+    ref = oracle.solve(b, g.dx, g.dy, g.dz, g.rho)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    p = plan.solve(torch.from_numpy(b).to("cuda", dt)).cpu().numpy()
+    assert relmax(p, ref) < (TOL64 if precision == "fp64" else TOL32)
+    lam = plan.solve_adjoint(torch.from_numpy(b).to("cuda", dt)).cpu().numpy()
+    lref = oracle.solve_adjoint(b, g.dx, g.dy, g.dz, g.rho)
+    assert relmax(lam, lref) < (TOL64 if precision == "fp64" else TOL32)
+
+
+def test_autotune_and_cache_file(tmp_path):
+    from paper_2010_14132_amd.binding import tune_cache_save
+    nz, ny, nx = 24, 96, 256
+    announce("autotune 256x96x24 fp32")
+    g = stretched(nx, ny, nz, seed=22)
+    plan = make_plan(g, "fp32")
+    plan.autotune(reps=2)
+    info = plan.info()
+    assert info["fft_variant_y"] == 0  # 96 has no register-resident kernel
+    b = np.random.default_rng(9).standard_normal((nz, ny, nx)).astype(np.float32)
+    ref = oracle.solve(b.astype(np.float64), g.dx, g.dy, g.dz, g.rho)
+    p = plan.solve(torch.from_numpy(b).cuda()).cpu().numpy()
+    assert relmax(p, ref) < TOL32
+    path = tmp_path / "cache.txt"
+    tune_cache_save(str(path))
+    assert " %d %d %d 1 " % (nx, ny, nz) in path.read_text()
