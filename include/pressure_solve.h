@@ -190,18 +190,49 @@ int ps_inverse_transform(ps_plan *plan, const void *spectrum, void *p);
 
 /* ---- batched: many independent solves of uneven sizes ------------------
  * Describe count problems once (each with its own grid and densities, all
- * of one precision); ps_batch_solve then solves all of them with one
- * persistent launch per step replayed from a captured hipGraph.
+ * of one precision; each planned as by ps_plan_create, so the plan's size
+ * limits apply, and nz <= 128); ps_batch_solve then solves all of them by
+ * replaying a captured hipGraph: every problem's five phases (x forward, y
+ * forward, column solves, y backward, x backward) are cut into block-sized
+ * tiles, and the graph holds one kernel per phase over the tiles of that
+ * phase of every problem (mode PS_BATCH_PHASES).
+ * CURRENTLY SWITCHED OFF: ps_batch_solve and ps_batch_autotune return
+ * PS_EUNSUPPORTED (the persistent form did not complete on the GPU, its
+ * cause is not found, and the per-phase graph has not been verified).
+ * Create, set_mode, set_stream, query, status and destroy work.
  *   nx, ny, nz, dx, dy : host arrays of count values.
  *   dz, rho            : host arrays of count host pointers to nz[i] values.
- *   precision          : PS_FP64 or PS_FP32. */
+ *   precision          : PS_FP64 or PS_FP32 (else PS_EUNSUPPORTED).
+ *   stream             : hipStream_t the graph is launched on.
+ * Errors as ps_plan_create (the message names the failing problem). */
 int ps_batch_create(ps_batch **out, int count, const int *nx, const int *ny,
                     const int *nz, const double *dx, const double *dy,
                     const double *const *dz, const double *const *rho,
                     int precision, void *stream);
-/* rhs, p: host arrays of count device pointers.  The first call (and any
- * call with different pointers) captures the graph; later calls replay it. */
+/* rhs, p: host arrays of count device pointers ([nz][ny][nx] fields of the
+ * batch's element type; rhs[i] must not alias p[i]).  The first call, and
+ * any call with different pointers, captures the graph (synchronising the
+ * stream first); later calls only replay it (asynchronous).  One replay in
+ * flight per batch. */
 int ps_batch_solve(ps_batch *batch, const void *const *rhs, void *const *p);
+int ps_batch_set_stream(ps_batch *batch, void *stream);
+/* PS_BATCH_PHASES: one launch per phase (the default).  PS_BATCH_PERSISTENT:
+ * all phases in a single persistent launch whose blocks take (problem, phase,
+ * tile) tickets and wait per problem for the previous phase -- switched off:
+ * it did not complete on the GPU, so requesting it returns PS_EUNSUPPORTED. */
+enum { PS_BATCH_PHASES = 0, PS_BATCH_PERSISTENT = 1 };
+int ps_batch_set_mode(ps_batch *batch, int mode);
+/* Time the tile layouts for 32, 48 and 60 KiB of LDS per block on the given
+ * fields (reps replays each) and keep the fastest.  Synchronises. */
+int ps_batch_autotune(ps_batch *batch, const void *const *rhs, void *const *p, int reps);
+/* count of problems, total tiles of the work list, blocks of the persistent
+ * launch, LDS budget per block in bytes (any pointer may be NULL). */
+int ps_batch_query(const ps_batch *batch, int *count, int *tiles, int *grid, int *lds_budget);
+/* Synchronise the batch's stream; PS_OK if the last replay completed, or
+ * PS_ESTATE if its persistent kernel gave up waiting for a phase (a bounded
+ * wait: the kernel then ends instead of hanging, leaving the outputs
+ * incomplete). */
+int ps_batch_status(ps_batch *batch);
 int ps_batch_destroy(ps_batch *batch);
 
 const char *ps_status_string(int status);

@@ -5,6 +5,6 @@ The solve runs in the HIP library libpressure_solve.so behind the C ABI of
 include/pressure_solve.h; this package is its thin Python binding
 (``Plan``, ``poisson_solve``) plus the seeded synthetic workloads.
 """
-from .binding import Plan, PressureSolveError, poisson_solve, PRECISIONS  # noqa: F401
+from .binding import BatchPlan, Plan, PressureSolveError, poisson_solve, PRECISIONS  # noqa: F401
 
-__all__ = ["Plan", "PressureSolveError", "poisson_solve", "PRECISIONS"]
+__all__ = ["BatchPlan", "Plan", "PressureSolveError", "poisson_solve", "PRECISIONS"]

@@ -60,6 +60,11 @@ SIGNATURES = {
                                        ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.c_int, _vp]),
     "ps_batch_solve": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "ps_batch_destroy": (ctypes.c_int, [_vp]),
+    "ps_batch_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "ps_batch_autotune": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int]),
+    "ps_batch_query": (ctypes.c_int, [_vp, _I, _I, _I, _I]),
+    "ps_batch_status": (ctypes.c_int, [_vp]),
+    "ps_batch_set_mode": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ps_plan_profile": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ps_plan_profile_report": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                               ctypes.POINTER(ctypes.c_double),
@@ -320,3 +325,82 @@ def tune_cache_save(path: str):
 
 def tune_cache_load(path: str):
     check(load().ps_tune_cache_load(os.fsencode(path)), "ps_tune_cache_load")
+
+
+class BatchPlan:
+    """Many independent solves of uneven sizes in one persistent launch
+    replayed from a captured hipGraph (the C ABI's ps_batch).
+
+    grids: sequence of workloads.Grid-like objects (nx, ny, nz, dx, dy, dz,
+    rho); precision "fp32" or "fp64"."""
+
+    MODES = {"phases": 0, "persistent": 1}
+
+    def __init__(self, grids, precision="fp32", mode="phases"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the pressure-solve library needs a GPU (no CPU fallback)")
+        lib = load()
+        self.grids = list(grids)
+        n = len(self.grids)
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        ia = lambda vals: (ctypes.c_int * n)(*vals)
+        da = lambda vals: (ctypes.c_double * n)(*vals)
+        self._dz = [np.ascontiguousarray(g.dz, dtype=np.float64) for g in self.grids]
+        self._rho = [np.ascontiguousarray(g.rho, dtype=np.float64) for g in self.grids]
+        dzp = (_D * n)(*[_dptr(a) for a in self._dz])
+        rhop = (_D * n)(*[_dptr(a) for a in self._rho])
+        h = _vp()
+        check(lib.ps_batch_create(ctypes.byref(h), n, ia([g.nx for g in self.grids]),
+                                  ia([g.ny for g in self.grids]), ia([g.nz for g in self.grids]),
+                                  da([g.dx for g in self.grids]), da([g.dy for g in self.grids]),
+                                  dzp, rhop, PRECISIONS[precision], _stream_handle()),
+              "ps_batch_create")
+        self._h = h
+        check(lib.ps_batch_set_mode(h, self.MODES[mode]), "ps_batch_set_mode")
+
+    def _ptrs(self, rhs, out):
+        n = len(self.grids)
+        for i, (b, p, g) in enumerate(zip(rhs, out, self.grids)):
+            for t, nm in ((b, "rhs"), (p, "out")):
+                if t.dtype != self.dtype or tuple(t.shape) != (g.nz, g.ny, g.nx) \
+                        or not t.is_contiguous() or t.device != self.device:
+                    raise ValueError("%s[%d] must be a contiguous %s tensor of shape %s on %s"
+                                     % (nm, i, self.dtype, (g.nz, g.ny, g.nx), self.device))
+        return ((_vp * n)(*[_vp(t.data_ptr()) for t in rhs]),
+                (_vp * n)(*[_vp(t.data_ptr()) for t in out]))
+
+    def solve(self, rhs, out):
+        """Solve every problem: rhs and out are lists of tensors."""
+        rp, op = self._ptrs(rhs, out)
+        check(load().ps_batch_set_stream(self._h, _stream_handle()), "ps_batch_set_stream")
+        check(load().ps_batch_solve(self._h, rp, op), "ps_batch_solve")
+        return out
+
+    def autotune(self, rhs, out, reps=3):
+        rp, op = self._ptrs(rhs, out)
+        check(load().ps_batch_set_stream(self._h, _stream_handle()), "ps_batch_set_stream")
+        check(load().ps_batch_autotune(self._h, rp, op, int(reps)), "ps_batch_autotune")
+
+    def status(self):
+        """Synchronise; raise if the last replay gave up waiting for a phase."""
+        check(load().ps_batch_status(self._h), "ps_batch_status")
+
+    def info(self) -> dict:
+        c, t, g, l = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(load().ps_batch_query(self._h, ctypes.byref(c), ctypes.byref(t), ctypes.byref(g),
+                                    ctypes.byref(l)), "ps_batch_query")
+        return {"count": c.value, "tiles": t.value, "grid": g.value, "lds_budget": l.value}
+
+    def close(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h is not None and h.value and _lib is not None:
+            _lib.ps_batch_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -10,72 +10,9 @@
 // even/odd split; the two real coefficients X_0 and X_{nx/2} share slot
 // kx = 0 as X_0 + i X_{nx/2}.
 #include "ps_internal.h"
+#include "ps_tiles.h"
 
 namespace ps {
-
-// ---------------------------------------------------------------- x forward
-// Block: `rows` consecutive rows (row g = level * ny + j).  Also records the
-// FP64 sum of every input row (for the mean column).
-template <typename T>
-__global__ __launch_bounds__(256) void k_fwd_x(const T *__restrict__ in, cx_t<T> *__restrict__ spec,
-                                               double *__restrict__ rowsum, int nx, int ny,
-                                               int nrows_total, int rows, StagePlan sp,
-                                               const cx_t<T> *__restrict__ twx,
-                                               const cx_t<T> *__restrict__ tws)
-{
-    using C = cx_t<T>;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int L = nx >> 1;
-    C *a = reinterpret_cast<C *>(smem);
-    C *b = a + rows * L;
-    C *stw = b + rows * L;
-    C *sws = stw + L;
-    const int row0 = blockIdx.x * rows;
-    const int nr = min(rows, nrows_total - row0);
-
-    for (int t = threadIdx.x; t < L; t += blockDim.x) {
-        stw[t] = twx[t];
-        sws[t] = tws[t];
-    }
-    // The block's rows are one contiguous run of nr * L complex pairs.
-    const C *src = reinterpret_cast<const C *>(in) + (size_t)row0 * L;
-    for (int t = threadIdx.x; t < nr * L; t += blockDim.x) a[t] = src[t];
-    __syncthreads();
-
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int r = wv; r < nr; r += nw) {
-        double s = 0.0;
-        for (int n = lane; n < L; n += 64) {
-            C z = a[r * L + n];
-            s += (double)z.x + (double)z.y;
-        }
-        s = wave_sum(s);
-        if (lane == 0) rowsum[row0 + r] = s;
-    }
-
-    C *Z = stockham_rows<-1>(a, b, nr, L, sp, stw);
-
-    // Even/odd split, X_k = E_k + W_nx^k O_k with E_k = (Z_k + conj Z_{L-k})/2
-    // and O_k = (Z_k - conj Z_{L-k})/(2i); slot 0 holds X_0 + i X_{L}.
-    for (int t = threadIdx.x; t < nr * L; t += blockDim.x) {
-        const int kx = t / nr, r = t - kx * nr;
-        const C *zr = Z + r * L;
-        C X;
-        if (kx == 0) {
-            C z0 = zr[0];
-            X = C{z0.x + z0.y, z0.x - z0.y};
-        } else {
-            C zk = zr[kx], zc = cconj(zr[L - kx]);
-            C e = C{T(0.5) * (zk.x + zc.x), T(0.5) * (zk.y + zc.y)};
-            C d = csub(zk, zc);
-            C o = C{T(0.5) * d.y, T(-0.5) * d.x};
-            X = cadd(e, cmul(o, sws[kx]));
-        }
-        const int g = row0 + r;
-        const int lev = g / ny, j = g - lev * ny;
-        spec[((size_t)lev * L + kx) * ny + j] = X;
-    }
-}
 
 // x forward of the residual r = b - A p (adjoint: r = b - A^T p with
 // A^T = D A D^{-1}, which changes only the vertical term), formed with FP64
@@ -166,43 +103,30 @@ __global__ __launch_bounds__(256) void k_fwd_x_residual(
     }
 }
 
-// ---------------------------------------------------------------- y pass
-// In-place complex transform of contiguous rows of length ny.  The rows
-// transformed are (level, kx) for kx in [kxlo, kxlo + kxcnt) of a spectrum
-// with L rows per level: row r maps to (r / kxcnt) L + kxlo + r % kxcnt.
+// ---------------------------------------------------------------- kernels
+template <typename T>
+__global__ __launch_bounds__(256) void k_fwd_x(const T *__restrict__ in, cx_t<T> *__restrict__ spec,
+                                               double *__restrict__ rowsum, int nx, int ny,
+                                               int nrows_total, int rows, StagePlan sp,
+                                               const cx_t<T> *__restrict__ twx,
+                                               const cx_t<T> *__restrict__ tws)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    fwd_x_tile<T>(in, spec, rowsum, nx, ny, nrows_total, rows, blockIdx.x * rows, sp, twx, tws,
+                  smem);
+}
+
 template <typename T, int DIR>
 __global__ __launch_bounds__(256) void k_fft_y(cx_t<T> *__restrict__ spec, int nrows_total, int ny,
                                                int rows, StagePlan sp,
                                                const cx_t<T> *__restrict__ twy, int L, int kxlo,
                                                int kxcnt)
 {
-    using C = cx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
-    C *a = reinterpret_cast<C *>(smem);
-    C *b = a + rows * ny;
-    C *stw = b + rows * ny;
-    const int row0 = blockIdx.x * rows;
-    const int nr = min(rows, nrows_total - row0);
-    for (int t = threadIdx.x; t < ny; t += blockDim.x) stw[t] = twy[t];
-    for (int t = threadIdx.x; t < nr * ny; t += blockDim.x) {
-        const int rr = row0 + t / ny, e = t - (t / ny) * ny;
-        const long row = (long)(rr / kxcnt) * L + kxlo + rr % kxcnt;
-        a[t] = spec[row * ny + e];
-    }
-    __syncthreads();
-    C *Z = stockham_rows<DIR>(a, b, nr, ny, sp, stw);
-    for (int t = threadIdx.x; t < nr * ny; t += blockDim.x) {
-        const int rr = row0 + t / ny, e = t - (t / ny) * ny;
-        const long row = (long)(rr / kxcnt) * L + kxlo + rr % kxcnt;
-        spec[row * ny + e] = Z[t];
-    }
+    fft_y_tile<T, DIR>(spec, nrows_total, ny, rows, blockIdx.x * rows, sp, twy, L, kxlo, kxcnt,
+                       smem);
 }
 
-// ---------------------------------------------------------------- x backward
-// Gathers a block of rows from the transposed spectrum, undoes the packing
-// (Z_k = (X_k + conj X_{L-k}) + i W_nx^{-k} (X_k - conj X_{L-k})), runs the
-// nx/2-point backward transform and writes real rows (optionally added to
-// what out already holds).
 template <typename T>
 __global__ __launch_bounds__(256) void k_inv_x(const cx_t<T> *__restrict__ spec, T *__restrict__ out,
                                                int nx, int ny, int nrows_total, int rows,
@@ -210,49 +134,9 @@ __global__ __launch_bounds__(256) void k_inv_x(const cx_t<T> *__restrict__ spec,
                                                const cx_t<T> *__restrict__ twx,
                                                const cx_t<T> *__restrict__ tws)
 {
-    using C = cx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int L = nx >> 1;
-    C *a = reinterpret_cast<C *>(smem);
-    C *b = a + rows * L;
-    C *stw = b + rows * L;
-    C *sws = stw + L;
-    const int row0 = blockIdx.x * rows;
-    const int nr = min(rows, nrows_total - row0);
-    for (int t = threadIdx.x; t < L; t += blockDim.x) {
-        stw[t] = twx[t];
-        sws[t] = tws[t];
-    }
-    for (int t = threadIdx.x; t < nr * L; t += blockDim.x) {
-        const int kx = t / nr, r = t - kx * nr;
-        const int g = row0 + r;
-        const int lev = g / ny, j = g - lev * ny;
-        a[r * L + kx] = spec[((size_t)lev * L + kx) * ny + j];
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < nr * L; t += blockDim.x) {
-        const int r = t / L, k = t - r * L;
-        const C *xr = a + r * L;
-        C Z;
-        if (k == 0) {
-            const T x0 = xr[0].x, xl = xr[0].y;
-            Z = C{x0 + xl, x0 - xl};
-        } else {
-            C xk = xr[k], xc = cconj(xr[L - k]);
-            C s = cadd(xk, xc);
-            C dw = cmul(csub(xk, xc), cconj(sws[k]));
-            Z = C{s.x - dw.y, s.y + dw.x};
-        }
-        b[t] = Z;
-    }
-    __syncthreads();
-    C *R = stockham_rows<1>(b, a, nr, L, sp, stw);
-    C *dst = reinterpret_cast<C *>(out) + (size_t)row0 * L;
-    for (int t = threadIdx.x; t < nr * L; t += blockDim.x) {
-        C v = R[t];
-        if (accumulate) v = cadd(v, dst[t]);
-        dst[t] = v;
-    }
+    inv_x_tile<T>(spec, out, nx, ny, nrows_total, rows, blockIdx.x * rows, accumulate, sp, twx,
+                  tws, smem);
 }
 
 // ---------------------------------------------------------------- launchers

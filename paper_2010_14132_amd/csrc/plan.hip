@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "ps_internal.h"
+#include "ps_plan_impl.h"
 #include "../../include/pressure_solve.h"
 
 using namespace ps;
@@ -24,6 +25,8 @@ static int fail(int code, const std::string &msg)
     g_last_error = msg;
     return code;
 }
+
+int ps::set_error(int code, const std::string &msg) { return fail(code, msg); }
 
 #define PS_HIP(call)                                                                               \
     do {                                                                                           \
@@ -77,77 +80,6 @@ StagePlan make_stage_plan(int L)
 }
 
 } // namespace ps
-
-// Per-kernel event timing (see ps_plan_profile).
-enum KernelId { K_FWD_X, K_FWD_X_RES, K_LEVEL_SUMS, K_FFT_Y_FWD, K_COLUMNS, K_SPECIAL, K_FFT_Y_INV,
-                K_INV_X, K_GRAD, K_COUNT };
-static const char *const kKernelNames[K_COUNT] = {
-    "fwd_x", "fwd_x_residual", "level_sums", "fft_y_fwd", "columns", "special_fp64",
-    "fft_y_inv", "inv_x", "grad_rho"};
-
-struct Profiler {
-    bool on = false;
-    struct Rec {
-        int id;
-        hipEvent_t a, b;
-    };
-    std::vector<Rec> recs;
-    std::vector<hipEvent_t> pool;
-    double total_ms[K_COUNT] = {};
-    int launches[K_COUNT] = {};
-    hipEvent_t get()
-    {
-        if (!pool.empty()) {
-            hipEvent_t e = pool.back();
-            pool.pop_back();
-            return e;
-        }
-        hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        return e;
-    }
-    ~Profiler()
-    {
-        for (auto &r : recs) {
-            (void)hipEventDestroy(r.a);
-            (void)hipEventDestroy(r.b);
-        }
-        for (auto e : pool) (void)hipEventDestroy(e);
-    }
-};
-
-struct ps_plan {
-    Profiler prof;
-    int nx = 0, ny = 0, nz = 0, L = 0, precision = 0;
-    double dx = 0, dy = 0, tau = 0;
-    std::vector<double> dz, rho;
-    hipStream_t stream = nullptr;
-    hipStream_t side = nullptr;        // the FP64 column kernel runs here, beside the main one
-    hipEvent_t fork = nullptr, join = nullptr;
-    int device = 0;
-    std::vector<double> ax, ay, f, D;
-    StagePlan spx{}, spy{};
-    FftGeom geom;
-    Tables<float> t32;
-    Tables<double> t64;
-    int *d_maskcnt = nullptr;
-    int *d_mlist = nullptr;
-    int nmask = 0;
-    int kmask = 1; // rows kx < kmask hold every column solved in FP64
-    void *d_spec = nullptr;
-    double *d_rowsum = nullptr;
-    double *d_S = nullptr;
-    double *d_ws = nullptr;
-    double *d_gk = nullptr;
-    double *d_partial = nullptr;
-    double *d_rc = nullptr; // residual vertical coefficients [fwd: 3 nz][adj: 3 nz]
-    int nblk = 0;
-    size_t bytes = 0;
-    std::vector<void *> allocs;
-    bool fp64() const { return precision == PS_FP64; }
-    size_t elem() const { return fp64() ? sizeof(double) : sizeof(float); }
-    size_t spec_elems() const { return (size_t)nz * L * ny; }
-};
 
 static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
@@ -681,7 +613,7 @@ static int columns(ps_plan *p, cx_t<T> *spec, int adjoint, int refine, int ypass
             p, K_SPECIAL,
             [&] {
                 return launch_special<T>(spec, p->nx, p->ny, p->nz, adjoint, p->d_mlist, p->nmask,
-                                         p->d_S, p->d_ws, p->t64, p->side, p->geom.special_par);
+                                         p->d_S, p->d_ws, p->t64, p->side, 0);
             },
             p->side));
         PS_HIP(hipEventRecord(p->join, p->side));
@@ -697,7 +629,7 @@ static int columns(ps_plan *p, cx_t<T> *spec, int adjoint, int refine, int ypass
     if (!p->geom.special_side) {
         PS_HIP(timed(p, K_SPECIAL, [&] {
             return launch_special<T>(spec, p->nx, p->ny, p->nz, adjoint, p->d_mlist, p->nmask,
-                                     p->d_S, p->d_ws, p->t64, p->stream, p->geom.special_par);
+                                     p->d_S, p->d_ws, p->t64, p->stream, 0);
         }));
         PS_HIP(timed(p, K_COLUMNS, [&] {
             return launch_columns_impl<T>(spec, p->nx, p->ny, p->nz, adjoint, refine, mc,
@@ -711,7 +643,7 @@ static int columns(ps_plan *p, cx_t<T> *spec, int adjoint, int refine, int ypass
         p, K_SPECIAL,
         [&] {
             return launch_special<T>(spec, p->nx, p->ny, p->nz, adjoint, p->d_mlist, p->nmask,
-                                     p->d_S, p->d_ws, p->t64, p->side, p->geom.special_par);
+                                     p->d_S, p->d_ws, p->t64, p->side, 0);
         },
         p->side));
     PS_HIP(hipEventRecord(p->join, p->side));

@@ -46,7 +46,6 @@ struct FftGeom {
     int rows_y = 1;   // rows per block of the y passes
     int variant_x = 0;
     int variant_y = 0;
-    int special_par = 2; // FP64 columns: 2 = compact prefetched loop (k_special_seq)
     int special_side = 1; // 1: FP64 columns on the side stream beside the main kernel
     int columns = 2;     // column-solve kernel variant (see launch_columns_impl)
 };
@@ -110,6 +109,7 @@ hipError_t launch_grad_rho(const T *lam, const T *p, int nx, int ny, int nz, con
 int grad_blocks(int nx, int ny);
 
 StagePlan make_stage_plan(int L);
+int set_error(int code, const std::string &msg); // records ps_last_error(), returns code
 int column_capacity(int nz);
 bool is_2a3b(int n);
 

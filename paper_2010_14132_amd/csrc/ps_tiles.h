@@ -1,0 +1,470 @@
+// Device-side work tiles shared by the standalone kernels and the batched
+// persistent kernel: the Stockham transform tiles (x forward with FP64 row
+// sums, y pass, x backward), the uniform-half column sweep over 128 columns
+// and the compact FP64 column task.  Each is executed by one 256-thread
+// block (the FP64 task by one lane).
+#pragma once
+#include "ps_internal.h"
+#include "../../include/pressure_solve.h"
+
+namespace ps {
+
+// ---------------------------------------------------------------- x forward
+// Block: `rows` consecutive rows (row g = level * ny + j).  Also records the
+// FP64 sum of every input row (for the mean column).
+template <typename T>
+__device__ void fwd_x_tile(const T *__restrict__ in, cx_t<T> *__restrict__ spec,
+                           double *__restrict__ rowsum, int nx, int ny, int nrows_total, int rows,
+                           int row0, const StagePlan &sp, const cx_t<T> *__restrict__ twx,
+                           const cx_t<T> *__restrict__ tws, unsigned char *smem)
+{
+    using C = cx_t<T>;
+    const int L = nx >> 1;
+    C *a = reinterpret_cast<C *>(smem);
+    C *b = a + rows * L;
+    C *stw = b + rows * L;
+    C *sws = stw + L;
+    const int nr = min(rows, nrows_total - row0);
+
+    for (int t = threadIdx.x; t < L; t += blockDim.x) {
+        stw[t] = twx[t];
+        sws[t] = tws[t];
+    }
+    // The block's rows are one contiguous run of nr * L complex pairs.
+    const C *src = reinterpret_cast<const C *>(in) + (size_t)row0 * L;
+    for (int t = threadIdx.x; t < nr * L; t += blockDim.x) a[t] = src[t];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int r = wv; r < nr; r += nw) {
+        double s = 0.0;
+        for (int n = lane; n < L; n += 64) {
+            C z = a[r * L + n];
+            s += (double)z.x + (double)z.y;
+        }
+        s = wave_sum(s);
+        if (lane == 0) rowsum[row0 + r] = s;
+    }
+
+    C *Z = stockham_rows<-1>(a, b, nr, L, sp, stw);
+
+    // Even/odd split, X_k = E_k + W_nx^k O_k with E_k = (Z_k + conj Z_{L-k})/2
+    // and O_k = (Z_k - conj Z_{L-k})/(2i); slot 0 holds X_0 + i X_{L}.
+    for (int t = threadIdx.x; t < nr * L; t += blockDim.x) {
+        const int kx = t / nr, r = t - kx * nr;
+        const C *zr = Z + r * L;
+        C X;
+        if (kx == 0) {
+            C z0 = zr[0];
+            X = C{z0.x + z0.y, z0.x - z0.y};
+        } else {
+            C zk = zr[kx], zc = cconj(zr[L - kx]);
+            C e = C{T(0.5) * (zk.x + zc.x), T(0.5) * (zk.y + zc.y)};
+            C d = csub(zk, zc);
+            C o = C{T(0.5) * d.y, T(-0.5) * d.x};
+            X = cadd(e, cmul(o, sws[kx]));
+        }
+        const int g = row0 + r;
+        const int lev = g / ny, j = g - lev * ny;
+        spec[((size_t)lev * L + kx) * ny + j] = X;
+    }
+}
+
+// ---------------------------------------------------------------- y pass
+// In-place complex transform of contiguous rows of length ny.  The rows
+// transformed are (level, kx) for kx in [kxlo, kxlo + kxcnt) of a spectrum
+// with L rows per level: row r maps to (r / kxcnt) L + kxlo + r % kxcnt.
+template <typename T, int DIR>
+__device__ void fft_y_tile(cx_t<T> *__restrict__ spec, int nrows_total, int ny, int rows, int row0,
+                           const StagePlan &sp, const cx_t<T> *__restrict__ twy, int L, int kxlo,
+                           int kxcnt, unsigned char *smem)
+{
+    using C = cx_t<T>;
+    C *a = reinterpret_cast<C *>(smem);
+    C *b = a + rows * ny;
+    C *stw = b + rows * ny;
+    const int nr = min(rows, nrows_total - row0);
+    for (int t = threadIdx.x; t < ny; t += blockDim.x) stw[t] = twy[t];
+    for (int t = threadIdx.x; t < nr * ny; t += blockDim.x) {
+        const int rr = row0 + t / ny, e = t - (t / ny) * ny;
+        const long row = (long)(rr / kxcnt) * L + kxlo + rr % kxcnt;
+        a[t] = spec[row * ny + e];
+    }
+    __syncthreads();
+    C *Z = stockham_rows<DIR>(a, b, nr, ny, sp, stw);
+    for (int t = threadIdx.x; t < nr * ny; t += blockDim.x) {
+        const int rr = row0 + t / ny, e = t - (t / ny) * ny;
+        const long row = (long)(rr / kxcnt) * L + kxlo + rr % kxcnt;
+        spec[row * ny + e] = Z[t];
+    }
+}
+
+// ---------------------------------------------------------------- x backward
+// Gathers a block of rows from the transposed spectrum, undoes the packing
+// (Z_k = (X_k + conj X_{L-k}) + i W_nx^{-k} (X_k - conj X_{L-k})), runs the
+// nx/2-point backward transform and writes real rows (optionally added to
+// what out already holds).
+template <typename T>
+__device__ void inv_x_tile(const cx_t<T> *__restrict__ spec, T *__restrict__ out, int nx, int ny,
+                           int nrows_total, int rows, int row0, int accumulate,
+                           const StagePlan &sp, const cx_t<T> *__restrict__ twx,
+                           const cx_t<T> *__restrict__ tws, unsigned char *smem)
+{
+    using C = cx_t<T>;
+    const int L = nx >> 1;
+    C *a = reinterpret_cast<C *>(smem);
+    C *b = a + rows * L;
+    C *stw = b + rows * L;
+    C *sws = stw + L;
+    const int nr = min(rows, nrows_total - row0);
+    for (int t = threadIdx.x; t < L; t += blockDim.x) {
+        stw[t] = twx[t];
+        sws[t] = tws[t];
+    }
+    for (int t = threadIdx.x; t < nr * L; t += blockDim.x) {
+        const int kx = t / nr, r = t - kx * nr;
+        const int g = row0 + r;
+        const int lev = g / ny, j = g - lev * ny;
+        a[r * L + kx] = spec[((size_t)lev * L + kx) * ny + j];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nr * L; t += blockDim.x) {
+        const int r = t / L, k = t - r * L;
+        const C *xr = a + r * L;
+        C Z;
+        if (k == 0) {
+            const T x0 = xr[0].x, xl = xr[0].y;
+            Z = C{x0 + xl, x0 - xl};
+        } else {
+            C xk = xr[k], xc = cconj(xr[L - k]);
+            C s = cadd(xk, xc);
+            C dw = cmul(csub(xk, xc), cconj(sws[k]));
+            Z = C{s.x - dw.y, s.y + dw.x};
+        }
+        b[t] = Z;
+    }
+    __syncthreads();
+    C *R = stockham_rows<1>(b, a, nr, L, sp, stw);
+    C *dst = reinterpret_cast<C *>(out) + (size_t)row0 * L;
+    for (int t = threadIdx.x; t < nr * L; t += blockDim.x) {
+        C v = R[t];
+        if (accumulate) v = cadd(v, dst[t]);
+        dst[t] = v;
+    }
+}
+
+// ----------------------------------------------------------- uniform-half sweep
+// Reciprocal of a pivot u > 0 in the normal range.  FP32: the hardware
+// reciprocal refined by one Newton step (within one ulp of the IEEE
+// quotient); FP64: IEEE division.
+__device__ __forceinline__ float pivot_rcp(float u)
+{
+    const float r = __builtin_amdgcn_rcpf(u);
+    const float e = __builtin_fmaf(-u, r, 1.0f);
+    return __builtin_fmaf(r, e, r);
+}
+__device__ __forceinline__ double pivot_rcp(double u) { return 1.0 / u; }
+
+// Per-slot coefficients in each half's elimination order (built by the plan):
+// slot [half][i], i in [0, NH), for level k = i (low half) or k = nz - 1 - i
+// (high half), with the half's real levels in the LAST n slots and dummy
+// slots in front (f_prev = f_next = 0, D = 1, rs = 0, off -> middle row).  A
+// dummy row never influences a real one: the first real row of each half is
+// a boundary row (f_prev = 0).  Slot [2 NH] is the middle row m.  rs/os are
+// the forward or adjoint right-hand-side and output factors.  `off` is the
+// byte offset of the level in the spectrum.  Wave-uniform, so they are read
+// through the scalar cache.
+// Two waves per group of 64 columns: the low-half wave eliminates levels
+// 0..m-1 and the high-half wave levels nz-1..m+1, one column per lane
+// (complex values, real pivots); they exchange their messages to the middle
+// row through LDS.  KEEPG keeps the reciprocal pivots in registers instead
+// of recomputing them in the backward pass.
+// `group` selects 128 consecutive columns of the kx >= 1 range; xa / xb
+// are LDS scratch of 2 * 2 * 64 values each (the block's 256 threads call
+// this together).
+template <typename T, int NH, bool KEEPG>
+__device__ void columns3_tile(cx_t<T> *__restrict__ spec, int L, int ny, const T *__restrict__ ax,
+                              const T *__restrict__ ay, const LevelCoef<T> *__restrict__ coef,
+                              const int *__restrict__ maskcnt, long group, T (*xa)[2][64],
+                              cx_t<T> (*xb)[2][64])
+{
+    using C = cx_t<T>;
+    constexpr int CH = NH < 8 ? NH : 8;
+    constexpr int NB = (NH + CH - 1) / CH;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int pair = w >> 1, half = w & 1;
+    const long ncol = (long)L * ny;
+    const long col = (long)ny + (group * 2 + pair) * 64 + lane;
+    const bool valid = col < ncol;
+    const int kx = valid ? (int)(col / ny) : 1;
+    const int ky = valid ? (int)(col - (long)kx * ny) : 0;
+    const T s = ax[kx] + ay[ky];
+    bool store = valid;
+    if (maskcnt && valid) {
+        const int d = min(ky, ny - ky);
+        if (d < maskcnt[kx]) store = false;
+    }
+    char *base = reinterpret_cast<char *>(spec + (valid ? col : 0));
+    const LevelCoef<T> *ct = coef + half * NH;
+
+    C v[NH];
+#pragma unroll
+    for (int i = 0; i < NH; ++i) {
+        const C x = *reinterpret_cast<const C *>(base + (ct[i].off < 0 ? coef[2 * NH].off : ct[i].off));
+        v[i] = C{x.x * ct[i].rs, x.y * ct[i].rs};
+    }
+    const LevelCoef<T> cm = coef[2 * NH];
+    C rmv = *reinterpret_cast<const C *>(base + cm.off);
+    rmv = C{rmv.x * cm.rs, rmv.y * cm.rs};
+
+    T qck[KEEPG ? 1 : NB];
+    T gk[KEEPG ? NH : 1];
+    T q = T(0), g = T(0);
+    C y = C{T(0), T(0)};
+#pragma unroll
+    for (int i = 0; i < NH; ++i) {
+        if (!KEEPG && i % CH == 0) qck[i / CH] = q;
+        const T e = s * ct[i].D + ct[i].fp * q;
+        const T gi = pivot_rcp(e + ct[i].fn);
+        const T c = ct[i].fp * g;
+        y = C{v[i].x + c * y.x, v[i].y + c * y.y};
+        v[i] = y;
+        q = e * gi;
+        g = gi;
+        if (KEEPG) gk[i] = gi;
+    }
+    const T fl = ct[NH - 1].fn;
+    xa[pair][half][lane] = fl * q;
+    xb[pair][half][lane] = C{(fl * g) * y.x, (fl * g) * y.y};
+    __syncthreads();
+    const T la = xa[pair][0][lane], ha = xa[pair][1][lane];
+    const C lb = xb[pair][0][lane], hb = xb[pair][1][lane];
+    const T den = (s * cm.D + la) + ha;
+    const C xm = C{((rmv.x + lb.x) + hb.x) / den, ((rmv.y + lb.y) + hb.y) / den};
+
+    C xn = xm;
+    if constexpr (KEEPG) {
+#pragma unroll
+        for (int i = NH - 1; i >= 0; --i) {
+            const T fn = ct[i].fn;
+            xn = C{gk[i] * (v[i].x + fn * xn.x), gk[i] * (v[i].y + fn * xn.y)};
+            v[i] = xn;
+        }
+    } else {
+#pragma unroll
+        for (int bb = NB - 1; bb >= 0; --bb) {
+            T gb[CH];
+            T qq = qck[bb];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int i = bb * CH + c;
+                const T e = s * ct[i].D + ct[i].fp * qq;
+                const T gi = pivot_rcp(e + ct[i].fn);
+                gb[c] = gi;
+                qq = e * gi;
+            }
+#pragma unroll
+            for (int c = CH - 1; c >= 0; --c) {
+                const int i = bb * CH + c;
+                const T fn = ct[i].fn;
+                xn = C{gb[c] * (v[i].x + fn * xn.x), gb[c] * (v[i].y + fn * xn.y)};
+                v[i] = xn;
+            }
+        }
+    }
+    if (store) {
+#pragma unroll
+        for (int i = 0; i < NH; ++i) {
+            const long long off = ct[i].off;
+            if (off >= 0)
+                *reinterpret_cast<C *>(base + off) = C{v[i].x * ct[i].os, v[i].y * ct[i].os};
+        }
+        if (half) *reinterpret_cast<C *>(base + cm.off) = C{xm.x * cm.os, xm.y * cm.os};
+    }
+}
+
+// ----------------------------------------------------------- FP64 columns, compact
+// One lane per task, FP64, with short code: the level loop is unrolled by U
+// only, the next U levels' loads are issued before the current U levels are
+// eliminated, and the eliminated values and reciprocal pivots go to the
+// workspace laid out [quantity][level][task] (consecutive tasks contiguous).
+// Tasks [0, ny/2]: the packed kx = 0 row -- the lane forms A (modes
+// (0, ky)) and B (modes (nx/2, ky)) from Z_ky and Z_{-ky}, runs both
+// eliminations interleaved and repacks Z'_ky = A' + i B',
+// Z'_{-ky} = conj A' + i conj B'.  Task 0's A is the singular mean column,
+// from the FP64 level sums.  Tasks beyond: near-singular columns kx >= 1.
+// The calling block stages the FP64 tables in LDS first: f (nz + 1 values),
+// D, rs, os and the level sums sS (nz values each).  t is the task index
+// (tasks >= ntask return at once).
+template <typename T, int U>
+__device__ void special_seq_tile(cx_t<T> *__restrict__ spec, int nx, int ny, int nz, int adjoint,
+                                 const int *__restrict__ mlist, int nmask, double *__restrict__ ws,
+                                 const double *__restrict__ ax, const double *__restrict__ ay,
+                                 const double *f, const double *D, const double *rs,
+                                 const double *os, const double *sS, int t)
+{
+    const int L = nx / 2;
+    const int npair = ny / 2 + 1;
+    const int ntask = npair + nmask;
+    if (t >= ntask) return;
+    const size_t st = (size_t)ntask, lz = (size_t)nz * st;
+    double *yar = ws + 0 * lz + t, *yai = ws + 1 * lz + t;
+    double *ybr = ws + 2 * lz + t, *ybi = ws + 3 * lz + t;
+    double *ga = ws + 4 * lz + t, *gb = ws + 5 * lz + t;
+    const size_t lvl = (size_t)L * ny;
+    const bool pair = t < npair;
+    int i0, i1; // spectrum indices within a level: Z_ky, Z_{-ky} (pair) or the column
+    double sa, sb = 1.0;
+    if (pair) {
+        i0 = t;
+        i1 = (ny - t) % ny;
+        sa = ay[t];
+        sb = ax[L] + ay[t];
+    } else {
+        const int c = mlist[t - npair];
+        const int kx = c / ny, ky = c - kx * ny;
+        i0 = i1 = c;
+        sa = ax[kx] + ay[ky];
+    }
+    const bool mean = pair && t == 0;
+    if (mean) sa = 1.0; // not used: the mean column is not eliminated
+
+    // ---- forward elimination, A and B interleaved
+    double qa = 0.0, gpa = 0.0, yra = 0.0, yia = 0.0;
+    double qb = 0.0, gpb = 0.0, yrb = 0.0, yib = 0.0;
+    cx_t<T> z0[U], z1[U];
+    auto fetch = [&](int k0, cx_t<T> *a, cx_t<T> *b) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u < nz ? k0 + u : nz - 1;
+            a[u] = spec[(size_t)k * lvl + i0];
+            b[u] = spec[(size_t)k * lvl + i1];
+        }
+    };
+    fetch(0, z0, z1);
+    for (int k0 = 0; k0 < nz; k0 += U) {
+        cx_t<T> n0[U], n1[U];
+        fetch(k0 + U < nz ? k0 + U : k0, n0, n1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u;
+            if (k < nz) {
+                double ar, ai, br = 0.0, bi = 0.0;
+                if (pair) { // A = (Z + conj Zm)/2, B = (Z - conj Zm)/(2i)
+                    const double zr = z0[u].x, zi = z0[u].y, mr = z1[u].x, mi = -(double)z1[u].y;
+                    ar = 0.5 * (zr + mr);
+                    ai = 0.5 * (zi + mi);
+                    br = 0.5 * (zi - mi);
+                    bi = -0.5 * (zr - mr);
+                } else {
+                    ar = z0[u].x;
+                    ai = z0[u].y;
+                }
+                const double fp = f[k], fn = f[k + 1], r = rs[k];
+                const double ea = sa * D[k] + fp * qa;
+                const double gi_a = 1.0 / (ea + fn);
+                const double ca = fp * gpa;
+                yra = r * ar + ca * yra;
+                yia = r * ai + ca * yia;
+                yar[k * st] = yra;
+                yai[k * st] = yia;
+                ga[k * st] = gi_a;
+                qa = ea * gi_a;
+                gpa = gi_a;
+                if (pair) {
+                    const double eb = sb * D[k] + fp * qb;
+                    const double gi_b = 1.0 / (eb + fn);
+                    const double cb = fp * gpb;
+                    yrb = r * br + cb * yrb;
+                    yib = r * bi + cb * yib;
+                    ybr[k * st] = yrb;
+                    ybi[k * st] = yib;
+                    gb[k * st] = gi_b;
+                    qb = eb * gi_b;
+                    gpb = gi_b;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            z0[u] = n0[u];
+            z1[u] = n1[u];
+        }
+    }
+
+    // ---- the mean column: level means minus mu (forward: D-weighted mean;
+    // adjoint: plain mean), V x = c by flux prefix sums, then the gauge
+    // (forward: zero plain mean; adjoint: sum_k D_k x_k = 0).  Stored into the
+    // A workspace as final values.
+    if (mean) {
+        const double on = 1.0 / ((double)nx * (double)ny);
+        double num = 0.0, den = 0.0, tot = 0.0;
+        for (int k = 0; k < nz; ++k) {
+            num += D[k] * sS[k];
+            den += D[k];
+            tot += sS[k];
+        }
+        const double mu = adjoint ? tot * on / (double)nz : num * on / den;
+        double F = 0.0, x = 0.0, acc = 0.0, wsum = 0.0;
+        for (int k = 0; k < nz; ++k) {
+            if (k > 0) {
+                const double c = sS[k - 1] * on - mu;
+                F += adjoint ? c : D[k - 1] * c;
+                x += F / f[k];
+            }
+            yar[k * st] = x;
+            const double wk = adjoint ? D[k] : 1.0;
+            acc += wk * x;
+            wsum += wk;
+        }
+        const double shift = acc / wsum;
+        for (int k = 0; k < nz; ++k) {
+            yar[k * st] -= shift;
+            yai[k * st] = 0.0;
+        }
+    }
+
+    // ---- backward substitution (loads of the next U levels prefetched)
+    double xra = 0.0, xia = 0.0, xrb = 0.0, xib = 0.0;
+    for (int k1 = nz - 1; k1 >= 0; k1 -= U) {
+        double lyar[U], lyai[U], lga[U], lybr[U], lybi[U], lgb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k1 - u >= 0 ? k1 - u : 0;
+            lyar[u] = yar[k * st];
+            lyai[u] = yai[k * st];
+            lga[u] = ga[k * st];
+            if (pair) {
+                lybr[u] = ybr[k * st];
+                lybi[u] = ybi[k * st];
+                lgb[u] = gb[k * st];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k1 - u;
+            if (k >= 0) {
+                const double fn = f[k + 1], o = os[k];
+                if (mean) {
+                    xra = lyar[u];
+                    xia = 0.0;
+                } else {
+                    xra = lga[u] * (lyar[u] + fn * xra);
+                    xia = lga[u] * (lyai[u] + fn * xia);
+                }
+                if (pair) {
+                    xrb = lgb[u] * (lybr[u] + fn * xrb);
+                    xib = lgb[u] * (lybi[u] + fn * xib);
+                    const double Ar = o * xra, Ai = o * xia, Br = o * xrb, Bi = o * xib;
+                    spec[(size_t)k * lvl + i0] = cx_t<T>{(T)(Ar - Bi), (T)(Ai + Br)};
+                    if (i1 != i0) spec[(size_t)k * lvl + i1] = cx_t<T>{(T)(Ar + Bi), (T)(Br - Ai)};
+                } else {
+                    spec[(size_t)k * lvl + i0] = cx_t<T>{(T)(o * xra), (T)(o * xia)};
+                }
+            }
+        }
+    }
+}
+
+} // namespace ps

@@ -13,6 +13,7 @@
 // in dominance-excess form (pivot u = e + f_next with
 // e_i = s D_i + f_prev e_{i-1}/u_{i-1}, built from positive terms only).
 #include "ps_internal.h"
+#include "ps_tiles.h"
 #include "../../include/pressure_solve.h"
 
 namespace ps {
@@ -371,32 +372,9 @@ __global__ __launch_bounds__(256) void k_columns2(cx_t<T> *__restrict__ spec, in
     }
 }
 
-// ----------------------------------------------------------- uniform-half sweep
-// Reciprocal of a pivot u > 0 in the normal range.  FP32: the hardware
-// reciprocal refined by one Newton step (within one ulp of the IEEE
-// quotient); FP64: IEEE division.
-__device__ __forceinline__ float pivot_rcp(float u)
-{
-    const float r = __builtin_amdgcn_rcpf(u);
-    const float e = __builtin_fmaf(-u, r, 1.0f);
-    return __builtin_fmaf(r, e, r);
-}
-__device__ __forceinline__ double pivot_rcp(double u) { return 1.0 / u; }
-
-// Per-slot coefficients in each half's elimination order (built by the plan):
-// slot [half][i], i in [0, NH), for level k = i (low half) or k = nz - 1 - i
-// (high half), with the half's real levels in the LAST n slots and dummy
-// slots in front (f_prev = f_next = 0, D = 1, rs = 0, off -> middle row).  A
-// dummy row never influences a real one: the first real row of each half is
-// a boundary row (f_prev = 0).  Slot [2 NH] is the middle row m.  rs/os are
-// the forward or adjoint right-hand-side and output factors.  `off` is the
-// byte offset of the level in the spectrum.  Wave-uniform, so they are read
-// through the scalar cache.
-// Two waves per group of 64 columns: the low-half wave eliminates levels
-// 0..m-1 and the high-half wave levels nz-1..m+1, one column per lane
-// (complex values, real pivots); they exchange their messages to the middle
-// row through LDS.  KEEPG keeps the reciprocal pivots in registers instead
-// of recomputing them in the backward pass.
+// ----------------------------------------------------------- tile kernels
+// The uniform-half column sweep and the compact FP64 column tasks (the
+// device code is in ps_tiles.h, shared with the batched persistent kernel).
 template <typename T, int NH, bool KEEPG>
 __global__ __launch_bounds__(256) void k_columns3(cx_t<T> *__restrict__ spec, int L, int ny,
                                                   const T *__restrict__ ax,
@@ -404,416 +382,13 @@ __global__ __launch_bounds__(256) void k_columns3(cx_t<T> *__restrict__ spec, in
                                                   const LevelCoef<T> *__restrict__ coef,
                                                   const int *__restrict__ maskcnt)
 {
-    using C = cx_t<T>;
-    constexpr int CH = NH < 8 ? NH : 8;
-    constexpr int NB = (NH + CH - 1) / CH;
     __shared__ T xa[2][2][64];
-    __shared__ C xb[2][2][64];
-    const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int pair = w >> 1, half = w & 1;
-    const long ncol = (long)L * ny;
-    const long col = (long)ny + ((long)blockIdx.x * 2 + pair) * 64 + lane;
-    const bool valid = col < ncol;
-    const int kx = valid ? (int)(col / ny) : 1;
-    const int ky = valid ? (int)(col - (long)kx * ny) : 0;
-    const T s = ax[kx] + ay[ky];
-    bool store = valid;
-    if (maskcnt && valid) {
-        const int d = min(ky, ny - ky);
-        if (d < maskcnt[kx]) store = false;
-    }
-    char *base = reinterpret_cast<char *>(spec + (valid ? col : 0));
-    const LevelCoef<T> *ct = coef + half * NH;
-
-    C v[NH];
-#pragma unroll
-    for (int i = 0; i < NH; ++i) {
-        const C x = *reinterpret_cast<const C *>(base + (ct[i].off < 0 ? coef[2 * NH].off : ct[i].off));
-        v[i] = C{x.x * ct[i].rs, x.y * ct[i].rs};
-    }
-    const LevelCoef<T> cm = coef[2 * NH];
-    C rmv = *reinterpret_cast<const C *>(base + cm.off);
-    rmv = C{rmv.x * cm.rs, rmv.y * cm.rs};
-
-    T qck[KEEPG ? 1 : NB];
-    T gk[KEEPG ? NH : 1];
-    T q = T(0), g = T(0);
-    C y = C{T(0), T(0)};
-#pragma unroll
-    for (int i = 0; i < NH; ++i) {
-        if (!KEEPG && i % CH == 0) qck[i / CH] = q;
-        const T e = s * ct[i].D + ct[i].fp * q;
-        const T gi = pivot_rcp(e + ct[i].fn);
-        const T c = ct[i].fp * g;
-        y = C{v[i].x + c * y.x, v[i].y + c * y.y};
-        v[i] = y;
-        q = e * gi;
-        g = gi;
-        if (KEEPG) gk[i] = gi;
-    }
-    const T fl = ct[NH - 1].fn;
-    xa[pair][half][lane] = fl * q;
-    xb[pair][half][lane] = C{(fl * g) * y.x, (fl * g) * y.y};
-    __syncthreads();
-    const T la = xa[pair][0][lane], ha = xa[pair][1][lane];
-    const C lb = xb[pair][0][lane], hb = xb[pair][1][lane];
-    const T den = (s * cm.D + la) + ha;
-    const C xm = C{((rmv.x + lb.x) + hb.x) / den, ((rmv.y + lb.y) + hb.y) / den};
-
-    C xn = xm;
-    if constexpr (KEEPG) {
-#pragma unroll
-        for (int i = NH - 1; i >= 0; --i) {
-            const T fn = ct[i].fn;
-            xn = C{gk[i] * (v[i].x + fn * xn.x), gk[i] * (v[i].y + fn * xn.y)};
-            v[i] = xn;
-        }
-    } else {
-#pragma unroll
-        for (int bb = NB - 1; bb >= 0; --bb) {
-            T gb[CH];
-            T qq = qck[bb];
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const int i = bb * CH + c;
-                const T e = s * ct[i].D + ct[i].fp * qq;
-                const T gi = pivot_rcp(e + ct[i].fn);
-                gb[c] = gi;
-                qq = e * gi;
-            }
-#pragma unroll
-            for (int c = CH - 1; c >= 0; --c) {
-                const int i = bb * CH + c;
-                const T fn = ct[i].fn;
-                xn = C{gb[c] * (v[i].x + fn * xn.x), gb[c] * (v[i].y + fn * xn.y)};
-                v[i] = xn;
-            }
-        }
-    }
-    if (store) {
-#pragma unroll
-        for (int i = 0; i < NH; ++i) {
-            const long long off = ct[i].off;
-            if (off >= 0)
-                *reinterpret_cast<C *>(base + off) = C{v[i].x * ct[i].os, v[i].y * ct[i].os};
-        }
-        if (half) *reinterpret_cast<C *>(base + cm.off) = C{xm.x * cm.os, xm.y * cm.os};
-    }
+    __shared__ cx_t<T> xb[2][2][64];
+    columns3_tile<T, NH, KEEPG>(spec, L, ny, ax, ay, coef, maskcnt, blockIdx.x, xa, xb);
 }
 
-// ----------------------------------------------------------- FP64 columns
-// One thread per task, FP64 throughout, column temporaries in the
-// workspace laid out [quantity][level][task] (consecutive tasks contiguous).
-__device__ void seq_column(int nz, double s, const double *f, const double *D, double *yr,
-                           double *yi, double *gg, size_t st)
-{
-    double q = 0.0, g = 0.0, pr = 0.0, pi = 0.0;
-    for (int k = 0; k < nz; ++k) {
-        const double fp = f[k], fn = f[k + 1];
-        const double e = s * D[k] + fp * q;
-        const double gi = 1.0 / (e + fn);
-        const double r = yr[k * st] + (fp * g) * pr;
-        const double i = yi[k * st] + (fp * g) * pi;
-        yr[k * st] = r;
-        yi[k * st] = i;
-        gg[k * st] = gi;
-        q = e * gi;
-        g = gi;
-        pr = r;
-        pi = i;
-    }
-    double xr = 0.0, xi = 0.0;
-    for (int k = nz - 1; k >= 0; --k) {
-        const double fn = f[k + 1];
-        xr = gg[k * st] * (yr[k * st] + fn * xr);
-        xi = gg[k * st] * (yi[k * st] + fn * xi);
-        yr[k * st] = xr;
-        yi[k * st] = xi;
-    }
-}
-
-// Tasks t in [0, ny/2]: the packed kx = 0 row.  Slot (kx=0, ky) holds
-// Z = A + i B with A = DFT_y of the x-DC coefficients (modes (0, ky)) and
-// B = DFT_y of the x-Nyquist coefficients (modes (nx/2, ky)); both come from
-// real sequences, so A_ky = (Z_ky + conj Z_{-ky})/2 and
-// B_ky = (Z_ky - conj Z_{-ky})/(2i).  The task solves A and B for ky and
-// repacks ky and -ky.  Mode (0,0) is the singular mean column: it is taken
-// from the FP64 level sums S_k instead of the transform (see below).
-// Tasks t > ny/2: near-singular columns kx >= 1 from mlist, in FP64.
-template <typename T>
-__global__ __launch_bounds__(64) void k_special(cx_t<T> *__restrict__ spec, int nx, int ny, int nz,
-                                                int adjoint, const int *__restrict__ mlist,
-                                                int nmask, const double *__restrict__ S,
-                                                double *__restrict__ ws, const double *__restrict__ ax,
-                                                const double *__restrict__ ay,
-                                                const double *__restrict__ fg,
-                                                const double *__restrict__ Dg,
-                                                const double *__restrict__ rs,
-                                                const double *__restrict__ os)
-{
-    __shared__ double f[PS_MAX_NZ + 1], D[PS_MAX_NZ];
-    for (int t = threadIdx.x; t <= nz; t += blockDim.x) {
-        f[t] = fg[t];
-        if (t < nz) D[t] = Dg[t];
-    }
-    __syncthreads();
-    const int L = nx / 2;
-    const int npair = ny / 2 + 1;
-    const int ntask = npair + nmask;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ntask) return;
-    const size_t st = (size_t)ntask;
-    double *Ar = ws + (0 * (size_t)nz) * st + t, *Ai = ws + (1 * (size_t)nz) * st + t;
-    double *Br = ws + (2 * (size_t)nz) * st + t, *Bi = ws + (3 * (size_t)nz) * st + t;
-    double *G = ws + (4 * (size_t)nz) * st + t;
-    const size_t lvl = (size_t)L * ny;
-    const double on = 1.0 / ((double)nx * (double)ny);
-
-    if (t < npair) {
-        const int ky = t, kp = (ny - t) % ny;
-        for (int k = 0; k < nz; ++k) {
-            const cx_t<T> z = spec[(size_t)k * lvl + ky];
-            const cx_t<T> w = spec[(size_t)k * lvl + kp];
-            const double zr = z.x, zi = z.y, wr = w.x, wi = -(double)w.y; // w = conj Z_{-ky}
-            Ar[k * st] = rs[k] * 0.5 * (zr + wr);
-            Ai[k * st] = rs[k] * 0.5 * (zi + wi);
-            Br[k * st] = rs[k] * 0.5 * (zi - wi);
-            Bi[k * st] = rs[k] * -0.5 * (zr - wr);
-        }
-        if (ky == 0) {
-            // Mean column from the FP64 level sums.  Forward: level means of
-            // b minus mu (the D-weighted mean); V x = c by flux prefix sums
-            // F_{k+1/2} = sum_{j<=k} D_j c_j, x_{k+1} = x_k + F/f_{k+1/2};
-            // gauge: zero mean over levels.  Adjoint: level means of w minus
-            // the plain mean; V z = c / D; gauge sum D z = 0; output D z.
-            double num = 0.0, den = 0.0, tot = 0.0;
-            for (int k = 0; k < nz; ++k) {
-                num += D[k] * S[k];
-                den += D[k];
-                tot += S[k];
-            }
-            const double mu = adjoint ? tot * on / (double)nz : num * on / den;
-            double F = 0.0, x = 0.0, acc = 0.0, wsum = 0.0;
-            Ar[0] = 0.0;
-            for (int k = 0; k + 1 < nz; ++k) {
-                const double c = S[k] * on - mu;
-                F += adjoint ? c : D[k] * c;
-                x += F / f[k + 1];
-                Ar[(k + 1) * st] = x;
-            }
-            for (int k = 0; k < nz; ++k) {
-                const double wk = adjoint ? D[k] : 1.0;
-                acc += wk * Ar[k * st];
-                wsum += wk;
-            }
-            const double shift = acc / wsum;
-            for (int k = 0; k < nz; ++k) {
-                Ar[k * st] -= shift;
-                Ai[k * st] = 0.0;
-            }
-        } else {
-            seq_column(nz, ay[ky], f, D, Ar, Ai, G, st);
-        }
-        seq_column(nz, ax[L] + ay[ky], f, D, Br, Bi, G, st);
-        for (int k = 0; k < nz; ++k) {
-            const double o = os ? os[k] : 1.0;
-            const double ar = o * Ar[k * st], ai = o * Ai[k * st];
-            const double br = o * Br[k * st], bi = o * Bi[k * st];
-            spec[(size_t)k * lvl + ky] = cx_t<T>{(T)(ar - bi), (T)(ai + br)};
-            if (kp != ky) spec[(size_t)k * lvl + kp] = cx_t<T>{(T)(ar + bi), (T)(br - ai)};
-        }
-    } else {
-        const int c = mlist[t - npair];
-        const int kx = c / ny, ky = c - kx * ny;
-        for (int k = 0; k < nz; ++k) {
-            const cx_t<T> z = spec[(size_t)k * lvl + c];
-            Ar[k * st] = rs[k] * (double)z.x;
-            Ai[k * st] = rs[k] * (double)z.y;
-        }
-        seq_column(nz, ax[kx] + ay[ky], f, D, Ar, Ai, G, st);
-        for (int k = 0; k < nz; ++k) {
-            const double o = os ? os[k] : 1.0;
-            spec[(size_t)k * lvl + c] = cx_t<T>{(T)(o * Ar[k * st]), (T)(o * Ai[k * st])};
-        }
-    }
-}
-
-// ----------------------------------------------------------- FP64 columns, parallel
-// The same FP64 work as k_special, with the register-resident two-ended
-// sweep (4 lanes per column).  Waves [0, npw): the packed kx = 0 row, eight
-// ky values per wave; lane = half*32 + 4*j + 2*which + comp, where which = 0
-// solves A (modes (0, ky), s = ay[ky]) and which = 1 solves B (modes
-// (nx/2, ky), s = ax[nx/2] + ay[ky]).  Each lane forms its component of A or
-// B from Z_ky and Z_{-ky}; after the solve the (A, re) and (A, im) lanes
-// repack Z'_ky = A' + i B' and Z'_{-ky} = conj A' + i conj B' with one
-// shuffle.  The (A, ky = 0) lanes hold the singular mean column, computed
-// from the FP64 level sums by flux prefix sums.  Waves [npw, npw + nmw):
-// near-singular columns kx >= 1 from mlist, 16 per wave.
-template <typename T, int NH>
-__global__ __launch_bounds__(256) void k_special_par(
-    cx_t<T> *__restrict__ spec, int nx, int ny, int nz, int adjoint, const int *__restrict__ mlist,
-    int nmask, const double *__restrict__ S, const double *__restrict__ ax,
-    const double *__restrict__ ay, const double *__restrict__ fg, const double *__restrict__ Dg,
-    const double *__restrict__ rsg, const double *__restrict__ osg)
-{
-    constexpr int CH = NH < 8 ? NH : 8;
-    __shared__ double sf[PS_MAX_NZ + 1], sD[PS_MAX_NZ], srs[PS_MAX_NZ], sos[PS_MAX_NZ],
-        sS[PS_MAX_NZ];
-    for (int t = threadIdx.x; t <= nz; t += blockDim.x) {
-        sf[t] = fg[t];
-        if (t < nz) {
-            sD[t] = Dg[t];
-            srs[t] = rsg[t];
-            sos[t] = osg ? osg[t] : 1.0;
-            sS[t] = S[t];
-        }
-    }
-    __syncthreads();
-    const int L = nx / 2;
-    const int npair = ny / 2 + 1;
-    const int npw = (npair + 7) / 8;
-    const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int half = lane >> 5, comp = lane & 1;
-    const size_t ls = (size_t)2 * L * ny; // level stride in T units
-    const T *sp = reinterpret_cast<const T *>(spec);
-    T *dp = reinterpret_cast<T *>(spec);
-    const int m = nz >> 1;
-    const int n = half ? nz - 1 - m : m;
-
-    bool pair = wave < npw;
-    int ky = 0, kp = 0, which = 0, col = 0;
-    bool valid;
-    double s;
-    if (pair) {
-        const int j = (lane & 31) >> 2;
-        which = (lane >> 1) & 1;
-        ky = wave * 8 + j;
-        valid = ky < npair;
-        if (!valid) ky = 0;
-        kp = (ny - ky) % ny;
-        s = which ? ax[L] + ay[ky] : ay[ky];
-    } else {
-        const int c = (wave - npw) * 16 + ((lane & 31) >> 1);
-        valid = c < nmask;
-        col = valid ? mlist[c] : ny; // column kx >= 1
-        const int kx = col / ny, kyy = col - kx * ny;
-        s = ax[kx] + ay[kyy];
-    }
-    const bool mean = pair && which == 0 && ky == 0;
-    if (!(s > 0.0)) s = 1.0; // the mean column is not swept
-
-    // value of this lane's component at level k
-    auto load = [&](int k) -> double {
-        if (!valid) return 0.0;
-        const size_t b = (size_t)k * ls;
-        if (!pair) return (double)sp[b + 2 * (size_t)col + comp];
-        const int c1 = which ? 1 - comp : comp;
-        const double zk = (double)sp[b + 2 * (size_t)ky + c1];
-        const double zm = (double)sp[b + 2 * (size_t)kp + c1];
-        // A.re = (zk.re+zm.re)/2, A.im = (zk.im-zm.im)/2,
-        // B.re = (zk.im+zm.im)/2, B.im = (zm.re-zk.re)/2
-        if (!which) return comp ? 0.5 * (zk - zm) : 0.5 * (zk + zm);
-        return comp ? 0.5 * (zm - zk) : 0.5 * (zk + zm);
-    };
-    double v[NH];
-#pragma unroll
-    for (int i = 0; i < NH; ++i)
-        if (i < n) {
-            const int k = half ? nz - 1 - i : i;
-            v[i] = load(k) * srs[k];
-        }
-    const double rm = load(m) * srs[m];
-    double xm = twisted_solve<double, NH, CH>(v, n, half, m, nz, s, sf, sD, rm);
-
-    if (mean) {
-        // Forward: c_k = level mean of b - mu (D-weighted mean); V x = c by
-        // F_{k+1/2} = sum_{j<=k} D_j c_j, x_{k+1} = x_k + F/f_{k+1/2}; gauge:
-        // zero plain mean.  Adjoint: c_k = level mean of w - plain mean;
-        // V z = c / D; gauge sum_k D_k z_k = 0.  Imaginary part zero.
-        const double on = 1.0 / ((double)nx * (double)ny);
-        double num = 0.0, den = 0.0, tot = 0.0;
-        for (int k = 0; k < nz; ++k) {
-            num += sD[k] * sS[k];
-            den += sD[k];
-            tot += sS[k];
-        }
-        const double mu = adjoint ? tot * on / (double)nz : num * on / den;
-        double F = 0.0, x = 0.0, acc = 0.0, wsum = 0.0;
-        for (int k = 0; k < nz; ++k) {
-            if (k > 0) {
-                const double c = sS[k - 1] * on - mu;
-                F += adjoint ? c : sD[k - 1] * c;
-                x += F / sf[k];
-            }
-            const double wk = adjoint ? sD[k] : 1.0;
-            acc += wk * x;
-            wsum += wk;
-        }
-        const double shift = acc / wsum;
-        F = 0.0;
-        x = 0.0;
-        for (int k = 0; k < nz; ++k) {
-            if (k > 0) {
-                const double c = sS[k - 1] * on - mu;
-                F += adjoint ? c : sD[k - 1] * c;
-                x += F / sf[k];
-            }
-            const double val = comp ? 0.0 : x - shift;
-#pragma unroll
-            for (int i = 0; i < NH; ++i) {
-                const int ki = half ? nz - 1 - i : i;
-                if (i < n && ki == k) v[i] = val;
-            }
-            if (k == m) xm = val;
-        }
-    }
-
-    if (pair) {
-        // (A, re) lanes: Z'_ky.re = A'.re - B'.im, Z'_-ky.re = A'.re + B'.im
-        // (A, im) lanes: Z'_ky.im = A'.im + B'.re, Z'_-ky.im = B'.re - A'.im
-        // the partner component sits in lane ^ 3.
-        // every lane of the wave takes part in each shuffle; `st` gates the store
-        auto emit = [&](int k, double x, bool st) {
-            const double o = x * sos[k];
-            const double other = __shfl_xor(o, 3, 64);
-            if (st && valid && which == 0) {
-                const size_t b = (size_t)k * ls;
-                const double zy = comp ? o + other : o - other;
-                const double zp = comp ? other - o : o + other;
-                dp[b + 2 * (size_t)ky + comp] = (T)zy;
-                if (kp != ky) dp[b + 2 * (size_t)kp + comp] = (T)zp;
-            }
-        };
-#pragma unroll
-        for (int i = 0; i < NH; ++i) {
-            const bool act = i < n;
-            const int k = act ? (half ? nz - 1 - i : i) : 0;
-            emit(k, act ? v[i] : 0.0, act);
-        }
-        emit(m, xm, half == 1); // the middle row is stored by the high half
-    } else if (valid) {
-#pragma unroll
-        for (int i = 0; i < NH; ++i)
-            if (i < n) {
-                const int k = half ? nz - 1 - i : i;
-                dp[(size_t)k * ls + 2 * (size_t)col + comp] = (T)(v[i] * sos[k]);
-            }
-        if (half) dp[(size_t)m * ls + 2 * (size_t)col + comp] = (T)(xm * sos[m]);
-    }
-}
-
-// ----------------------------------------------------------- FP64 columns, compact
-// One lane per task, FP64, with short code: the level loop is unrolled by U
-// only, the next U levels' loads are issued before the current U levels are
-// eliminated, and the eliminated values and reciprocal pivots go to the
-// workspace laid out [quantity][level][task] (consecutive tasks contiguous).
-// Tasks [0, ny/2]: the packed kx = 0 row -- the lane forms A (modes
-// (0, ky)) and B (modes (nx/2, ky)) from Z_ky and Z_{-ky}, runs both
-// eliminations interleaved and repacks Z'_ky = A' + i B',
-// Z'_{-ky} = conj A' + i conj B'.  Task 0's A is the singular mean column,
-// from the FP64 level sums.  Tasks beyond: near-singular columns kx >= 1.
+// These few waves carry long dependent chains and usually share their SIMDs
+// with the main column kernel: they are issued first (wave priority).
 template <typename T, int U>
 __global__ __launch_bounds__(64) void k_special_seq(
     cx_t<T> *__restrict__ spec, int nx, int ny, int nz, int adjoint, const int *__restrict__ mlist,
@@ -821,8 +396,6 @@ __global__ __launch_bounds__(64) void k_special_seq(
     const double *__restrict__ ax, const double *__restrict__ ay, const double *__restrict__ fg,
     const double *__restrict__ Dg, const double *__restrict__ rsg, const double *__restrict__ osg)
 {
-    // These few waves carry long dependent chains and usually share their
-    // SIMDs with the main column kernel: issue them first.
     __builtin_amdgcn_s_setprio(3);
     __shared__ double f[PS_MAX_NZ + 1], D[PS_MAX_NZ], rs[PS_MAX_NZ], os[PS_MAX_NZ],
         sS[PS_MAX_NZ];
@@ -836,168 +409,8 @@ __global__ __launch_bounds__(64) void k_special_seq(
         }
     }
     __syncthreads();
-    const int L = nx / 2;
-    const int npair = ny / 2 + 1;
-    const int ntask = npair + nmask;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ntask) return;
-    const size_t st = (size_t)ntask, lz = (size_t)nz * st;
-    double *yar = ws + 0 * lz + t, *yai = ws + 1 * lz + t;
-    double *ybr = ws + 2 * lz + t, *ybi = ws + 3 * lz + t;
-    double *ga = ws + 4 * lz + t, *gb = ws + 5 * lz + t;
-    const size_t lvl = (size_t)L * ny;
-    const bool pair = t < npair;
-    int i0, i1; // spectrum indices within a level: Z_ky, Z_{-ky} (pair) or the column
-    double sa, sb = 1.0;
-    if (pair) {
-        i0 = t;
-        i1 = (ny - t) % ny;
-        sa = ay[t];
-        sb = ax[L] + ay[t];
-    } else {
-        const int c = mlist[t - npair];
-        const int kx = c / ny, ky = c - kx * ny;
-        i0 = i1 = c;
-        sa = ax[kx] + ay[ky];
-    }
-    const bool mean = pair && t == 0;
-    if (mean) sa = 1.0; // not used: the mean column is not eliminated
-
-    // ---- forward elimination, A and B interleaved
-    double qa = 0.0, gpa = 0.0, yra = 0.0, yia = 0.0;
-    double qb = 0.0, gpb = 0.0, yrb = 0.0, yib = 0.0;
-    cx_t<T> z0[U], z1[U];
-    auto fetch = [&](int k0, cx_t<T> *a, cx_t<T> *b) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = k0 + u < nz ? k0 + u : nz - 1;
-            a[u] = spec[(size_t)k * lvl + i0];
-            b[u] = spec[(size_t)k * lvl + i1];
-        }
-    };
-    fetch(0, z0, z1);
-    for (int k0 = 0; k0 < nz; k0 += U) {
-        cx_t<T> n0[U], n1[U];
-        fetch(k0 + U < nz ? k0 + U : k0, n0, n1);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = k0 + u;
-            if (k < nz) {
-                double ar, ai, br = 0.0, bi = 0.0;
-                if (pair) { // A = (Z + conj Zm)/2, B = (Z - conj Zm)/(2i)
-                    const double zr = z0[u].x, zi = z0[u].y, mr = z1[u].x, mi = -(double)z1[u].y;
-                    ar = 0.5 * (zr + mr);
-                    ai = 0.5 * (zi + mi);
-                    br = 0.5 * (zi - mi);
-                    bi = -0.5 * (zr - mr);
-                } else {
-                    ar = z0[u].x;
-                    ai = z0[u].y;
-                }
-                const double fp = f[k], fn = f[k + 1], r = rs[k];
-                const double ea = sa * D[k] + fp * qa;
-                const double gi_a = 1.0 / (ea + fn);
-                const double ca = fp * gpa;
-                yra = r * ar + ca * yra;
-                yia = r * ai + ca * yia;
-                yar[k * st] = yra;
-                yai[k * st] = yia;
-                ga[k * st] = gi_a;
-                qa = ea * gi_a;
-                gpa = gi_a;
-                if (pair) {
-                    const double eb = sb * D[k] + fp * qb;
-                    const double gi_b = 1.0 / (eb + fn);
-                    const double cb = fp * gpb;
-                    yrb = r * br + cb * yrb;
-                    yib = r * bi + cb * yib;
-                    ybr[k * st] = yrb;
-                    ybi[k * st] = yib;
-                    gb[k * st] = gi_b;
-                    qb = eb * gi_b;
-                    gpb = gi_b;
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            z0[u] = n0[u];
-            z1[u] = n1[u];
-        }
-    }
-
-    // ---- the mean column: level means minus mu (forward: D-weighted mean;
-    // adjoint: plain mean), V x = c by flux prefix sums, then the gauge
-    // (forward: zero plain mean; adjoint: sum_k D_k x_k = 0).  Stored into the
-    // A workspace as final values.
-    if (mean) {
-        const double on = 1.0 / ((double)nx * (double)ny);
-        double num = 0.0, den = 0.0, tot = 0.0;
-        for (int k = 0; k < nz; ++k) {
-            num += D[k] * sS[k];
-            den += D[k];
-            tot += sS[k];
-        }
-        const double mu = adjoint ? tot * on / (double)nz : num * on / den;
-        double F = 0.0, x = 0.0, acc = 0.0, wsum = 0.0;
-        for (int k = 0; k < nz; ++k) {
-            if (k > 0) {
-                const double c = sS[k - 1] * on - mu;
-                F += adjoint ? c : D[k - 1] * c;
-                x += F / f[k];
-            }
-            yar[k * st] = x;
-            const double wk = adjoint ? D[k] : 1.0;
-            acc += wk * x;
-            wsum += wk;
-        }
-        const double shift = acc / wsum;
-        for (int k = 0; k < nz; ++k) {
-            yar[k * st] -= shift;
-            yai[k * st] = 0.0;
-        }
-    }
-
-    // ---- backward substitution (loads of the next U levels prefetched)
-    double xra = 0.0, xia = 0.0, xrb = 0.0, xib = 0.0;
-    for (int k1 = nz - 1; k1 >= 0; k1 -= U) {
-        double lyar[U], lyai[U], lga[U], lybr[U], lybi[U], lgb[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = k1 - u >= 0 ? k1 - u : 0;
-            lyar[u] = yar[k * st];
-            lyai[u] = yai[k * st];
-            lga[u] = ga[k * st];
-            if (pair) {
-                lybr[u] = ybr[k * st];
-                lybi[u] = ybi[k * st];
-                lgb[u] = gb[k * st];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = k1 - u;
-            if (k >= 0) {
-                const double fn = f[k + 1], o = os[k];
-                if (mean) {
-                    xra = lyar[u];
-                    xia = 0.0;
-                } else {
-                    xra = lga[u] * (lyar[u] + fn * xra);
-                    xia = lga[u] * (lyai[u] + fn * xia);
-                }
-                if (pair) {
-                    xrb = lgb[u] * (lybr[u] + fn * xrb);
-                    xib = lgb[u] * (lybi[u] + fn * xib);
-                    const double Ar = o * xra, Ai = o * xia, Br = o * xrb, Bi = o * xib;
-                    spec[(size_t)k * lvl + i0] = cx_t<T>{(T)(Ar - Bi), (T)(Ai + Br)};
-                    if (i1 != i0) spec[(size_t)k * lvl + i1] = cx_t<T>{(T)(Ar + Bi), (T)(Br - Ai)};
-                } else {
-                    spec[(size_t)k * lvl + i0] = cx_t<T>{(T)(o * xra), (T)(o * xia)};
-                }
-            }
-        }
-    }
+    special_seq_tile<T, U>(spec, nx, ny, nz, adjoint, mlist, nmask, ws, ax, ay, f, D, rs, os, sS,
+                           blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ----------------------------------------------------------- level sums
@@ -1147,49 +560,20 @@ template hipError_t launch_columns_impl<double>(cx_t<double> *, int, int, int, i
                                                 const int *, const Tables<double> &,
                                                 const Tables<double> *, hipStream_t, int);
 
-template <typename T, int NH>
-static hipError_t special_nh(cx_t<T> *spec, int nx, int ny, int nz, int adjoint, const int *mlist,
-                             int nmask, const double *S, const Tables<double> &tb64, hipStream_t st)
-{
-    const int npw = (ny / 2 + 1 + 7) / 8;
-    const int nmw = (nmask + 15) / 16;
-    const int grid = (npw + nmw + 3) / 4;
-    hipLaunchKernelGGL((k_special_par<T, NH>), dim3(grid), dim3(256), 0, st, spec, nx, ny, nz,
-                       adjoint, mlist, nmask, S, tb64.ax, tb64.ay, tb64.f, tb64.D,
-                       adjoint ? tb64.rs_adj : tb64.rs_fwd, adjoint ? tb64.os_adj : nullptr);
-    return hipGetLastError();
-}
-
 // FP64 columns: the packed kx = 0 row, the mean column and the near-singular
-// columns.  parallel != 0 selects the register-resident sweep (k_special_par);
-// otherwise one thread per task walks its column through the workspace.
+// columns, one lane per task (k_special_seq).
 template <typename T>
 hipError_t launch_special(cx_t<T> *spec, int nx, int ny, int nz, int adjoint, const int *mlist,
                           int nmask, const double *S, double *ws, const Tables<double> &tb64,
                           hipStream_t st, int parallel)
 {
-    if (parallel == 2) {
-        const int ntask = ny / 2 + 1 + nmask;
-        const int grid = (ntask + 63) / 64;
-        hipLaunchKernelGGL((k_special_seq<T, 16>), dim3(grid), dim3(64), 0, st, spec, nx, ny, nz,
-                           adjoint, mlist, nmask, S, ws, tb64.ax, tb64.ay, tb64.f, tb64.D,
-                           adjoint ? tb64.rs_adj : tb64.rs_fwd, adjoint ? tb64.os_adj : nullptr);
-        return hipGetLastError();
-    }
-    if (!parallel) {
-        const int ntask = ny / 2 + 1 + nmask;
-        const int grid = (ntask + 63) / 64;
-        hipLaunchKernelGGL(k_special<T>, dim3(grid), dim3(64), 0, st, spec, nx, ny, nz, adjoint,
-                           mlist, nmask, S, ws, tb64.ax, tb64.ay, tb64.f, tb64.D,
-                           adjoint ? tb64.rs_adj : tb64.rs_fwd, adjoint ? tb64.os_adj : nullptr);
-        return hipGetLastError();
-    }
-    const int need = nz / 2;
-#define PS_NH(N)                                                                                   \
-    if (need <= N) return special_nh<T, N>(spec, nx, ny, nz, adjoint, mlist, nmask, S, tb64, st);
-    PS_NH(1) PS_NH(2) PS_NH(4) PS_NH(8) PS_NH(16) PS_NH(32) PS_NH(64) PS_NH(128)
-#undef PS_NH
-    return hipErrorInvalidValue;
+    (void)parallel;
+    const int ntask = ny / 2 + 1 + nmask;
+    const int grid = (ntask + 63) / 64;
+    hipLaunchKernelGGL((k_special_seq<T, 16>), dim3(grid), dim3(64), 0, st, spec, nx, ny, nz,
+                       adjoint, mlist, nmask, S, ws, tb64.ax, tb64.ay, tb64.f, tb64.D,
+                       adjoint ? tb64.rs_adj : tb64.rs_fwd, adjoint ? tb64.os_adj : nullptr);
+    return hipGetLastError();
 }
 
 template hipError_t launch_special<float>(cx_t<float> *, int, int, int, int, const int *, int,
