@@ -168,9 +168,10 @@ def main():
             avg = tot / n
             per_solve_ms = tot / steps
             bpp = kernel_bytes_per_point(name, e, g.nx)
-            # fwd_x_residual runs once per solve; the y passes may be split in
-            # two launches (rows holding the FP64 columns first)
-            npass = 1 if name == "fwd_x_residual" else passes
+            # the x forward passes run once each per solve (the refinement's
+            # second one is fwd_x_residual); the y passes may be split in two
+            # launches (rows holding the FP64 columns first)
+            npass = 1 if name.startswith("fwd_x") else passes
             alg = bpp * N * npass  # algorithmic bytes per solve
             kt[name] = {"avg_ms": avg, "launches_per_solve": n / steps, "ms_per_solve": per_solve_ms,
                         "alg_bytes_per_solve": alg,

@@ -328,8 +328,10 @@ def tune_cache_load(path: str):
 
 
 class BatchPlan:
-    """Many independent solves of uneven sizes in one persistent launch
-    replayed from a captured hipGraph (the C ABI's ps_batch).
+    """Many independent solves of uneven sizes replayed from a captured
+    hipGraph (the C ABI's ps_batch).  Solving is currently switched off in
+    the library: solve() and autotune() raise PressureSolveError
+    (PS_EUNSUPPORTED); planning, info() and close() work.
 
     grids: sequence of workloads.Grid-like objects (nx, ny, nz, dx, dy, dz,
     rho); precision "fp32" or "fp64"."""

@@ -314,6 +314,8 @@ static void choose_geometry(ps_plan *p)
     // register-resident kernels where the length has one (variant 1)
     p->geom.variant_x = fast_length(p->L) ? 1 : 0;
     p->geom.variant_y = fast_length(p->ny) ? 1 : 0;
+    // the in-register refinement: refining uniform-half column kernel
+    if (p->precision == PS_FP32_R2) p->geom.columns = 3;
 }
 
 // Near-singular columns of the FP32 forms: lateral eigenvalue
@@ -472,7 +474,7 @@ extern "C" int ps_plan_query(const ps_plan *p, ps_plan_info *info)
     info->fft_variant_x = p->geom.variant_x;
     info->fft_variant_y = p->geom.variant_y;
     info->spectrum_elems = p->spec_elems();
-    info->column_variant = p->precision == PS_FP32_R2 ? 0 : p->geom.columns;
+    info->column_variant = p->geom.columns;
     return PS_OK;
 }
 
@@ -789,7 +791,11 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
         if (it != g_tune.end()) {
-            p->geom = it->second;
+            // only the tuned knobs: the tile shapes follow from the plan
+            p->geom.variant_x = it->second.variant_x && fast_length(p->L) ? 1 : 0;
+            p->geom.variant_y = it->second.variant_y && fast_length(p->ny) ? 1 : 0;
+            p->geom.columns = it->second.columns;
+            p->geom.special_side = it->second.special_side;
             return PS_OK;
         }
     }
@@ -825,7 +831,10 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
     if (fast_length(p->ny)) vy.push_back(1);
     pick(&FftGeom::variant_x, vx);
     pick(&FftGeom::variant_y, vy);
-    if (p->precision != PS_FP32_R2) pick(&FftGeom::columns, {0, 1, 2, 3, 4});
+    if (p->precision != PS_FP32_R2)
+        pick(&FftGeom::columns, {0, 1, 2, 3, 4});
+    else
+        pick(&FftGeom::columns, {0, 3});
     pick(&FftGeom::special_side, {0, 1});
     p->prof.on = prof;
     (void)hipStreamSynchronize(p->stream);

@@ -284,6 +284,162 @@ __device__ void columns3_tile(cx_t<T> *__restrict__ spec, int L, int ny, const T
     }
 }
 
+// ----------------------------------------------------------- refined sweep (FP32)
+// columns3_tile followed by one refinement: the residual rho = r - M x of
+// every column is formed in FP64 from the FP64 coefficient table (same slot
+// layout; s from the FP64 wavenumber tables) and the FP32 solution, rounded
+// to FP32, and M d = rho is solved with the same FP32 elimination; x + d is
+// stored.  The elimination of the correction has the same pivots, so only
+// the right-hand-side part of the middle-row message is exchanged again.
+// Pivots are recomputed from checkpoints in both backward passes.  xe is LDS
+// scratch of 2 * 2 * 64 complex values (the halves' last solution values,
+// which the middle row's residual needs).
+template <int NH>
+__device__ void columns3r_tile(float2 *__restrict__ spec, int L, int ny, const float *__restrict__ ax,
+                               const float *__restrict__ ay,
+                               const LevelCoef<float> *__restrict__ coef,
+                               const LevelCoef<double> *__restrict__ coef64,
+                               const double *__restrict__ ax64, const double *__restrict__ ay64,
+                               const int *__restrict__ maskcnt, long group, float (*xa)[2][64],
+                               float2 (*xb)[2][64], float2 (*xe)[2][64])
+{
+    using C = float2;
+    constexpr int CH = NH < 8 ? NH : 8;
+    constexpr int NB = (NH + CH - 1) / CH;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int pair = w >> 1, half = w & 1;
+    const long ncol = (long)L * ny;
+    const long col = (long)ny + (group * 2 + pair) * 64 + lane;
+    const bool valid = col < ncol;
+    const int kx = valid ? (int)(col / ny) : 1;
+    const int ky = valid ? (int)(col - (long)kx * ny) : 0;
+    const float s = ax[kx] + ay[ky];
+    const double s64 = ax64[kx] + ay64[ky];
+    bool store = valid;
+    if (maskcnt && valid) {
+        const int d = min(ky, ny - ky);
+        if (d < maskcnt[kx]) store = false;
+    }
+    char *base = reinterpret_cast<char *>(spec + (valid ? col : 0));
+    const LevelCoef<float> *ct = coef + half * NH;
+    const LevelCoef<double> *ct64 = coef64 + half * NH;
+    const LevelCoef<float> cm = coef[2 * NH];
+    const LevelCoef<double> cm64 = coef64[2 * NH];
+
+    C raw[NH], v[NH];
+#pragma unroll
+    for (int i = 0; i < NH; ++i) {
+        raw[i] = *reinterpret_cast<const C *>(base + (ct[i].off < 0 ? cm.off : ct[i].off));
+        v[i] = C{raw[i].x * ct[i].rs, raw[i].y * ct[i].rs};
+    }
+    const C rawm = *reinterpret_cast<const C *>(base + cm.off);
+
+    // ---- solve M x = r
+    float qck[NB];
+    float q = 0.f, g = 0.f;
+    C y = C{0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < NH; ++i) {
+        if (i % CH == 0) qck[i / CH] = q;
+        const float e = s * ct[i].D + ct[i].fp * q;
+        const float gi = pivot_rcp(e + ct[i].fn);
+        const float c = ct[i].fp * g;
+        y = C{v[i].x + c * y.x, v[i].y + c * y.y};
+        v[i] = y;
+        q = e * gi;
+        g = gi;
+    }
+    const float fl = ct[NH - 1].fn;
+    const float gl = fl * g;
+    xa[pair][half][lane] = fl * q;
+    xb[pair][half][lane] = C{gl * y.x, gl * y.y};
+    __syncthreads();
+    const float den = (s * cm.D + xa[pair][0][lane]) + xa[pair][1][lane];
+    C lb = xb[pair][0][lane], hb = xb[pair][1][lane];
+    C xm = C{((rawm.x * cm.rs + lb.x) + hb.x) / den, ((rawm.y * cm.rs + lb.y) + hb.y) / den};
+    auto backward = [&](C(&a)[NH], C xn) {
+#pragma unroll
+        for (int bb = NB - 1; bb >= 0; --bb) {
+            float gb[CH];
+            float qq = qck[bb];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int i = bb * CH + c;
+                const float e = s * ct[i].D + ct[i].fp * qq;
+                const float gi = pivot_rcp(e + ct[i].fn);
+                gb[c] = gi;
+                qq = e * gi;
+            }
+#pragma unroll
+            for (int c = CH - 1; c >= 0; --c) {
+                const int i = bb * CH + c;
+                const float fn = ct[i].fn;
+                xn = C{gb[c] * (a[i].x + fn * xn.x), gb[c] * (a[i].y + fn * xn.y)};
+                a[i] = xn;
+            }
+        }
+    };
+    backward(v, xm);
+
+    // ---- residual in FP64 (dummy slots give 0: rs = fp = fn = 0, x = 0)
+    xe[pair][half][lane] = v[NH - 1];
+    __syncthreads(); // also: every wave has read xb above
+    const C xlo = xe[pair][0][lane], xhi = xe[pair][1][lane];
+#pragma unroll
+    for (int i = 0; i < NH; ++i) {
+        const double fp = ct64[i].fp, fn = ct64[i].fn, r = ct64[i].rs;
+        const double diag = s64 * ct64[i].D + fp + fn;
+        const C xp = i > 0 ? v[i - 1] : C{0.f, 0.f};
+        const C xn = i + 1 < NH ? v[i + 1] : xm;
+        const double rr = r * (double)raw[i].x -
+                          (diag * (double)v[i].x - fp * (double)xp.x - fn * (double)xn.x);
+        const double ri = r * (double)raw[i].y -
+                          (diag * (double)v[i].y - fp * (double)xp.y - fn * (double)xn.y);
+        raw[i] = C{(float)rr, (float)ri};
+    }
+    const double diagm = s64 * cm64.D + cm64.fp + cm64.fn;
+    const C rhom = C{(float)(cm64.rs * (double)rawm.x -
+                             (diagm * (double)xm.x - cm64.fp * (double)xlo.x -
+                              cm64.fn * (double)xhi.x)),
+                     (float)(cm64.rs * (double)rawm.y -
+                             (diagm * (double)xm.y - cm64.fp * (double)xlo.y -
+                              cm64.fn * (double)xhi.y))};
+
+    // ---- correction: same elimination on the residual
+    q = 0.f;
+    g = 0.f;
+    y = C{0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < NH; ++i) {
+        const float e = s * ct[i].D + ct[i].fp * q;
+        const float gi = pivot_rcp(e + ct[i].fn);
+        const float c = ct[i].fp * g;
+        y = C{raw[i].x + c * y.x, raw[i].y + c * y.y};
+        raw[i] = y;
+        q = e * gi;
+        g = gi;
+    }
+    xb[pair][half][lane] = C{gl * y.x, gl * y.y};
+    __syncthreads();
+    lb = xb[pair][0][lane];
+    hb = xb[pair][1][lane];
+    const C dm = C{((rhom.x + lb.x) + hb.x) / den, ((rhom.y + lb.y) + hb.y) / den};
+    backward(raw, dm);
+    xm = C{xm.x + dm.x, xm.y + dm.y};
+
+    if (store) {
+#pragma unroll
+        for (int i = 0; i < NH; ++i) {
+            const long long off = ct[i].off;
+            if (off >= 0)
+                *reinterpret_cast<C *>(base + off) =
+                    C{(v[i].x + raw[i].x) * ct[i].os, (v[i].y + raw[i].y) * ct[i].os};
+        }
+        if (half) *reinterpret_cast<C *>(base + cm.off) = C{xm.x * cm.os, xm.y * cm.os};
+    }
+}
+
 // ----------------------------------------------------------- FP64 columns, compact
 // One lane per task, FP64, with short code: the level loop is unrolled by U
 // only, the next U levels' loads are issued before the current U levels are

@@ -387,6 +387,22 @@ __global__ __launch_bounds__(256) void k_columns3(cx_t<T> *__restrict__ spec, in
     columns3_tile<T, NH, KEEPG>(spec, L, ny, ax, ay, coef, maskcnt, blockIdx.x, xa, xb);
 }
 
+template <int NH>
+__global__ __launch_bounds__(256) void k_columns3r(float2 *__restrict__ spec, int L, int ny,
+                                                   const float *__restrict__ ax,
+                                                   const float *__restrict__ ay,
+                                                   const LevelCoef<float> *__restrict__ coef,
+                                                   const LevelCoef<double> *__restrict__ coef64,
+                                                   const double *__restrict__ ax64,
+                                                   const double *__restrict__ ay64,
+                                                   const int *__restrict__ maskcnt)
+{
+    __shared__ float xa[2][2][64];
+    __shared__ float2 xb[2][2][64], xe[2][2][64];
+    columns3r_tile<NH>(spec, L, ny, ax, ay, coef, coef64, ax64, ay64, maskcnt, blockIdx.x, xa, xb,
+                       xe);
+}
+
 // These few waves carry long dependent chains and usually share their SIMDs
 // with the main column kernel: they are issued first (wave priority).
 template <typename T, int U>
@@ -505,6 +521,33 @@ static hipError_t columns3_dispatch(cx_t<T> *spec, int L, int ny, int nz, int ad
     return hipErrorInvalidValue;
 }
 
+template <int NH>
+static hipError_t columns3r_nh(float2 *spec, int L, int ny, int adjoint, const int *maskcnt,
+                               const Tables<float> &tb, const Tables<double> &t64, hipStream_t st)
+{
+    const long ncols = (long)(L - 1) * ny;
+    if (ncols <= 0) return hipSuccess;
+    const long grid = (ncols + 127) / 128;
+    const auto *ct = reinterpret_cast<const LevelCoef<float> *>(adjoint ? tb.coef_adj : tb.coef_fwd);
+    const auto *c64 =
+        reinterpret_cast<const LevelCoef<double> *>(adjoint ? t64.coef_adj : t64.coef_fwd);
+    hipLaunchKernelGGL((k_columns3r<NH>), dim3((unsigned)grid), dim3(256), 0, st, spec, L, ny,
+                       tb.ax, tb.ay, ct, c64, t64.ax, t64.ay, maskcnt);
+    return hipGetLastError();
+}
+
+static hipError_t columns3r_dispatch(float2 *spec, int L, int ny, int nz, int adjoint,
+                                     const int *maskcnt, const Tables<float> &tb,
+                                     const Tables<double> &t64, hipStream_t st)
+{
+    const int need = nz / 2;
+#define PS_NH(N)                                                                                   \
+    if (need <= N) return columns3r_nh<N>(spec, L, ny, adjoint, maskcnt, tb, t64, st);
+    PS_NH(1) PS_NH(2) PS_NH(4) PS_NH(8) PS_NH(16) PS_NH(32) PS_NH(64) PS_NH(128)
+#undef PS_NH
+    return hipErrorInvalidValue;
+}
+
 template <typename T, bool REFINE>
 static hipError_t columns_dispatch(cx_t<T> *spec, int L, int ny, int nz, const T *rs, const T *os,
                                    const int *maskcnt, const Tables<T> &tb, const double *ax64,
@@ -525,7 +568,8 @@ static hipError_t columns_dispatch(cx_t<T> *spec, int L, int ny, int nz, const T
 // 1 = two lanes per column, pivots recomputed, 2 = two lanes, pivots kept,
 // 3 = halves in separate waves with scalar coefficient tables, pivots
 // recomputed, 4 = as 3 with pivots kept.
-// The in-register refinement always uses variant 0.
+// The in-register refinement (FP32 only) uses variant 0's refining kernel
+// for variants 0-2 and the refining uniform-half kernel for 3-4.
 template <typename T>
 hipError_t launch_columns_impl(cx_t<T> *spec, int nx, int ny, int nz, int adjoint, int refine,
                                const int *maskcnt, const Tables<T> &tb, const Tables<double> *t64,
@@ -535,6 +579,8 @@ hipError_t launch_columns_impl(cx_t<T> *spec, int nx, int ny, int nz, int adjoin
     const T *rs = adjoint ? tb.rs_adj : tb.rs_fwd;
     const T *os = adjoint ? tb.os_adj : nullptr;
     if constexpr (std::is_same<T, float>::value) {
+        if (refine && variant >= 3)
+            return columns3r_dispatch(spec, L, ny, nz, adjoint, maskcnt, tb, *t64, st);
         if (refine) {
             const double *rs64 = adjoint ? t64->rs_adj : t64->rs_fwd;
             return columns_dispatch<float, true>(spec, L, ny, nz, rs, os, maskcnt, tb, t64->ax,
