@@ -40,10 +40,14 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 #   inv_x with accumulation (refinement): + read p                 = 3e
 
 
-def kernel_bytes_per_point(name: str, e: int, nx: int) -> float:
+
+
+def kernel_bytes_per_point(name: str, e: int, nx: int, accumulate: bool = False) -> float:
     if name == "columns":
         return 2.0 * e * (1.0 - 2.0 / nx)
     if name == "fwd_x_residual":
+        return 3.0 * e
+    if name == "inv_x" and accumulate:
         return 3.0 * e
     return {"fwd_x": 2.0 * e, "fft_y_fwd": 2.0 * e, "fft_y_inv": 2.0 * e,
             "inv_x": 2.0 * e}.get(name, 0.0)
@@ -117,6 +121,11 @@ def main():
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the planner's kernel choice instead of timing the variants")
+    ap.add_argument("--tune-cache", default=None,
+                    help="tune-cache file: loaded first if it exists, written after tuning "
+                         "(so that profiled runs use the same kernels)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for scaling HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -125,11 +134,31 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2010_14132_amd import Plan
+    from paper_2010_14132_amd import Plan, binding
     from paper_2010_14132_amd import workloads as wl
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    copy_gbs = None
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        binding.tune_cache_load(args.tune_cache)
+        print("bench: loaded tune cache %s" % args.tune_cache, file=sys.stderr, flush=True)
+    if args.copy_calibration:
+        # a plain copy of known size: 1 GiB read + 1 GiB written per launch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 2 * src.numel() * 4 / (e0.elapsed_time(e1) / 5 * 1e-3) / 1e9
+        print("bench: 1 GiB device copy %.0f GB/s" % copy_gbs, file=sys.stderr, flush=True)
+        del src, dst
     prob = wl.precision_1024("f32")
     g = prob.grid
     N = g.points
@@ -162,17 +191,23 @@ def main():
         kern = plan.profile_report()
         plan.profile(False)
         e = 8 if form == "fp64" else 4
-        passes = 2 if form == "fp32_r1" else 1  # the refinement repeats the transform passes
+        info = plan.info()
+        # the refinement repeats the y, column and backward x passes under
+        # the same kernel names (its second x forward is fwd_x_residual)
+        r1 = form == "fp32_r1"
+        results[form]["chunks"] = info["chunks"]
         kt = {}
         for name, (tot, n) in kern.items():
             avg = tot / n
             per_solve_ms = tot / steps
-            bpp = kernel_bytes_per_point(name, e, g.nx)
-            # the x forward passes run once each per solve (the refinement's
-            # second one is fwd_x_residual); the y passes may be split in two
-            # launches (rows holding the FP64 columns first)
-            npass = 1 if name.startswith("fwd_x") else passes
-            alg = bpp * N * npass  # algorithmic bytes per solve
+            if r1 and name == "inv_x":
+                # one plain pass and one accumulating pass
+                alg = (kernel_bytes_per_point(name, e, g.nx)
+                       + kernel_bytes_per_point(name, e, g.nx, accumulate=True)) * N
+            else:
+                npass = 2 if (r1 and name in ("fft_y_fwd", "columns", "fft_y_inv")) else 1
+                alg = kernel_bytes_per_point(name, e, g.nx) * N * npass  # per solve
+            bpp = alg / N
             kt[name] = {"avg_ms": avg, "launches_per_solve": n / steps, "ms_per_solve": per_solve_ms,
                         "alg_bytes_per_solve": alg,
                         "gbs": (alg / (per_solve_ms * 1e-3) / 1e9) if bpp else None}
@@ -180,6 +215,8 @@ def main():
         if form == args.precision:
             kernels = kt
         plan.close()
+    if args.tune_cache:
+        binding.tune_cache_save(args.tune_cache)
     # dominant kernel: the largest share of the solve among the kernels that
     # run once per transform pass (one launch = one full pass over the data)
     single = {k: v for k, v in kernels.items()
@@ -227,6 +264,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
     }
+    if copy_gbs is not None:
+        line["device_copy_gbs"] = copy_gbs
     if "fp64" in results and args.precision != "fp64":
         line["speedup_vs_fp64"] = results["fp64"]["ms_per_solve"] / results[args.precision]["ms_per_solve"]
     if not args.no_cpu_baseline:

@@ -141,6 +141,7 @@ typedef struct ps_plan_info {
     int fft_variant_y;
     size_t spectrum_elems;/* complex elements of the spectral layout, nz*(nx/2)*ny */
     int column_variant;   /* column-solve kernel chosen by planning / autotuning */
+    int chunks;           /* kx ranges the y / column / y passes are split into */
 } ps_plan_info;
 
 int ps_plan_query(const ps_plan *plan, ps_plan_info *info);
@@ -152,8 +153,10 @@ int ps_plan_query(const ps_plan *plan, ps_plan_info *info);
  * nz, precision) for the life of the process -- a later autotune of an equal
  * plan just applies them -- and can be saved to / loaded from a text file
  * (one line per entry: arch nx ny nz precision x_variant y_variant
- * column_variant [fp64_beside], the last 1 when the FP64 columns run on a
- * second stream beside the main column kernel).  Synchronises. */
+ * column_variant [fp64_beside [chunks]]: fp64_beside 1 when the FP64 columns
+ * run on a second stream beside the main column kernel, chunks the number of
+ * kx ranges the y / column / y passes are taken in; both default to 1).
+ * Synchronises. */
 int ps_plan_autotune(ps_plan *plan, int reps);
 int ps_tune_cache_save(const char *path);
 int ps_tune_cache_load(const char *path);

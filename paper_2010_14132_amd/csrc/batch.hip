@@ -69,8 +69,8 @@ __device__ void batch_columns(const BatchProblem &P, long group, T (*xa)[2][64],
 {
     columns3_tile<T, NH, false>(reinterpret_cast<cx_t<T> *>(P.spec), P.L, P.ny,
                                 reinterpret_cast<const T *>(P.ax), reinterpret_cast<const T *>(P.ay),
-                                reinterpret_cast<const LevelCoef<T> *>(P.coef), P.maskcnt, group,
-                                xa, xb);
+                                reinterpret_cast<const LevelCoef<T> *>(P.coef), P.maskcnt,
+                                (long)P.ny, (long)P.L * P.ny, group, xa, xb);
 }
 
 // Bound on the polls of one wait (each poll sleeps ~50 ns, plus the load):

@@ -9,6 +9,29 @@
 
 namespace ps {
 
+// Block -> tile map.  Blocks are handed to the eight XCDs in turn (block b
+// to XCD b mod 8), each with its own L2; with swz set, XCD x takes one
+// contiguous range of tiles instead of every eighth one, so neighbouring
+// tiles (adjacent rows, adjacent 128-byte runs of the transposed layout)
+// meet in the same L2.  A bijection of [0, nb) for any nb.
+__device__ __forceinline__ int tile_of(int b, int nb, int swz)
+{
+    if (!swz) return b;
+    const int q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
+// LDS slot of element (kx, rr) of the x passes' [kx][row] staging (ROWS rows
+// of L values): rows XOR-swizzled per kx so that both the column-wise writes
+// (R1 consecutive kx of each row) and the row-wise reads (ROWS consecutive
+// rows of each kx) hit distinct banks.
+template <int R1, int ROWS> __device__ __forceinline__ int stage_idx(int kx, int rr)
+{
+    constexpr int KB = R1 / ROWS > 1 ? R1 / ROWS : 1;
+    constexpr int KM = ROWS / R1 > 1 ? ROWS / R1 : 1;
+    return kx * ROWS + (rr ^ (((kx / KB) * KM) & (ROWS - 1)));
+}
+
 // ---------------------------------------------------------------- y pass
 // In place over contiguous rows of length L (= ny); NT threads = NT / R1
 // rows.  Row r of the launch is spectrum row (r / kxcnt) nkx + kxlo +
@@ -16,20 +39,20 @@ namespace ps {
 template <typename T, int R1, int R2, int DIR, int NT>
 __global__ __launch_bounds__(NT) void k_fft_y_fast(cx_t<T> *__restrict__ spec, int nrows,
                                                    const cx_t<T> *__restrict__ tw4, int nkx,
-                                                   int kxlo, int kxcnt)
+                                                   int kxlo, int kxcnt, int swz)
 {
     using C = cx_t<T>;
-    constexpr int L = R1 * R2, RB = NT / R1;
-    __shared__ T lds[RB * R2 * (R1 + 1)];
+    constexpr int L = R1 * R2, RB = NT / R1, S = four_step_stride<R1, R2, T>();
+    __shared__ T lds[RB * S];
     const int r = threadIdx.x / R1, t = threadIdx.x - r * R1;
-    const long rr = (long)blockIdx.x * RB + r;
+    const long rr = (long)tile_of(blockIdx.x, gridDim.x, swz) * RB + r;
     const bool ok = rr < nrows;
     const long row = ok ? (rr / kxcnt) * nkx + kxlo + rr % kxcnt : 0;
     C *base = spec + row * (long)L;
     C v[R2], w[R2];
 #pragma unroll
     for (int q = 0; q < R2; ++q) v[q] = ok ? base[t + R1 * q] : C{T(0), T(0)};
-    four_step<R1, R2, DIR>(v, w, t, lds + r * R2 * (R1 + 1), tw4);
+    four_step<R1, R2, DIR>(v, w, t, lds + r * S, tw4);
     if (ok) {
 #pragma unroll
         for (int j = 0; j < R2 / R1; ++j)
@@ -44,6 +67,10 @@ __global__ __launch_bounds__(NT) void k_fft_y_fast(cx_t<T> *__restrict__ spec, i
 // shuffle per value (the partner of slot (t, j, k1), index L - k, sits in lane
 // R1 - t of the same row, or in lane 0's own registers for t = 0), and stores
 // the block's rows transposed through LDS (one real component at a time).
+// korder (requires ny % ROWS == 0): tiles are taken level-fastest -- tile
+// t covers rows j in [(t / nz) ROWS, +ROWS) of level t % nz -- so that, with
+// XCD-contiguous tiles, the blocks of levels k-1, k, k+1 of one row range run
+// together on one XCD and the residual's vertical neighbours come from L2.
 // RES: the transformed row is the residual r = b - A p (b = in) formed with
 // FP64 arithmetic from the stored b and p, rounded once to T.  The vertical
 // term of row k is a_up p_{k+1} + a_dn p_{k-1} - a_c p_k with per-level
@@ -60,14 +87,17 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
                                                       const cx_t<T> *__restrict__ tws,
                                                       const T *__restrict__ pres, int nz,
                                                       double idx2, double idy2,
-                                                      const double *__restrict__ rc)
+                                                      const double *__restrict__ rc, int swz,
+                                                      int korder)
 {
     using C = cx_t<T>;
-    constexpr int L = R1 * R2, NT = ROWS * R1, J = R2 / R1;
-    constexpr int A = ROWS * R2 * (R1 + 1), B = L * (ROWS + 1);
+    constexpr int L = R1 * R2, NT = ROWS * R1, J = R2 / R1, S = four_step_stride<R1, R2, T>();
+    constexpr int A = ROWS * S, B = L * ROWS;
     __shared__ T lds[A > B ? A : B];
     const int r = threadIdx.x / R1, t = threadIdx.x - r * R1;
-    const long g = (long)blockIdx.x * ROWS + r;
+    const long tile = tile_of(blockIdx.x, gridDim.x, swz);
+    const long g0 = korder ? (tile % nz) * (long)ny + (tile / nz) * ROWS : tile * ROWS;
+    const long g = g0 + r;
     const bool ok = g < nrows;
     const C *src = reinterpret_cast<const C *>(in) + (ok ? g : 0) * (long)L;
     C v[R2], w[R2];
@@ -125,7 +155,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
     for (int o = R1 / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if (ok && t == 0) rowsum[g] = s;
 
-    four_step<R1, R2, -1>(v, w, t, lds + r * R2 * (R1 + 1), tw4);
+    four_step<R1, R2, -1>(v, w, t, lds + r * S, tw4);
 
     // split: X_k = (Z_k + Zc)/2 + W_nx^k (Z_k - Zc)/(2i), Zc = conj Z_{L-k}
     const int lane = threadIdx.x & 63;
@@ -156,35 +186,36 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
     }
 
     // transposed store: [row][kx] -> spec[level][kx][j]
-    constexpr int P = ROWS + 1;
     T outr[R2], outi[R2];
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < J; ++j)
 #pragma unroll
-        for (int k1 = 0; k1 < R1; ++k1) lds[((t + R1 * j) + R2 * k1) * P + r] = X[j * R1 + k1].x;
+        for (int k1 = 0; k1 < R1; ++k1)
+            lds[stage_idx<R1, ROWS>((t + R1 * j) + R2 * k1, r)] = X[j * R1 + k1].x;
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < R2; ++i) {
         const int e = threadIdx.x + NT * i;
-        outr[i] = lds[(e / ROWS) * P + (e % ROWS)];
+        outr[i] = lds[stage_idx<R1, ROWS>(e / ROWS, e % ROWS)];
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < J; ++j)
 #pragma unroll
-        for (int k1 = 0; k1 < R1; ++k1) lds[((t + R1 * j) + R2 * k1) * P + r] = X[j * R1 + k1].y;
+        for (int k1 = 0; k1 < R1; ++k1)
+            lds[stage_idx<R1, ROWS>((t + R1 * j) + R2 * k1, r)] = X[j * R1 + k1].y;
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < R2; ++i) {
         const int e = threadIdx.x + NT * i;
-        outi[i] = lds[(e / ROWS) * P + (e % ROWS)];
+        outi[i] = lds[stage_idx<R1, ROWS>(e / ROWS, e % ROWS)];
     }
 #pragma unroll
     for (int i = 0; i < R2; ++i) {
         const int e = threadIdx.x + NT * i;
         const int kx = e / ROWS, rr = e % ROWS;
-        const long g2 = (long)blockIdx.x * ROWS + rr;
+        const long g2 = g0 + rr;
         if (g2 < nrows) {
             const long lev = g2 / ny, jj = g2 - lev * ny;
             spec[(lev * L + kx) * (long)ny + jj] = C{outr[i], outi[i]};
@@ -201,15 +232,15 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
                                                       T *__restrict__ out, int ny, int nrows,
                                                       int accumulate,
                                                       const cx_t<T> *__restrict__ tw4,
-                                                      const cx_t<T> *__restrict__ tws)
+                                                      const cx_t<T> *__restrict__ tws, int swz)
 {
     using C = cx_t<T>;
-    constexpr int L = R1 * R2, NT = ROWS * R1, J = R2 / R1;
-    constexpr int A = ROWS * R2 * (R1 + 1), B = L * (ROWS + 1);
-    constexpr int P = ROWS + 1;
+    constexpr int L = R1 * R2, NT = ROWS * R1, J = R2 / R1, S = four_step_stride<R1, R2, T>();
+    constexpr int A = ROWS * S, B = L * ROWS;
     __shared__ T lds[A > B ? A : B];
     const int r = threadIdx.x / R1, t = threadIdx.x - r * R1;
-    const long g = (long)blockIdx.x * ROWS + r;
+    const long tile = tile_of(blockIdx.x, gridDim.x, swz);
+    const long g = tile * ROWS + r;
     const bool ok = g < nrows;
 
     T inr[R2], ini[R2];
@@ -217,7 +248,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
     for (int i = 0; i < R2; ++i) {
         const int e = threadIdx.x + NT * i;
         const int kx = e / ROWS, rr = e % ROWS;
-        const long g2 = (long)blockIdx.x * ROWS + rr;
+        const long g2 = tile * ROWS + rr;
         C x = C{T(0), T(0)};
         if (g2 < nrows) {
             const long lev = g2 / ny, jj = g2 - lev * ny;
@@ -230,27 +261,27 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
 #pragma unroll
     for (int i = 0; i < R2; ++i) {
         const int e = threadIdx.x + NT * i;
-        lds[(e / ROWS) * P + (e % ROWS)] = inr[i];
+        lds[stage_idx<R1, ROWS>(e / ROWS, e % ROWS)] = inr[i];
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < R2; ++q) {
         const int k = t + R1 * q;
-        xa[q].x = lds[k * P + r];
-        xb[q].x = lds[((L - k) & (L - 1)) * P + r];
+        xa[q].x = lds[stage_idx<R1, ROWS>(k, r)];
+        xb[q].x = lds[stage_idx<R1, ROWS>((L - k) & (L - 1), r)];
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < R2; ++i) {
         const int e = threadIdx.x + NT * i;
-        lds[(e / ROWS) * P + (e % ROWS)] = ini[i];
+        lds[stage_idx<R1, ROWS>(e / ROWS, e % ROWS)] = ini[i];
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < R2; ++q) {
         const int k = t + R1 * q;
-        xa[q].y = lds[k * P + r];
-        xb[q].y = lds[((L - k) & (L - 1)) * P + r];
+        xa[q].y = lds[stage_idx<R1, ROWS>(k, r)];
+        xb[q].y = lds[stage_idx<R1, ROWS>((L - k) & (L - 1), r)];
     }
     C v[R2], w[R2];
 #pragma unroll
@@ -267,7 +298,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
         }
     }
     __syncthreads();
-    four_step<R1, R2, 1>(v, w, t, lds + r * R2 * (R1 + 1), tw4);
+    four_step<R1, R2, 1>(v, w, t, lds + r * S, tw4);
     if (ok) {
         C *dst = reinterpret_cast<C *>(out) + g * (long)L;
 #pragma unroll
@@ -284,13 +315,14 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
 
 // ---------------------------------------------------------------- launchers
 // Rows per block of the x passes: 128-byte runs of the transposed layout
-// (16 FP32 or 8 FP64 complex values), halved until the LDS buffer fits 64 KiB.
-template <typename T, int R1, int R2> constexpr int x_rows()
+// (16 FP32 or 8 FP64 complex values), halved until the LDS buffer fits 64 KiB;
+// WIDE: 256-byte runs within 128 KiB.
+template <typename T, int R1, int R2, bool WIDE> constexpr int x_rows()
 {
-    int rows = sizeof(T) == 8 ? 8 : 16;
+    int rows = (sizeof(T) == 8 ? 8 : 16) * (WIDE ? 2 : 1);
     while (rows > 1) {
-        const int a = rows * R2 * (R1 + 1), b = R1 * R2 * (rows + 1);
-        if ((a > b ? a : b) * (int)sizeof(T) <= 65536) break;
+        const int a = rows * four_step_stride<R1, R2, T>(), b = R1 * R2 * rows;
+        if ((a > b ? a : b) * (int)sizeof(T) <= (WIDE ? 131072 : 65536)) break;
         rows /= 2;
     }
     return rows;
@@ -299,7 +331,7 @@ template <typename T, int R1, int R2> constexpr int x_rows()
 // Returns hipErrorNotSupported when L has no register-resident kernel.
 template <typename T, int R1, int R2>
 static hipError_t y_fast(cx_t<T> *spec, int nrows, int dir, const cx_t<T> *tw4, int nkx, int kxlo,
-                         int kxcnt, hipStream_t st)
+                         int kxcnt, int swz, hipStream_t st)
 {
     constexpr int NT = sizeof(T) == 8 && R1 * R2 >= 512 ? 128 : 256;
     constexpr int RB = NT / R1;
@@ -307,10 +339,10 @@ static hipError_t y_fast(cx_t<T> *spec, int nrows, int dir, const cx_t<T> *tw4, 
     const int grid = (nrows + RB - 1) / RB;
     if (dir < 0)
         hipLaunchKernelGGL((k_fft_y_fast<T, R1, R2, -1, NT>), dim3(grid), dim3(NT), 0, st, spec,
-                           nrows, tw4, nkx, kxlo, kxcnt);
+                           nrows, tw4, nkx, kxlo, kxcnt, swz);
     else
         hipLaunchKernelGGL((k_fft_y_fast<T, R1, R2, 1, NT>), dim3(grid), dim3(NT), 0, st, spec,
-                           nrows, tw4, nkx, kxlo, kxcnt);
+                           nrows, tw4, nkx, kxlo, kxcnt, swz);
     return hipGetLastError();
 }
 
@@ -329,72 +361,104 @@ int fast_r1(int L) { return L <= 32 ? 4 : L <= 128 ? 8 : L <= 512 ? 16 : 32; }
     default: return hipErrorNotSupported;                                                          \
     }
 
+// variant: 1 = plain block order, 2 = XCD-contiguous tiles.
 template <typename T>
 hipError_t launch_fft_y_fast(cx_t<T> *spec, int nz, int nkx, int kxlo, int kxcnt, int ny, int dir,
-                             const cx_t<T> *tw4, hipStream_t st)
+                             const cx_t<T> *tw4, hipStream_t st, int variant)
 {
     const int nrows = nz * kxcnt;
-#define PS_Y(a, b) y_fast<T, a, b>(spec, nrows, dir, tw4, nkx, kxlo, kxcnt, st)
+    const int swz = variant >= 2;
+#define PS_Y(a, b) y_fast<T, a, b>(spec, nrows, dir, tw4, nkx, kxlo, kxcnt, swz, st)
     PS_FAST_SWITCH(ny, PS_Y)
 #undef PS_Y
 }
 
+template <typename T, int R1, int R2, bool WIDE>
+static hipError_t r2c_fast_rows(const T *in, cx_t<T> *spec, double *rowsum, int ny, int nz,
+                                const cx_t<T> *tw4, const cx_t<T> *tws, const T *pres,
+                                double idx2, double idy2, const double *rc, int swz,
+                                hipStream_t st)
+{
+    constexpr int ROWS = x_rows<T, R1, R2, WIDE>();
+    const int nrows = ny * nz;
+    const int grid = (nrows + ROWS - 1) / ROWS;
+    // the residual's level-fastest tile order, where tiles do not straddle levels
+    const int korder = pres && swz && ny % ROWS == 0;
+    if (pres)
+        hipLaunchKernelGGL((k_r2c_fast<T, R1, R2, ROWS, true>), dim3(grid), dim3(ROWS * R1), 0, st,
+                           in, spec, rowsum, ny, nrows, tw4, tws, pres, nz, idx2, idy2, rc, swz,
+                           korder);
+    else
+        hipLaunchKernelGGL((k_r2c_fast<T, R1, R2, ROWS, false>), dim3(grid), dim3(ROWS * R1), 0,
+                           st, in, spec, rowsum, ny, nrows, tw4, tws, pres, nz, idx2, idy2, rc,
+                           swz, 0);
+    return hipGetLastError();
+}
+
+// variant: 1 = plain block order, 2 = XCD-contiguous tiles, 3 = as 2 with
+// twice the rows per block (256-byte runs of the transposed layout).
 template <typename T, int R1, int R2>
 static hipError_t r2c_fast(const T *in, cx_t<T> *spec, double *rowsum, int ny, int nz,
                            const cx_t<T> *tw4, const cx_t<T> *tws, const T *pres, double idx2,
-                           double idy2, const double *rc, hipStream_t st)
+                           double idy2, const double *rc, int variant, hipStream_t st)
 {
-    constexpr int ROWS = x_rows<T, R1, R2>();
-    const int nrows = ny * nz;
-    const int grid = (nrows + ROWS - 1) / ROWS;
-    if (pres)
-        hipLaunchKernelGGL((k_r2c_fast<T, R1, R2, ROWS, true>), dim3(grid), dim3(ROWS * R1), 0, st,
-                           in, spec, rowsum, ny, nrows, tw4, tws, pres, nz, idx2, idy2, rc);
-    else
-        hipLaunchKernelGGL((k_r2c_fast<T, R1, R2, ROWS, false>), dim3(grid), dim3(ROWS * R1), 0,
-                           st, in, spec, rowsum, ny, nrows, tw4, tws, pres, nz, idx2, idy2, rc);
-    return hipGetLastError();
+    if (variant >= 3)
+        return r2c_fast_rows<T, R1, R2, true>(in, spec, rowsum, ny, nz, tw4, tws, pres, idx2,
+                                              idy2, rc, 1, st);
+    return r2c_fast_rows<T, R1, R2, false>(in, spec, rowsum, ny, nz, tw4, tws, pres, idx2, idy2,
+                                           rc, variant >= 2, st);
 }
 
 template <typename T>
 hipError_t launch_r2c_fast(const T *in, cx_t<T> *spec, double *rowsum, int nx, int ny, int nz,
                            const cx_t<T> *tw4, const cx_t<T> *tws, hipStream_t st,
-                           const T *pres, double idx2, double idy2, const double *rc)
+                           const T *pres, double idx2, double idy2, const double *rc, int variant)
 {
-#define PS_X(a, b) r2c_fast<T, a, b>(in, spec, rowsum, ny, nz, tw4, tws, pres, idx2, idy2, rc, st)
+#define PS_X(a, b)                                                                                 \
+    r2c_fast<T, a, b>(in, spec, rowsum, ny, nz, tw4, tws, pres, idx2, idy2, rc, variant, st)
     PS_FAST_SWITCH(nx / 2, PS_X)
 #undef PS_X
 }
 
-template <typename T, int R1, int R2>
-static hipError_t c2r_fast(const cx_t<T> *spec, T *out, int ny, int nrows, int accumulate,
-                           const cx_t<T> *tw4, const cx_t<T> *tws, hipStream_t st)
+template <typename T, int R1, int R2, bool WIDE>
+static hipError_t c2r_fast_rows(const cx_t<T> *spec, T *out, int ny, int nrows, int accumulate,
+                                const cx_t<T> *tw4, const cx_t<T> *tws, int swz, hipStream_t st)
 {
-    constexpr int ROWS = x_rows<T, R1, R2>();
+    constexpr int ROWS = x_rows<T, R1, R2, WIDE>();
     const int grid = (nrows + ROWS - 1) / ROWS;
     hipLaunchKernelGGL((k_c2r_fast<T, R1, R2, ROWS>), dim3(grid), dim3(ROWS * R1), 0, st, spec, out,
-                       ny, nrows, accumulate, tw4, tws);
+                       ny, nrows, accumulate, tw4, tws, swz);
     return hipGetLastError();
+}
+
+template <typename T, int R1, int R2>
+static hipError_t c2r_fast(const cx_t<T> *spec, T *out, int ny, int nrows, int accumulate,
+                           const cx_t<T> *tw4, const cx_t<T> *tws, int variant, hipStream_t st)
+{
+    if (variant >= 3)
+        return c2r_fast_rows<T, R1, R2, true>(spec, out, ny, nrows, accumulate, tw4, tws, 1, st);
+    return c2r_fast_rows<T, R1, R2, false>(spec, out, ny, nrows, accumulate, tw4, tws,
+                                           variant >= 2, st);
 }
 
 template <typename T>
 hipError_t launch_c2r_fast(const cx_t<T> *spec, T *out, int nx, int ny, int nz, int accumulate,
-                           const cx_t<T> *tw4, const cx_t<T> *tws, hipStream_t st)
+                           const cx_t<T> *tw4, const cx_t<T> *tws, hipStream_t st, int variant)
 {
     const int nrows = ny * nz;
-#define PS_X(a, b) c2r_fast<T, a, b>(spec, out, ny, nrows, accumulate, tw4, tws, st)
+#define PS_X(a, b) c2r_fast<T, a, b>(spec, out, ny, nrows, accumulate, tw4, tws, variant, st)
     PS_FAST_SWITCH(nx / 2, PS_X)
 #undef PS_X
 }
 
 #define PS_INST(T)                                                                                 \
     template hipError_t launch_fft_y_fast<T>(cx_t<T> *, int, int, int, int, int, int,            \
-                                             const cx_t<T> *, hipStream_t);                       \
+                                             const cx_t<T> *, hipStream_t, int);                  \
     template hipError_t launch_r2c_fast<T>(const T *, cx_t<T> *, double *, int, int, int,        \
                                            const cx_t<T> *, const cx_t<T> *, hipStream_t,         \
-                                           const T *, double, double, const double *);            \
+                                           const T *, double, double, const double *, int);       \
     template hipError_t launch_c2r_fast<T>(const cx_t<T> *, T *, int, int, int, int,             \
-                                           const cx_t<T> *, const cx_t<T> *, hipStream_t);
+                                           const cx_t<T> *, const cx_t<T> *, hipStream_t, int);
 PS_INST(float)
 PS_INST(double)
 #undef PS_INST

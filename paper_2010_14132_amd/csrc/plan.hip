@@ -475,6 +475,7 @@ extern "C" int ps_plan_query(const ps_plan *p, ps_plan_info *info)
     info->fft_variant_y = p->geom.variant_y;
     info->spectrum_elems = p->spec_elems();
     info->column_variant = p->geom.columns;
+    info->chunks = p->geom.special_side ? p->geom.chunks : 1;
     return PS_OK;
 }
 
@@ -547,9 +548,9 @@ static hipError_t y_pass(ps_plan *p, cx_t<T> *spec, int dir, int kxlo = 0, int k
     if (kxcnt < 0) kxcnt = p->L - kxlo;
     if (kxcnt <= 0) return hipSuccess;
     return timed(p, dir < 0 ? K_FFT_Y_FWD : K_FFT_Y_INV, [&] {
-        if (p->geom.variant_y == 1)
+        if (p->geom.variant_y >= 1)
             return launch_fft_y_fast<T>(spec, p->nz, p->L, kxlo, kxcnt, p->ny, dir, tb.tw4_y,
-                                        p->stream);
+                                        p->stream, p->geom.variant_y);
         return launch_fft_y<T>(spec, p->nz, p->L, kxlo, kxcnt, p->ny, dir, p->geom, p->spy, tb,
                                p->stream);
     });
@@ -560,9 +561,10 @@ template <typename T> static int fwd_x(ps_plan *p, const T *rhs, cx_t<T> *spec)
 {
     const Tables<T> &tb = tables<T>(p);
     PS_HIP(timed(p, K_FWD_X, [&] {
-        if (p->geom.variant_x == 1)
+        if (p->geom.variant_x >= 1)
             return launch_r2c_fast<T>(rhs, spec, p->d_rowsum, p->nx, p->ny, p->nz, tb.tw4_x,
-                                      tb.tw_s, p->stream);
+                                      tb.tw_s, p->stream, nullptr, 0.0, 0.0, nullptr,
+                                      p->geom.variant_x);
         return launch_fwd_x<T>(rhs, spec, p->d_rowsum, p->nx, p->ny, p->nz, p->geom, p->spx, tb,
                                p->stream);
     }));
@@ -578,14 +580,16 @@ template <typename T> static int fwd(ps_plan *p, const T *rhs, cx_t<T> *spec)
     return PS_OK;
 }
 
-template <typename T> static int fwd_residual_x(ps_plan *p, const T *b, const T *x, cx_t<T> *spec, int adjoint)
+template <typename T>
+static int fwd_residual_x(ps_plan *p, const T *b, const T *x, cx_t<T> *spec, int adjoint)
 {
     PS_HIP(timed(p, K_FWD_X_RES, [&] {
-        if (p->geom.variant_x == 1)
+        if (p->geom.variant_x >= 1)
             return launch_r2c_fast<T>(b, spec, p->d_rowsum, p->nx, p->ny, p->nz,
                                       tables<T>(p).tw4_x, tables<T>(p).tw_s, p->stream, x,
                                       1.0 / (p->dx * p->dx), 1.0 / (p->dy * p->dy),
-                                      p->d_rc + (adjoint ? 3 * (size_t)p->nz : 0));
+                                      p->d_rc + (adjoint ? 3 * (size_t)p->nz : 0),
+                                      p->geom.variant_x);
         return launch_fwd_x_residual<T>(b, x, spec, p->d_rowsum, p->nx, p->ny, p->nz,
                                         1.0 / (p->dx * p->dx), 1.0 / (p->dy * p->dy), p->t64.f,
                                         p->t64.D, adjoint, p->geom, p->spx, tables<T>(p),
@@ -596,79 +600,122 @@ template <typename T> static int fwd_residual_x(ps_plan *p, const T *b, const T 
     return PS_OK;
 }
 
-// The FP64 columns (packed kx = 0 row, mean column, near-singular columns)
-// and the main column kernel touch disjoint columns.  When the forward y
-// pass is part of the call (ypass != 0) and the FP64 kernel runs beside the
-// main one, the y pass first transforms only the rows kx < kmask (which hold
-// every FP64 column), the FP64 kernel is forked onto the plan's side stream,
-// and the remaining y pass and the main column kernel run meanwhile; the
-// streams join before the backward transform.
+// Main column solves of the rows kx in [kxlo, kxhi) on the plan's stream.
 template <typename T>
-static int columns(ps_plan *p, cx_t<T> *spec, int adjoint, int refine, int ypass = 0)
+static hipError_t main_columns(ps_plan *p, cx_t<T> *spec, int adjoint, int refine, int kxlo,
+                               int kxhi)
 {
     const int *mc = p->fp64() ? nullptr : p->d_maskcnt;
-    if (ypass && p->geom.special_side) {
-        PS_HIP(y_pass<T>(p, spec, -1, 0, p->kmask));
-        PS_HIP(hipEventRecord(p->fork, p->stream));
-        PS_HIP(hipStreamWaitEvent(p->side, p->fork, 0));
-        PS_HIP(timed(
-            p, K_SPECIAL,
-            [&] {
-                return launch_special<T>(spec, p->nx, p->ny, p->nz, adjoint, p->d_mlist, p->nmask,
-                                         p->d_S, p->d_ws, p->t64, p->side, 0);
-            },
-            p->side));
-        PS_HIP(hipEventRecord(p->join, p->side));
-        PS_HIP(y_pass<T>(p, spec, -1, p->kmask));
-        PS_HIP(timed(p, K_COLUMNS, [&] {
-            return launch_columns_impl<T>(spec, p->nx, p->ny, p->nz, adjoint, refine, mc,
-                                          tables<T>(p), &p->t64, p->stream, p->geom.columns);
-        }));
-        PS_HIP(hipStreamWaitEvent(p->stream, p->join, 0));
-        return PS_OK;
-    }
-    if (ypass) PS_HIP(y_pass<T>(p, spec, -1));
-    if (!p->geom.special_side) {
-        PS_HIP(timed(p, K_SPECIAL, [&] {
-            return launch_special<T>(spec, p->nx, p->ny, p->nz, adjoint, p->d_mlist, p->nmask,
-                                     p->d_S, p->d_ws, p->t64, p->stream, 0);
-        }));
-        PS_HIP(timed(p, K_COLUMNS, [&] {
-            return launch_columns_impl<T>(spec, p->nx, p->ny, p->nz, adjoint, refine, mc,
-                                          tables<T>(p), &p->t64, p->stream, p->geom.columns);
-        }));
-        return PS_OK;
-    }
-    PS_HIP(hipEventRecord(p->fork, p->stream));
-    PS_HIP(hipStreamWaitEvent(p->side, p->fork, 0));
-    PS_HIP(timed(
+    return timed(p, K_COLUMNS, [&] {
+        return launch_columns_impl<T>(spec, p->nx, p->ny, p->nz, adjoint, refine, mc,
+                                      tables<T>(p), &p->t64, p->stream, p->geom.columns, kxlo,
+                                      kxhi);
+    });
+}
+
+// The FP64 columns (packed kx = 0 row, mean column, near-singular columns)
+// on stream st.
+template <typename T>
+static hipError_t special_columns(ps_plan *p, cx_t<T> *spec, int adjoint, hipStream_t st)
+{
+    return timed(
         p, K_SPECIAL,
         [&] {
             return launch_special<T>(spec, p->nx, p->ny, p->nz, adjoint, p->d_mlist, p->nmask,
-                                     p->d_S, p->d_ws, p->t64, p->side, 0);
+                                     p->d_S, p->d_ws, p->t64, st, 0);
         },
-        p->side));
+        st);
+}
+
+// Forks the FP64 columns onto the side stream (after what the plan's stream
+// has queued); the caller waits for p->join before touching those rows.
+template <typename T> static int fork_special(ps_plan *p, cx_t<T> *spec, int adjoint)
+{
+    PS_HIP(hipEventRecord(p->fork, p->stream));
+    PS_HIP(hipStreamWaitEvent(p->side, p->fork, 0));
+    PS_HIP(special_columns<T>(p, spec, adjoint, p->side));
     PS_HIP(hipEventRecord(p->join, p->side));
-    PS_HIP(timed(p, K_COLUMNS, [&] {
-        return launch_columns_impl<T>(spec, p->nx, p->ny, p->nz, adjoint, refine, mc,
-                                      tables<T>(p), &p->t64, p->stream, p->geom.columns);
-    }));
+    return PS_OK;
+}
+
+// Column solves only (the spectral stage on its own).  The FP64 columns and
+// the main column kernel touch disjoint columns, so they may run side by side.
+template <typename T> static int columns(ps_plan *p, cx_t<T> *spec, int adjoint, int refine)
+{
+    if (!p->geom.special_side) {
+        PS_HIP(special_columns<T>(p, spec, adjoint, p->stream));
+        PS_HIP(main_columns<T>(p, spec, adjoint, refine, 1, p->L));
+        return PS_OK;
+    }
+    PS_TRY(fork_special<T>(p, spec, adjoint));
+    PS_HIP(main_columns<T>(p, spec, adjoint, refine, 1, p->L));
     PS_HIP(hipStreamWaitEvent(p->stream, p->join, 0));
     return PS_OK;
 }
 
-template <typename T> static int inv(ps_plan *p, cx_t<T> *spec, T *out, int accumulate)
+// y forward, column solves and y backward.  With the FP64 kernel beside the
+// main one, the y pass first transforms only the rows kx < kmask (which hold
+// every FP64 column), the FP64 kernel is forked onto the side stream, and the
+// rest runs meanwhile; the streams join before those rows are transformed
+// back.  With chunks > 1 the rows kx >= kmask are processed in that many
+// ranges, each y forward -> columns -> y backward in turn, so that a range's
+// spectrum (nz ny (range) values) can still be in the last-level cache (the
+// 256 MB Infinity Cache) when the column kernel and the backward y pass read
+// it back.
+template <typename T> static int middle(ps_plan *p, cx_t<T> *spec, int adjoint, int refine)
+{
+    const int L = p->L;
+    if (!p->geom.special_side) {
+        PS_HIP(y_pass<T>(p, spec, -1));
+        PS_HIP(special_columns<T>(p, spec, adjoint, p->stream));
+        PS_HIP(main_columns<T>(p, spec, adjoint, refine, 1, L));
+        PS_HIP(y_pass<T>(p, spec, 1));
+        return PS_OK;
+    }
+    const int km = std::min(p->kmask, L);
+    PS_HIP(y_pass<T>(p, spec, -1, 0, km));
+    PS_TRY(fork_special<T>(p, spec, adjoint));
+    const int nch = std::max(1, std::min(p->geom.chunks, L - km));
+    if (nch <= 1) {
+        PS_HIP(y_pass<T>(p, spec, -1, km));
+        PS_HIP(main_columns<T>(p, spec, adjoint, refine, 1, L));
+        PS_HIP(hipStreamWaitEvent(p->stream, p->join, 0));
+        PS_HIP(y_pass<T>(p, spec, 1));
+        return PS_OK;
+    }
+    PS_HIP(main_columns<T>(p, spec, adjoint, refine, 1, km));
+    const long rest = L - km;
+    for (int c = 0; c < nch; ++c) {
+        const int a = km + (int)(rest * c / nch), b = km + (int)(rest * (c + 1) / nch);
+        if (b <= a) continue;
+        PS_HIP(y_pass<T>(p, spec, -1, a, b - a));
+        PS_HIP(main_columns<T>(p, spec, adjoint, refine, a, b));
+        PS_HIP(y_pass<T>(p, spec, 1, a, b - a));
+    }
+    PS_HIP(hipStreamWaitEvent(p->stream, p->join, 0));
+    PS_HIP(y_pass<T>(p, spec, 1, 0, km));
+    return PS_OK;
+}
+
+// Backward x pass only.
+template <typename T> static int inv_x(ps_plan *p, cx_t<T> *spec, T *out, int accumulate)
 {
     const Tables<T> &tb = tables<T>(p);
-    PS_HIP(y_pass<T>(p, spec, 1));
     PS_HIP(timed(p, K_INV_X, [&] {
-        if (p->geom.variant_x == 1)
+        if (p->geom.variant_x >= 1)
             return launch_c2r_fast<T>(spec, out, p->nx, p->ny, p->nz, accumulate, tb.tw4_x,
-                                      tb.tw_s, p->stream);
+                                      tb.tw_s, p->stream, p->geom.variant_x);
         return launch_inv_x<T>(spec, out, p->nx, p->ny, p->nz, accumulate, p->geom, p->spx, tb,
                                p->stream);
     }));
     return PS_OK;
+}
+
+// Backward y and x passes (the inverse-transform stage on its own).
+template <typename T> static int inv(ps_plan *p, cx_t<T> *spec, T *out, int accumulate)
+{
+    PS_HIP(y_pass<T>(p, spec, 1));
+    return inv_x<T>(p, spec, out, accumulate);
 }
 
 template <typename T> static int run(ps_plan *p, const T *in, T *out, int adjoint)
@@ -676,12 +723,12 @@ template <typename T> static int run(ps_plan *p, const T *in, T *out, int adjoin
     auto *spec = reinterpret_cast<cx_t<T> *>(p->d_spec);
     const int refine = p->precision == PS_FP32_R2;
     PS_TRY(fwd_x<T>(p, in, spec));
-    PS_TRY(columns<T>(p, spec, adjoint, refine, 1));
-    PS_TRY(inv<T>(p, spec, out, 0));
+    PS_TRY(middle<T>(p, spec, adjoint, refine));
+    PS_TRY(inv_x<T>(p, spec, out, 0));
     if (p->precision == PS_FP32_R1) {
         PS_TRY(fwd_residual_x<T>(p, in, out, spec, adjoint));
-        PS_TRY(columns<T>(p, spec, adjoint, 0, 1));
-        PS_TRY(inv<T>(p, spec, out, 1));
+        PS_TRY(middle<T>(p, spec, adjoint, 0));
+        PS_TRY(inv_x<T>(p, spec, out, 1));
     }
     return PS_OK;
 }
@@ -792,10 +839,11 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
         auto it = g_tune.find(key);
         if (it != g_tune.end()) {
             // only the tuned knobs: the tile shapes follow from the plan
-            p->geom.variant_x = it->second.variant_x && fast_length(p->L) ? 1 : 0;
-            p->geom.variant_y = it->second.variant_y && fast_length(p->ny) ? 1 : 0;
+            p->geom.variant_x = fast_length(p->L) ? it->second.variant_x : 0;
+            p->geom.variant_y = fast_length(p->ny) ? it->second.variant_y : 0;
             p->geom.columns = it->second.columns;
             p->geom.special_side = it->second.special_side;
+            p->geom.chunks = it->second.chunks;
             return PS_OK;
         }
     }
@@ -827,15 +875,16 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
         p->geom.*knob = best;
     };
     std::vector<int> vx{0}, vy{0};
-    if (fast_length(p->L)) vx.push_back(1);
-    if (fast_length(p->ny)) vy.push_back(1);
+    if (fast_length(p->L)) vx.insert(vx.end(), {1, 2, 3});
+    if (fast_length(p->ny)) vy.insert(vy.end(), {1, 2});
     pick(&FftGeom::variant_x, vx);
     pick(&FftGeom::variant_y, vy);
     if (p->precision != PS_FP32_R2)
-        pick(&FftGeom::columns, {0, 1, 2, 3, 4});
+        pick(&FftGeom::columns, {0, 1, 2, 3, 4, 5});
     else
-        pick(&FftGeom::columns, {0, 3});
+        pick(&FftGeom::columns, {0, 3, 5});
     pick(&FftGeom::special_side, {0, 1});
+    if (p->geom.special_side) pick(&FftGeom::chunks, {1, 2, 4, 8});
     p->prof.on = prof;
     (void)hipStreamSynchronize(p->stream);
     (void)hipFree(in);
@@ -847,7 +896,7 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
 }
 
 // Text format, one line per entry: arch nx ny nz precision variant_x
-// variant_y columns
+// variant_y columns special_side chunks (the last two optional on reading)
 extern "C" int ps_tune_cache_save(const char *path)
 {
     if (!path) return fail(PS_EINVAL, "path is NULL");
@@ -856,7 +905,8 @@ extern "C" int ps_tune_cache_save(const char *path)
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (auto &kv : g_tune)
         f << kv.first << ' ' << kv.second.variant_x << ' ' << kv.second.variant_y << ' '
-          << kv.second.columns << ' ' << kv.second.special_side << '\n';
+          << kv.second.columns << ' ' << kv.second.special_side << ' ' << kv.second.chunks
+          << '\n';
     return f.good() ? PS_OK : fail(PS_EINVAL, "write failed");
 }
 
@@ -870,18 +920,21 @@ extern "C" int ps_tune_cache_load(const char *path)
     while (std::getline(f, line)) {
         std::istringstream is(line);
         std::string arch;
-        int nx, ny, nz, prec, vx, vy, col, side = 1;
+        int nx, ny, nz, prec, vx, vy, col, side = 1, chunks = 1;
         if (!(is >> arch >> nx >> ny >> nz >> prec >> vx >> vy >> col)) continue;
         if (!(is >> side)) side = 1;
-        if (vx < 0 || vx > 1 || vy < 0 || vy > 1 || col < 0 || col > 4 || side < 0 || side > 1)
+        if (!(is >> chunks)) chunks = 1;
+        if (vx < 0 || vx > 3 || vy < 0 || vy > 2 || col < 0 || col > 5 || side < 0 || side > 1 ||
+            chunks < 1 || chunks > 64)
             continue;
         std::ostringstream k;
         k << arch << ' ' << nx << ' ' << ny << ' ' << nz << ' ' << prec;
         FftGeom g;
-        g.variant_x = vx && fast_length(nx / 2) ? 1 : 0;
-        g.variant_y = vy && fast_length(ny) ? 1 : 0;
+        g.variant_x = fast_length(nx / 2) ? vx : 0;
+        g.variant_y = fast_length(ny) ? vy : 0;
         g.columns = col;
         g.special_side = side;
+        g.chunks = chunks;
         got[k.str()] = g;
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);

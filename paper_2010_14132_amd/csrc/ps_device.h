@@ -161,7 +161,18 @@ template <int R, int DIR, typename C> __device__ __forceinline__ void dft(C *v)
 // On exit w[j R1 + k1] = X[(t + R1 j) + R2 k1], j in [0, R2/R1).
 // tw4[k2 R1 + t] = W_L^{t k2} (forward roots; conjugated for DIR > 0).
 // lds is this row's scratch of R2 (R1 + 1) values; every thread of the block
-// must call this together (it synchronises the block).
+// must call this together (it synchronises the block).  Consecutive rows'
+// scratch areas are four_step_stride() values apart: the padding puts the
+// rows that share a wavefront on disjoint LDS banks (32 banks of 4 bytes:
+// a row stride congruent to R1 words modulo the bank count), so both the
+// column writes and the row reads run at the conflict-free rate.
+template <int R1, int R2, typename T> constexpr int four_step_stride()
+{
+    constexpr int base = R2 * (R1 + 1);
+    return sizeof(T) == 8 ? base + (((R1 / 2 - base) % 16) + 16) % 16
+                          : base + (((R1 - base) % 32) + 32) % 32;
+}
+
 template <int R1, int R2, int DIR, typename C, typename T>
 __device__ __forceinline__ void four_step(C (&v)[R2], C (&w)[R2], int t, T *lds,
                                           const C *__restrict__ tw4)

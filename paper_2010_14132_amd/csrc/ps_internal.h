@@ -48,6 +48,7 @@ struct FftGeom {
     int variant_y = 0;
     int special_side = 1; // 1: FP64 columns on the side stream beside the main kernel
     int columns = 2;     // column-solve kernel variant (see launch_columns_impl)
+    int chunks = 1;      // y forward / columns / y backward run in this many kx chunks
 };
 
 struct Launch {
@@ -76,26 +77,31 @@ hipError_t launch_inv_x(const cx_t<T> *spec, T *out, int nx, int ny, int nz, int
 
 bool fast_length(int L);
 int fast_r1(int L); // lanes per row of the register-resident kernels
+// variant (the plan's variant_x / variant_y >= 1): 1 = plain block order,
+// 2 = XCD-contiguous tiles, 3 (x passes only) = as 2 with twice the rows per
+// block.
 template <typename T>
 hipError_t launch_fft_y_fast(cx_t<T> *spec, int nz, int L, int kxlo, int kxcnt, int ny, int dir,
-                             const cx_t<T> *tw4, hipStream_t st);
+                             const cx_t<T> *tw4, hipStream_t st, int variant);
 // pres != nullptr: transform the residual in - A pres (or in - A^T pres),
 // with the per-level vertical coefficients rc (see k_r2c_fast).
 template <typename T>
 hipError_t launch_r2c_fast(const T *in, cx_t<T> *spec, double *rowsum, int nx, int ny, int nz,
                            const cx_t<T> *tw4, const cx_t<T> *tws, hipStream_t st,
-                           const T *pres = nullptr, double idx2 = 0, double idy2 = 0,
-                           const double *rc = nullptr);
+                           const T *pres, double idx2, double idy2, const double *rc,
+                           int variant);
 template <typename T>
 hipError_t launch_c2r_fast(const cx_t<T> *spec, T *out, int nx, int ny, int nz, int accumulate,
-                           const cx_t<T> *tw4, const cx_t<T> *tws, hipStream_t st);
+                           const cx_t<T> *tw4, const cx_t<T> *tws, hipStream_t st, int variant);
 
 hipError_t launch_level_sums(const double *rowsum, double *S, int ny, int nz, hipStream_t st);
 
+// Column solves of the rows kx in [kxlo, kxhi) (kx = 0 excluded: the FP64
+// kernel's row).
 template <typename T>
 hipError_t launch_columns_impl(cx_t<T> *spec, int nx, int ny, int nz, int adjoint, int refine,
                                const int *maskcnt, const Tables<T> &tb, const Tables<double> *t64,
-                               hipStream_t st, int variant);
+                               hipStream_t st, int variant, int kxlo, int kxhi);
 
 template <typename T>
 hipError_t launch_special(cx_t<T> *spec, int nx, int ny, int nz, int adjoint, const int *mlist,

@@ -179,13 +179,14 @@ __device__ __forceinline__ double pivot_rcp(double u) { return 1.0 / u; }
 // (complex values, real pivots); they exchange their messages to the middle
 // row through LDS.  KEEPG keeps the reciprocal pivots in registers instead
 // of recomputing them in the backward pass.
-// `group` selects 128 consecutive columns of the kx >= 1 range; xa / xb
+// `group` selects 128 consecutive columns of the range [c0, c1) (column
+// index kx * ny + ky; c0 >= ny, every kx >= 1); xa / xb
 // are LDS scratch of 2 * 2 * 64 values each (the block's 256 threads call
 // this together).
 template <typename T, int NH, bool KEEPG>
 __device__ void columns3_tile(cx_t<T> *__restrict__ spec, int L, int ny, const T *__restrict__ ax,
                               const T *__restrict__ ay, const LevelCoef<T> *__restrict__ coef,
-                              const int *__restrict__ maskcnt, long group, T (*xa)[2][64],
+                              const int *__restrict__ maskcnt, long c0, long c1, long group, T (*xa)[2][64],
                               cx_t<T> (*xb)[2][64])
 {
     using C = cx_t<T>;
@@ -194,9 +195,8 @@ __device__ void columns3_tile(cx_t<T> *__restrict__ spec, int L, int ny, const T
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int pair = w >> 1, half = w & 1;
-    const long ncol = (long)L * ny;
-    const long col = (long)ny + (group * 2 + pair) * 64 + lane;
-    const bool valid = col < ncol;
+    const long col = c0 + (group * 2 + pair) * 64 + lane;
+    const bool valid = col < c1;
     const int kx = valid ? (int)(col / ny) : 1;
     const int ky = valid ? (int)(col - (long)kx * ny) : 0;
     const T s = ax[kx] + ay[ky];
@@ -224,6 +224,7 @@ __device__ void columns3_tile(cx_t<T> *__restrict__ spec, int L, int ny, const T
     C y = C{T(0), T(0)};
 #pragma unroll
     for (int i = 0; i < NH; ++i) {
+        if (i % CH == 0) __asm__ volatile("" ::: "memory"); // keep table loads near their use
         if (!KEEPG && i % CH == 0) qck[i / CH] = q;
         const T e = s * ct[i].D + ct[i].fp * q;
         const T gi = pivot_rcp(e + ct[i].fn);
@@ -256,6 +257,7 @@ __device__ void columns3_tile(cx_t<T> *__restrict__ spec, int L, int ny, const T
         for (int bb = NB - 1; bb >= 0; --bb) {
             T gb[CH];
             T qq = qck[bb];
+            __asm__ volatile("" ::: "memory");
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 const int i = bb * CH + c;
@@ -300,7 +302,7 @@ __device__ void columns3r_tile(float2 *__restrict__ spec, int L, int ny, const f
                                const LevelCoef<float> *__restrict__ coef,
                                const LevelCoef<double> *__restrict__ coef64,
                                const double *__restrict__ ax64, const double *__restrict__ ay64,
-                               const int *__restrict__ maskcnt, long group, float (*xa)[2][64],
+                               const int *__restrict__ maskcnt, long c0, long c1, long group, float (*xa)[2][64],
                                float2 (*xb)[2][64], float2 (*xe)[2][64])
 {
     using C = float2;
@@ -309,9 +311,8 @@ __device__ void columns3r_tile(float2 *__restrict__ spec, int L, int ny, const f
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int pair = w >> 1, half = w & 1;
-    const long ncol = (long)L * ny;
-    const long col = (long)ny + (group * 2 + pair) * 64 + lane;
-    const bool valid = col < ncol;
+    const long col = c0 + (group * 2 + pair) * 64 + lane;
+    const bool valid = col < c1;
     const int kx = valid ? (int)(col / ny) : 1;
     const int ky = valid ? (int)(col - (long)kx * ny) : 0;
     const float s = ax[kx] + ay[ky];
@@ -341,7 +342,10 @@ __device__ void columns3r_tile(float2 *__restrict__ spec, int L, int ny, const f
     C y = C{0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < NH; ++i) {
-        if (i % CH == 0) qck[i / CH] = q;
+        if (i % CH == 0) {
+            qck[i / CH] = q;
+            __asm__ volatile("" ::: "memory"); // keep table loads near their use
+        }
         const float e = s * ct[i].D + ct[i].fp * q;
         const float gi = pivot_rcp(e + ct[i].fn);
         const float c = ct[i].fp * g;
@@ -363,6 +367,7 @@ __device__ void columns3r_tile(float2 *__restrict__ spec, int L, int ny, const f
         for (int bb = NB - 1; bb >= 0; --bb) {
             float gb[CH];
             float qq = qck[bb];
+            __asm__ volatile("" ::: "memory");
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 const int i = bb * CH + c;
@@ -412,6 +417,7 @@ __device__ void columns3r_tile(float2 *__restrict__ spec, int L, int ny, const f
     y = C{0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < NH; ++i) {
+        if (i % CH == 0) __asm__ volatile("" ::: "memory");
         const float e = s * ct[i].D + ct[i].fp * q;
         const float gi = pivot_rcp(e + ct[i].fn);
         const float c = ct[i].fp * g;
@@ -437,6 +443,147 @@ __device__ void columns3r_tile(float2 *__restrict__ spec, int L, int ny, const f
                     C{(v[i].x + raw[i].x) * ct[i].os, (v[i].y + raw[i].y) * ct[i].os};
         }
         if (half) *reinterpret_cast<C *>(base + cm.off) = C{xm.x * cm.os, xm.y * cm.os};
+    }
+}
+
+// ----------------------------------------------------------- split-lane sweep
+// As columns3_tile, with the real and imaginary parts of a column half in
+// two adjacent lanes (lane 2c + comp, comp 0: real, 1: imaginary): a wave
+// pair covers 32 columns, each lane holds NH real values, and both lanes of
+// a column compute the (real) pivots.  Half the registers per lane of the
+// complex form, for FP64 and for the refining FP32 form.  REFINE (FP32 only)
+// adds the refinement of columns3r_tile: FP64 residual from the FP64 table,
+// FP32 correction with the same elimination.  xa, xb, xe: LDS scratch of
+// 2 * 2 * 64 values each.
+template <typename T, int NH, bool REFINE>
+__device__ void columns3s_tile(cx_t<T> *__restrict__ spec, int L, int ny, const T *__restrict__ ax,
+                               const T *__restrict__ ay, const LevelCoef<T> *__restrict__ coef,
+                               const LevelCoef<double> *__restrict__ coef64,
+                               const double *__restrict__ ax64, const double *__restrict__ ay64,
+                               const int *__restrict__ maskcnt, long c0, long c1, long group, T (*xa)[2][64],
+                               T (*xb)[2][64], T (*xe)[2][64])
+{
+    constexpr int CH = NH < 8 ? NH : 8;
+    constexpr int NB = (NH + CH - 1) / CH;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int pair = w >> 1, half = w & 1;
+    const long col = c0 + (group * 2 + pair) * 32 + (lane >> 1);
+    const bool valid = col < c1;
+    const int kx = valid ? (int)(col / ny) : 1;
+    const int ky = valid ? (int)(col - (long)kx * ny) : 0;
+    const T s = ax[kx] + ay[ky];
+    bool store = valid;
+    if (maskcnt && valid) {
+        const int d = min(ky, ny - ky);
+        if (d < maskcnt[kx]) store = false;
+    }
+    char *base = reinterpret_cast<char *>(spec + (valid ? col : 0)) + (lane & 1) * sizeof(T);
+    const LevelCoef<T> *ct = coef + half * NH;
+    const LevelCoef<T> cm = coef[2 * NH];
+
+    T v[NH];
+    T raw[REFINE ? NH : 1];
+#pragma unroll
+    for (int i = 0; i < NH; ++i) {
+        const T x = *reinterpret_cast<const T *>(base + (ct[i].off < 0 ? cm.off : ct[i].off));
+        if constexpr (REFINE) raw[i] = x;
+        v[i] = x * ct[i].rs;
+    }
+    const T rawm = *reinterpret_cast<const T *>(base + cm.off);
+
+    T qck[NB];
+    T q = T(0), g = T(0), y = T(0);
+#pragma unroll
+    for (int i = 0; i < NH; ++i) {
+        if (i % CH == 0) {
+            qck[i / CH] = q;
+            __asm__ volatile("" ::: "memory"); // keep the table loads near their use
+        }
+        const T e = s * ct[i].D + ct[i].fp * q;
+        const T gi = pivot_rcp(e + ct[i].fn);
+        y = v[i] + (ct[i].fp * g) * y;
+        v[i] = y;
+        q = e * gi;
+        g = gi;
+    }
+    const T gl = ct[NH - 1].fn * g;
+    xa[pair][half][lane] = ct[NH - 1].fn * q;
+    xb[pair][half][lane] = gl * y;
+    __syncthreads();
+    const T den = (s * cm.D + xa[pair][0][lane]) + xa[pair][1][lane];
+    T xm = ((rawm * cm.rs + xb[pair][0][lane]) + xb[pair][1][lane]) / den;
+    auto backward = [&](T(&a)[NH], T xn) {
+#pragma unroll
+        for (int bb = NB - 1; bb >= 0; --bb) {
+            T gb[CH];
+            T qq = qck[bb];
+            __asm__ volatile("" ::: "memory");
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int i = bb * CH + c;
+                const T e = s * ct[i].D + ct[i].fp * qq;
+                const T gi = pivot_rcp(e + ct[i].fn);
+                gb[c] = gi;
+                qq = e * gi;
+            }
+#pragma unroll
+            for (int c = CH - 1; c >= 0; --c) {
+                const int i = bb * CH + c;
+                xn = gb[c] * (a[i] + ct[i].fn * xn);
+                a[i] = xn;
+            }
+        }
+    };
+    backward(v, xm);
+
+    if constexpr (REFINE) {
+        const LevelCoef<double> *ct64 = coef64 + half * NH;
+        const LevelCoef<double> cm64 = coef64[2 * NH];
+        const double s64 = ax64[kx] + ay64[ky];
+        xe[pair][half][lane] = v[NH - 1];
+        __syncthreads(); // also: every wave has read xb above
+        const double xlo = xe[pair][0][lane], xhi = xe[pair][1][lane];
+#pragma unroll
+        for (int i = 0; i < NH; ++i) {
+            const double fp = ct64[i].fp, fn = ct64[i].fn;
+            const double diag = s64 * ct64[i].D + fp + fn;
+            const double xp = i > 0 ? (double)v[i - 1] : 0.0;
+            const double xn = i + 1 < NH ? (double)v[i + 1] : (double)xm;
+            raw[i] = (T)(ct64[i].rs * (double)raw[i] - (diag * (double)v[i] - fp * xp - fn * xn));
+        }
+        const double diagm = s64 * cm64.D + cm64.fp + cm64.fn;
+        const T rhom = (T)(cm64.rs * (double)rawm -
+                           (diagm * (double)xm - cm64.fp * xlo - cm64.fn * xhi));
+        q = T(0);
+        g = T(0);
+        y = T(0);
+#pragma unroll
+        for (int i = 0; i < NH; ++i) {
+            if (i % CH == 0) __asm__ volatile("" ::: "memory");
+            const T e = s * ct[i].D + ct[i].fp * q;
+            const T gi = pivot_rcp(e + ct[i].fn);
+            y = raw[i] + (ct[i].fp * g) * y;
+            raw[i] = y;
+            q = e * gi;
+            g = gi;
+        }
+        xb[pair][half][lane] = gl * y;
+        __syncthreads();
+        const T dm = ((rhom + xb[pair][0][lane]) + xb[pair][1][lane]) / den;
+        backward(raw, dm);
+#pragma unroll
+        for (int i = 0; i < NH; ++i) v[i] += raw[i];
+        xm += dm;
+    }
+
+    if (store) {
+#pragma unroll
+        for (int i = 0; i < NH; ++i) {
+            const long long off = ct[i].off;
+            if (off >= 0) *reinterpret_cast<T *>(base + off) = v[i] * ct[i].os;
+        }
+        if (half) *reinterpret_cast<T *>(base + cm.off) = xm * cm.os;
     }
 }
 

@@ -114,7 +114,8 @@ __global__ __launch_bounds__(256) void k_columns(cx_t<T> *__restrict__ spec, int
                                                  const double *__restrict__ ay64,
                                                  const double *__restrict__ f64,
                                                  const double *__restrict__ D64,
-                                                 const double *__restrict__ rs64)
+                                                 const double *__restrict__ rs64, long c0,
+                                                 long c1)
 {
     __shared__ T sf[PS_MAX_NZ + 1], sD[PS_MAX_NZ], srs[PS_MAX_NZ], sos[PS_MAX_NZ];
     __shared__ double df[REFINE ? PS_MAX_NZ + 1 : 1], dD[REFINE ? PS_MAX_NZ : 1],
@@ -136,9 +137,8 @@ __global__ __launch_bounds__(256) void k_columns(cx_t<T> *__restrict__ spec, int
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int half = lane >> 5, comp = lane & 1, cl = (lane & 31) >> 1;
-    const long ncol = (long)L * ny;
-    const long col = (long)ny + ((long)blockIdx.x * 4 + wave) * 16 + cl;
-    const bool valid = col < ncol;
+    const long col = c0 + ((long)blockIdx.x * 4 + wave) * 16 + cl;
+    const bool valid = col < c1;
     const int kx = valid ? (int)(col / ny) : 1;
     const int ky = valid ? (int)(col - (long)kx * ny) : 0;
     const T s = ax[kx] + ay[ky];
@@ -318,7 +318,8 @@ __global__ __launch_bounds__(256) void k_columns2(cx_t<T> *__restrict__ spec, in
                                                   const T *__restrict__ Dg,
                                                   const T *__restrict__ rsg,
                                                   const T *__restrict__ osg,
-                                                  const int *__restrict__ maskcnt)
+                                                  const int *__restrict__ maskcnt, long c0,
+                                                  long c1)
 {
     using C = cx_t<T>;
     __shared__ T sf[PS_MAX_NZ + 1], sD[PS_MAX_NZ], srs[PS_MAX_NZ], sos[PS_MAX_NZ];
@@ -333,9 +334,8 @@ __global__ __launch_bounds__(256) void k_columns2(cx_t<T> *__restrict__ spec, in
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int half = lane >> 5, cl = lane & 31;
-    const long ncol = (long)L * ny;
-    const long col = (long)ny + ((long)blockIdx.x * 4 + wave) * 32 + cl;
-    const bool valid = col < ncol;
+    const long col = c0 + ((long)blockIdx.x * 4 + wave) * 32 + cl;
+    const bool valid = col < c1;
     const int kx = valid ? (int)(col / ny) : 1;
     const int ky = valid ? (int)(col - (long)kx * ny) : 0;
     const T s = ax[kx] + ay[ky];
@@ -380,11 +380,12 @@ __global__ __launch_bounds__(256) void k_columns3(cx_t<T> *__restrict__ spec, in
                                                   const T *__restrict__ ax,
                                                   const T *__restrict__ ay,
                                                   const LevelCoef<T> *__restrict__ coef,
-                                                  const int *__restrict__ maskcnt)
+                                                  const int *__restrict__ maskcnt, long c0,
+                                                  long c1)
 {
     __shared__ T xa[2][2][64];
     __shared__ cx_t<T> xb[2][2][64];
-    columns3_tile<T, NH, KEEPG>(spec, L, ny, ax, ay, coef, maskcnt, blockIdx.x, xa, xb);
+    columns3_tile<T, NH, KEEPG>(spec, L, ny, ax, ay, coef, maskcnt, c0, c1, blockIdx.x, xa, xb);
 }
 
 template <int NH>
@@ -395,12 +396,29 @@ __global__ __launch_bounds__(256) void k_columns3r(float2 *__restrict__ spec, in
                                                    const LevelCoef<double> *__restrict__ coef64,
                                                    const double *__restrict__ ax64,
                                                    const double *__restrict__ ay64,
-                                                   const int *__restrict__ maskcnt)
+                                                   const int *__restrict__ maskcnt, long c0,
+                                                   long c1)
 {
     __shared__ float xa[2][2][64];
     __shared__ float2 xb[2][2][64], xe[2][2][64];
-    columns3r_tile<NH>(spec, L, ny, ax, ay, coef, coef64, ax64, ay64, maskcnt, blockIdx.x, xa, xb,
-                       xe);
+    columns3r_tile<NH>(spec, L, ny, ax, ay, coef, coef64, ax64, ay64, maskcnt, c0, c1, blockIdx.x,
+                       xa, xb, xe);
+}
+
+template <typename T, int NH, bool REFINE>
+__global__ __launch_bounds__(256) void k_columns3s(cx_t<T> *__restrict__ spec, int L, int ny,
+                                                   const T *__restrict__ ax,
+                                                   const T *__restrict__ ay,
+                                                   const LevelCoef<T> *__restrict__ coef,
+                                                   const LevelCoef<double> *__restrict__ coef64,
+                                                   const double *__restrict__ ax64,
+                                                   const double *__restrict__ ay64,
+                                                   const int *__restrict__ maskcnt, long c0,
+                                                   long c1)
+{
+    __shared__ T xa[2][2][64], xb[2][2][64], xe[REFINE ? 2 : 1][2][64];
+    columns3s_tile<T, NH, REFINE>(spec, L, ny, ax, ay, coef, coef64, ax64, ay64, maskcnt, c0, c1,
+                                  blockIdx.x, xa, xb, xe);
 }
 
 // These few waves carry long dependent chains and usually share their SIMDs
@@ -457,38 +475,41 @@ template <typename T, int NH, bool REFINE>
 static hipError_t columns_nh(cx_t<T> *spec, int L, int ny, int nz, const T *rs, const T *os,
                              const int *maskcnt, const Tables<T> &tb, const double *ax64,
                              const double *ay64, const double *f64, const double *D64,
-                             const double *rs64, hipStream_t st)
+                             const double *rs64, long c0, long c1, hipStream_t st)
 {
     constexpr int CH = NH < 8 ? NH : 8;
-    const long ncols = (long)(L - 1) * ny;
+    const long ncols = c1 - c0;
     if (ncols <= 0) return hipSuccess;
     const long grid = (ncols + 63) / 64;
     hipLaunchKernelGGL((k_columns<T, NH, CH, REFINE>), dim3((unsigned)grid), dim3(256), 0, st, spec,
                        L, ny, nz, tb.ax, tb.ay, tb.f, tb.D, rs, os, maskcnt, ax64, ay64, f64, D64,
-                       rs64);
+                       rs64, c0, c1);
     return hipGetLastError();
 }
 
 template <typename T, int NH, bool KEEPG>
 static hipError_t columns2_nh(cx_t<T> *spec, int L, int ny, int nz, const T *rs, const T *os,
-                              const int *maskcnt, const Tables<T> &tb, hipStream_t st)
+                              const int *maskcnt, const Tables<T> &tb, long c0, long c1,
+                              hipStream_t st)
 {
     constexpr int CH = NH < 8 ? NH : 8;
-    const long ncols = (long)(L - 1) * ny;
+    const long ncols = c1 - c0;
     if (ncols <= 0) return hipSuccess;
     const long grid = (ncols + 127) / 128;
     hipLaunchKernelGGL((k_columns2<T, NH, CH, KEEPG>), dim3((unsigned)grid), dim3(256), 0, st,
-                       spec, L, ny, nz, tb.ax, tb.ay, tb.f, tb.D, rs, os, maskcnt);
+                       spec, L, ny, nz, tb.ax, tb.ay, tb.f, tb.D, rs, os, maskcnt, c0, c1);
     return hipGetLastError();
 }
 
 template <typename T, bool KEEPG>
 static hipError_t columns2_dispatch(cx_t<T> *spec, int L, int ny, int nz, const T *rs, const T *os,
-                                    const int *maskcnt, const Tables<T> &tb, hipStream_t st)
+                                    const int *maskcnt, const Tables<T> &tb, long c0, long c1,
+                                    hipStream_t st)
 {
     const int need = nz / 2;
 #define PS_NH(N)                                                                                   \
-    if (need <= N) return columns2_nh<T, N, KEEPG>(spec, L, ny, nz, rs, os, maskcnt, tb, st);
+    if (need <= N)                                                                                 \
+        return columns2_nh<T, N, KEEPG>(spec, L, ny, nz, rs, os, maskcnt, tb, c0, c1, st);
     PS_NH(1) PS_NH(2) PS_NH(4) PS_NH(8) PS_NH(16) PS_NH(32) PS_NH(64) PS_NH(128)
 #undef PS_NH
     return hipErrorInvalidValue;
@@ -496,26 +517,29 @@ static hipError_t columns2_dispatch(cx_t<T> *spec, int L, int ny, int nz, const 
 
 template <typename T, int NH, bool KEEPG>
 static hipError_t columns3_nh(cx_t<T> *spec, int L, int ny, int nz, int adjoint,
-                              const int *maskcnt, const Tables<T> &tb, hipStream_t st)
+                              const int *maskcnt, const Tables<T> &tb, long c0, long c1,
+                              hipStream_t st)
 {
     (void)nz;
-    const long ncols = (long)(L - 1) * ny;
+    const long ncols = c1 - c0;
     if (ncols <= 0) return hipSuccess;
     const long grid = (ncols + 127) / 128;
     const LevelCoef<T> *ct = reinterpret_cast<const LevelCoef<T> *>(
         adjoint ? tb.coef_adj : tb.coef_fwd);
     hipLaunchKernelGGL((k_columns3<T, NH, KEEPG>), dim3((unsigned)grid), dim3(256), 0, st, spec, L,
-                       ny, tb.ax, tb.ay, ct, maskcnt);
+                       ny, tb.ax, tb.ay, ct, maskcnt, c0, c1);
     return hipGetLastError();
 }
 
 template <typename T, bool KEEPG>
 static hipError_t columns3_dispatch(cx_t<T> *spec, int L, int ny, int nz, int adjoint,
-                                    const int *maskcnt, const Tables<T> &tb, hipStream_t st)
+                                    const int *maskcnt, const Tables<T> &tb, long c0, long c1,
+                                    hipStream_t st)
 {
     const int need = nz / 2;
 #define PS_NH(N)                                                                                   \
-    if (need <= N) return columns3_nh<T, N, KEEPG>(spec, L, ny, nz, adjoint, maskcnt, tb, st);
+    if (need <= N)                                                                                 \
+        return columns3_nh<T, N, KEEPG>(spec, L, ny, nz, adjoint, maskcnt, tb, c0, c1, st);
     PS_NH(1) PS_NH(2) PS_NH(4) PS_NH(8) PS_NH(16) PS_NH(32) PS_NH(64) PS_NH(128)
 #undef PS_NH
     return hipErrorInvalidValue;
@@ -523,26 +547,57 @@ static hipError_t columns3_dispatch(cx_t<T> *spec, int L, int ny, int nz, int ad
 
 template <int NH>
 static hipError_t columns3r_nh(float2 *spec, int L, int ny, int adjoint, const int *maskcnt,
-                               const Tables<float> &tb, const Tables<double> &t64, hipStream_t st)
+                               const Tables<float> &tb, const Tables<double> &t64, long c0,
+                               long c1, hipStream_t st)
 {
-    const long ncols = (long)(L - 1) * ny;
+    const long ncols = c1 - c0;
     if (ncols <= 0) return hipSuccess;
     const long grid = (ncols + 127) / 128;
     const auto *ct = reinterpret_cast<const LevelCoef<float> *>(adjoint ? tb.coef_adj : tb.coef_fwd);
     const auto *c64 =
         reinterpret_cast<const LevelCoef<double> *>(adjoint ? t64.coef_adj : t64.coef_fwd);
     hipLaunchKernelGGL((k_columns3r<NH>), dim3((unsigned)grid), dim3(256), 0, st, spec, L, ny,
-                       tb.ax, tb.ay, ct, c64, t64.ax, t64.ay, maskcnt);
+                       tb.ax, tb.ay, ct, c64, t64.ax, t64.ay, maskcnt, c0, c1);
     return hipGetLastError();
 }
 
 static hipError_t columns3r_dispatch(float2 *spec, int L, int ny, int nz, int adjoint,
                                      const int *maskcnt, const Tables<float> &tb,
-                                     const Tables<double> &t64, hipStream_t st)
+                                     const Tables<double> &t64, long c0, long c1, hipStream_t st)
 {
     const int need = nz / 2;
 #define PS_NH(N)                                                                                   \
-    if (need <= N) return columns3r_nh<N>(spec, L, ny, adjoint, maskcnt, tb, t64, st);
+    if (need <= N) return columns3r_nh<N>(spec, L, ny, adjoint, maskcnt, tb, t64, c0, c1, st);
+    PS_NH(1) PS_NH(2) PS_NH(4) PS_NH(8) PS_NH(16) PS_NH(32) PS_NH(64) PS_NH(128)
+#undef PS_NH
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int NH, bool REFINE>
+static hipError_t columns3s_nh(cx_t<T> *spec, int L, int ny, int adjoint, const int *maskcnt,
+                               const Tables<T> &tb, const Tables<double> &t64, long c0, long c1,
+                               hipStream_t st)
+{
+    const long ncols = c1 - c0;
+    if (ncols <= 0) return hipSuccess;
+    const long grid = (ncols + 63) / 64;
+    const auto *ct = reinterpret_cast<const LevelCoef<T> *>(adjoint ? tb.coef_adj : tb.coef_fwd);
+    const auto *c64 =
+        reinterpret_cast<const LevelCoef<double> *>(adjoint ? t64.coef_adj : t64.coef_fwd);
+    hipLaunchKernelGGL((k_columns3s<T, NH, REFINE>), dim3((unsigned)grid), dim3(256), 0, st, spec, L,
+                       ny, tb.ax, tb.ay, ct, c64, t64.ax, t64.ay, maskcnt, c0, c1);
+    return hipGetLastError();
+}
+
+template <typename T, bool REFINE>
+static hipError_t columns3s_dispatch(cx_t<T> *spec, int L, int ny, int nz, int adjoint,
+                                     const int *maskcnt, const Tables<T> &tb,
+                                     const Tables<double> &t64, long c0, long c1, hipStream_t st)
+{
+    const int need = nz / 2;
+#define PS_NH(N)                                                                                   \
+    if (need <= N)                                                                                 \
+        return columns3s_nh<T, N, REFINE>(spec, L, ny, adjoint, maskcnt, tb, t64, c0, c1, st);
     PS_NH(1) PS_NH(2) PS_NH(4) PS_NH(8) PS_NH(16) PS_NH(32) PS_NH(64) PS_NH(128)
 #undef PS_NH
     return hipErrorInvalidValue;
@@ -552,13 +607,13 @@ template <typename T, bool REFINE>
 static hipError_t columns_dispatch(cx_t<T> *spec, int L, int ny, int nz, const T *rs, const T *os,
                                    const int *maskcnt, const Tables<T> &tb, const double *ax64,
                                    const double *ay64, const double *f64, const double *D64,
-                                   const double *rs64, hipStream_t st)
+                                   const double *rs64, long c0, long c1, hipStream_t st)
 {
     const int need = nz / 2;
 #define PS_NH(N)                                                                                   \
     if (need <= N)                                                                                 \
         return columns_nh<T, N, REFINE>(spec, L, ny, nz, rs, os, maskcnt, tb, ax64, ay64, f64,     \
-                                        D64, rs64, st);
+                                        D64, rs64, c0, c1, st);
     PS_NH(1) PS_NH(2) PS_NH(4) PS_NH(8) PS_NH(16) PS_NH(32) PS_NH(64) PS_NH(128)
 #undef PS_NH
     return hipErrorInvalidValue;
@@ -568,43 +623,56 @@ static hipError_t columns_dispatch(cx_t<T> *spec, int L, int ny, int nz, const T
 // 1 = two lanes per column, pivots recomputed, 2 = two lanes, pivots kept,
 // 3 = halves in separate waves with scalar coefficient tables, pivots
 // recomputed, 4 = as 3 with pivots kept.
+// 5 = as 3 with the real and imaginary parts in two lanes.
 // The in-register refinement (FP32 only) uses variant 0's refining kernel
-// for variants 0-2 and the refining uniform-half kernel for 3-4.
+// for variants 0-2, the refining uniform-half kernel for 3-4 and the
+// refining split-lane kernel for 5.
 template <typename T>
 hipError_t launch_columns_impl(cx_t<T> *spec, int nx, int ny, int nz, int adjoint, int refine,
                                const int *maskcnt, const Tables<T> &tb, const Tables<double> *t64,
-                               hipStream_t st, int variant)
+                               hipStream_t st, int variant, int kxlo, int kxhi)
 {
     const int L = nx / 2;
+    if (kxlo < 1) kxlo = 1;
+    if (kxhi > L) kxhi = L;
+    if (kxhi <= kxlo) return hipSuccess;
+    const long c0 = (long)kxlo * ny, c1 = (long)kxhi * ny;
     const T *rs = adjoint ? tb.rs_adj : tb.rs_fwd;
     const T *os = adjoint ? tb.os_adj : nullptr;
     if constexpr (std::is_same<T, float>::value) {
+        if (refine && variant == 5)
+            return columns3s_dispatch<float, true>(spec, L, ny, nz, adjoint, maskcnt, tb, *t64, c0,
+                                                   c1, st);
         if (refine && variant >= 3)
-            return columns3r_dispatch(spec, L, ny, nz, adjoint, maskcnt, tb, *t64, st);
+            return columns3r_dispatch(spec, L, ny, nz, adjoint, maskcnt, tb, *t64, c0, c1, st);
         if (refine) {
             const double *rs64 = adjoint ? t64->rs_adj : t64->rs_fwd;
             return columns_dispatch<float, true>(spec, L, ny, nz, rs, os, maskcnt, tb, t64->ax,
-                                                 t64->ay, t64->f, t64->D, rs64, st);
+                                                 t64->ay, t64->f, t64->D, rs64, c0, c1, st);
         }
     }
     if (variant == 1)
-        return columns2_dispatch<T, false>(spec, L, ny, nz, rs, os, maskcnt, tb, st);
+        return columns2_dispatch<T, false>(spec, L, ny, nz, rs, os, maskcnt, tb, c0, c1, st);
     if (variant == 2)
-        return columns2_dispatch<T, true>(spec, L, ny, nz, rs, os, maskcnt, tb, st);
+        return columns2_dispatch<T, true>(spec, L, ny, nz, rs, os, maskcnt, tb, c0, c1, st);
     if (variant == 3)
-        return columns3_dispatch<T, false>(spec, L, ny, nz, adjoint, maskcnt, tb, st);
+        return columns3_dispatch<T, false>(spec, L, ny, nz, adjoint, maskcnt, tb, c0, c1, st);
     if (variant == 4)
-        return columns3_dispatch<T, true>(spec, L, ny, nz, adjoint, maskcnt, tb, st);
+        return columns3_dispatch<T, true>(spec, L, ny, nz, adjoint, maskcnt, tb, c0, c1, st);
+    if (variant == 5)
+        return columns3s_dispatch<T, false>(spec, L, ny, nz, adjoint, maskcnt, tb, *t64, c0, c1,
+                                            st);
     return columns_dispatch<T, false>(spec, L, ny, nz, rs, os, maskcnt, tb, nullptr, nullptr,
-                                      nullptr, nullptr, nullptr, st);
+                                      nullptr, nullptr, nullptr, c0, c1, st);
 }
 
 template hipError_t launch_columns_impl<float>(cx_t<float> *, int, int, int, int, int, const int *,
                                                const Tables<float> &, const Tables<double> *,
-                                               hipStream_t, int);
+                                               hipStream_t, int, int, int);
 template hipError_t launch_columns_impl<double>(cx_t<double> *, int, int, int, int, int,
                                                 const int *, const Tables<double> &,
-                                                const Tables<double> *, hipStream_t, int);
+                                                const Tables<double> *, hipStream_t, int, int,
+                                                int);
 
 // FP64 columns: the packed kx = 0 row, the mean column and the near-singular
 // columns, one lane per task (k_special_seq).
