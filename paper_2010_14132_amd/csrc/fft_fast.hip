@@ -257,7 +257,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
         inr[i] = x.x;
         ini[i] = x.y;
     }
-    C xa[R2], xb[R2];
+    C xa[R2];
 #pragma unroll
     for (int i = 0; i < R2; ++i) {
         const int e = threadIdx.x + NT * i;
@@ -265,11 +265,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < R2; ++q) {
-        const int k = t + R1 * q;
-        xa[q].x = lds[stage_idx<R1, ROWS>(k, r)];
-        xb[q].x = lds[stage_idx<R1, ROWS>((L - k) & (L - 1), r)];
-    }
+    for (int q = 0; q < R2; ++q) xa[q].x = lds[stage_idx<R1, ROWS>(t + R1 * q, r)];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < R2; ++i) {
@@ -278,20 +274,24 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < R2; ++q) {
-        const int k = t + R1 * q;
-        xa[q].y = lds[stage_idx<R1, ROWS>(k, r)];
-        xb[q].y = lds[stage_idx<R1, ROWS>((L - k) & (L - 1), r)];
-    }
+    for (int q = 0; q < R2; ++q) xa[q].y = lds[stage_idx<R1, ROWS>(t + R1 * q, r)];
+    // X_{L-k} for k = t + R1 q: lane R1 - t of the row, slot R2 - 1 - q (for
+    // t = 0: this lane, slot (R2 - q) mod R2)
+    const int lane = threadIdx.x & 63;
+    const int src_lane = lane - t + ((R1 - t) & (R1 - 1));
     C v[R2], w[R2];
 #pragma unroll
     for (int q = 0; q < R2; ++q) {
         const int k = t + R1 * q;
+        C xb;
+        xb.x = __shfl(xa[R2 - 1 - q].x, src_lane, 64);
+        xb.y = __shfl(xa[R2 - 1 - q].y, src_lane, 64);
+        if (t == 0) xb = xa[(R2 - q) & (R2 - 1)];
         if (k == 0) {
             const T x0 = xa[q].x, xl = xa[q].y;
             v[q] = C{x0 + xl, x0 - xl};
         } else {
-            const C xc = cconj(xb[q]);
+            const C xc = cconj(xb);
             const C sm = cadd(xa[q], xc);
             const C dw = cmul(csub(xa[q], xc), cconj(tws[k]));
             v[q] = C{sm.x - dw.y, sm.y + dw.x};
