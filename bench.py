@@ -53,6 +53,44 @@ def kernel_bytes_per_point(name: str, e: int, nx: int, accumulate: bool = False)
             "inv_x": 2.0 * e}.get(name, 0.0)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_solve_1024x1024x128.txt")
+
+
+def kernel_sources_digest() -> str:
+    """SHA-256 (first 16 hex digits) of the HIP sources, in name order: a
+    counter summary taken on other sources no longer describes the kernels."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2010_14132_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(form: str, kernel: str):
+    """HBM bytes per solve (FETCH_SIZE + WRITE_SIZE, each scaled by the
+    factor a plain device copy of known size gives) of one kernel of one
+    precision form, from the committed rocprofv3 counter summary, or None if
+    there is none for it or it was taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    digest, found = None, None
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            w = line.split()
+            if len(w) >= 2 and w[0] == "sources":
+                digest = w[1]
+            if len(w) >= 4 and w[0] == "form" and w[1] == form and w[2] == "kernel" and w[3] == kernel:
+                kv = dict(zip(w[4::2], w[5::2]))
+                found = float(kv["fetch_bytes_per_solve"]) + float(kv["write_bytes_per_solve"])
+    if digest != kernel_sources_digest():
+        return None
+    return found
+
+
 def sampled_oracle_error(p: np.ndarray, b: np.ndarray, g, modes) -> float:
     """Relative error of sampled wavenumber columns against the oracle's
     column solve of a plain DFT of the input (test infrastructure)."""
@@ -261,8 +299,13 @@ def main():
         "forms": results,
         "errors": errs,
         "kernels": kernels,
+        # achieved: algorithmic bytes of the dominant kernel per solve over its
+        # event-timed duration per solve (profiled pass of `steps` solves);
+        # traffic: measured HBM bytes per solve of that kernel
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.precision, dom),
+                     "algorithmic_bytes": dk["alg_bytes_per_solve"]},
     }
     if copy_gbs is not None:
         line["device_copy_gbs"] = copy_gbs

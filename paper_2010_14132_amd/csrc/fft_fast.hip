@@ -157,10 +157,14 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
 
     four_step<R1, R2, -1>(v, w, t, lds + r * S, tw4);
 
-    // split: X_k = (Z_k + Zc)/2 + W_nx^k (Z_k - Zc)/(2i), Zc = conj Z_{L-k}
+    // split: X_k = (Z_k + Zc)/2 + W_nx^k (Z_k - Zc)/(2i), Zc = conj Z_{L-k};
+    // the real parts go straight to the [kx][row] staging in LDS, the
+    // imaginary parts wait in registers for the second staging round
     const int lane = threadIdx.x & 63;
     const int src_lane = lane - t + ((R1 - t) & (R1 - 1));
-    C X[R2];
+    T Xi[R2];
+    T outr[R2], outi[R2];
+    __syncthreads(); // the transform's last LDS reads are done
 #pragma unroll
     for (int j = 0; j < J; ++j) {
 #pragma unroll
@@ -174,25 +178,21 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
             const C zk = w[j * R1 + k1];
             const int k = (t + R1 * j) + R2 * k1;
             const C zc = cconj(zp);
+            C X;
             if (k == 0) {
-                X[j * R1 + k1] = C{zk.x + zk.y, zk.x - zk.y};
+                X = C{zk.x + zk.y, zk.x - zk.y};
             } else {
                 const C e = C{T(0.5) * (zk.x + zc.x), T(0.5) * (zk.y + zc.y)};
                 const C d = csub(zk, zc);
                 const C o = C{T(0.5) * d.y, T(-0.5) * d.x};
-                X[j * R1 + k1] = cadd(e, cmul(o, tws[k]));
+                X = cadd(e, cmul(o, tws[k]));
             }
+            lds[stage_idx<R1, ROWS>(k, r)] = X.x;
+            Xi[j * R1 + k1] = X.y;
         }
     }
 
     // transposed store: [row][kx] -> spec[level][kx][j]
-    T outr[R2], outi[R2];
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < J; ++j)
-#pragma unroll
-        for (int k1 = 0; k1 < R1; ++k1)
-            lds[stage_idx<R1, ROWS>((t + R1 * j) + R2 * k1, r)] = X[j * R1 + k1].x;
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < R2; ++i) {
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
     for (int j = 0; j < J; ++j)
 #pragma unroll
         for (int k1 = 0; k1 < R1; ++k1)
-            lds[stage_idx<R1, ROWS>((t + R1 * j) + R2 * k1, r)] = X[j * R1 + k1].y;
+            lds[stage_idx<R1, ROWS>((t + R1 * j) + R2 * k1, r)] = Xi[j * R1 + k1];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < R2; ++i) {
