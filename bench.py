@@ -219,7 +219,8 @@ def main():
         results[form] = {"ms_per_solve": ms, "solves_per_s": 1e3 / ms, "mpts_per_s": N / ms / 1e3,
                          "fp64_columns": plan.info()["fp64_columns"], "steps": steps,
                          "kernels": {k: plan.info()[k] for k in
-                                     ("fft_variant_x", "fft_variant_y", "column_variant")}}
+                                     ("fft_variant_x", "fft_variant_xi", "fft_variant_y",
+                                      "column_variant", "chunks")}}
         outputs[form] = out
         print("bench: %-8s %.4f ms/solve" % (form, ms), file=sys.stderr, flush=True)
         # per-kernel event timing (a separate pass: events add a little per launch)

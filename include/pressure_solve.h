@@ -137,11 +137,12 @@ typedef struct ps_plan_info {
     int nx, ny, nz, precision;
     int fp64_columns;     /* near-singular columns solved in FP64 (FP32 forms) */
     double tau;           /* threshold in effect */
-    int fft_variant_x;    /* transform kernels chosen by planning / autotuning */
-    int fft_variant_y;
+    int fft_variant_x;    /* transform kernels chosen by planning / autotuning: */
+    int fft_variant_y;    /* forward x, y, ... */
     size_t spectrum_elems;/* complex elements of the spectral layout, nz*(nx/2)*ny */
     int column_variant;   /* column-solve kernel chosen by planning / autotuning */
     int chunks;           /* kx ranges the y / column / y passes are split into */
+    int fft_variant_xi;   /* ... and backward x */
 } ps_plan_info;
 
 int ps_plan_query(const ps_plan *plan, ps_plan_info *info);
@@ -153,9 +154,11 @@ int ps_plan_query(const ps_plan *plan, ps_plan_info *info);
  * nz, precision) for the life of the process -- a later autotune of an equal
  * plan just applies them -- and can be saved to / loaded from a text file
  * (one line per entry: arch nx ny nz precision x_variant y_variant
- * column_variant [fp64_beside [chunks]]: fp64_beside 1 when the FP64 columns
- * run on a second stream beside the main column kernel, chunks the number of
- * kx ranges the y / column / y passes are taken in; both default to 1).
+ * column_variant [fp64_beside [chunks [xi_variant]]]: fp64_beside 1 when the
+ * FP64 columns run on a second stream beside the main column kernel, chunks
+ * the number of kx ranges the y / column / y passes are taken in, both
+ * defaulting to 1; xi_variant the backward x pass's, defaulting to
+ * x_variant).
  * Synchronises. */
 int ps_plan_autotune(ps_plan *plan, int reps);
 int ps_tune_cache_save(const char *path);

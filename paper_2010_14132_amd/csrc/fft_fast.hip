@@ -79,7 +79,24 @@ __global__ __launch_bounds__(NT) void k_fft_y_fast(cx_t<T> *__restrict__ spec, i
 // f_{k-1/2}/D_{k-1}, (f_{k+1/2}+f_{k-1/2})/D_k); zero at the ends.  The x
 // neighbours x_{2n-1} and x_{2n+2} of the pair z_n = (x_{2n}, x_{2n+1}) come
 // from the neighbouring lanes of the row.
-template <typename T, int R1, int R2, int ROWS, bool RES>
+// PAIR (R1 = 2 R2): the row transform is four_step_pair, whose output slot
+// kk of lane t = 2m + h is X[m + R2 kk + R2^2 h].
+template <int R1, int R2, bool PAIR> __device__ __forceinline__ int out_index(int t, int i)
+{
+    if constexpr (PAIR)
+        return (t >> 1) + R2 * i + R2 * R2 * (t & 1);
+    else
+        return (t + R1 * (i / R1)) + R2 * (i % R1);
+}
+template <int R1, int R2, typename T, bool PAIR> constexpr int row_stride()
+{
+    if constexpr (PAIR)
+        return R2 * (R1 + 2);
+    else
+        return four_step_stride<R1, R2, T>();
+}
+
+template <typename T, int R1, int R2, int ROWS, bool RES, bool PAIR = false>
 __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
                                                       cx_t<T> *__restrict__ spec,
                                                       double *__restrict__ rowsum, int ny,
@@ -91,7 +108,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
                                                       int korder)
 {
     using C = cx_t<T>;
-    constexpr int L = R1 * R2, NT = ROWS * R1, J = R2 / R1, S = four_step_stride<R1, R2, T>();
+    constexpr int L = R1 * R2, NT = ROWS * R1, S = row_stride<R1, R2, T, PAIR>();
     constexpr int A = ROWS * S, B = L * ROWS;
     __shared__ T lds[A > B ? A : B];
     const int r = threadIdx.x / R1, t = threadIdx.x - r * R1;
@@ -100,7 +117,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
     const long g = g0 + r;
     const bool ok = g < nrows;
     const C *src = reinterpret_cast<const C *>(in) + (ok ? g : 0) * (long)L;
-    C v[R2], w[R2];
+    C v[R2], w[PAIR ? 1 : R2];
     double s = 0.0;
     if constexpr (RES) {
         const long gg = ok ? g : 0;
@@ -155,41 +172,57 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
     for (int o = R1 / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if (ok && t == 0) rowsum[g] = s;
 
-    four_step<R1, R2, -1>(v, w, t, lds + r * S, tw4);
+    if constexpr (PAIR)
+        four_step_pair<R1, R2, -1>(v, t, lds + r * S, tw4);
+    else
+        four_step<R1, R2, -1>(v, w, t, lds + r * S, tw4);
+    C *Z = PAIR ? v : w;
 
     // split: X_k = (Z_k + Zc)/2 + W_nx^k (Z_k - Zc)/(2i), Zc = conj Z_{L-k};
     // the real parts go straight to the [kx][row] staging in LDS, the
-    // imaginary parts wait in registers for the second staging round
+    // imaginary parts wait in registers for the second staging round.
+    // Z_{L-k} of slot i sits in lane src_lane, slot R2 - 1 - i (PAIR: lane
+    // R1 + 1 - t; the lanes of pair 0 take lane t ^ 1, slot R2 - i); for
+    // t = 0 of the plain form in this lane's own registers.
     const int lane = threadIdx.x & 63;
-    const int src_lane = lane - t + ((R1 - t) & (R1 - 1));
+    const int src_lane = PAIR ? lane - t + ((R1 + 1 - t) & (R1 - 1))
+                              : lane - t + ((R1 - t) & (R1 - 1));
     T Xi[R2];
     T outr[R2], outi[R2];
     __syncthreads(); // the transform's last LDS reads are done
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-#pragma unroll
-        for (int k1 = 0; k1 < R1; ++k1) {
+    for (int i = 0; i < R2; ++i) {
+        C zp;
+        if constexpr (PAIR) {
+            zp.x = __shfl(Z[R2 - 1 - i].x, src_lane, 64);
+            zp.y = __shfl(Z[R2 - 1 - i].y, src_lane, 64);
+            C zq;
+            zq.x = __shfl_xor(Z[(R2 - i) & (R2 - 1)].x, 1, 64);
+            zq.y = __shfl_xor(Z[(R2 - i) & (R2 - 1)].y, 1, 64);
+            if (t < 2) zp = i == 0 ? Z[0] : zq;
+        } else {
+            constexpr int J = R2 / R1;
+            const int j = i / R1, k1 = i % R1;
             const int other = (J - 1 - j) * R1 + (R1 - 1 - k1);
             const int own = j == 0 ? ((R1 - k1) & (R1 - 1)) : (J - j) * R1 + (R1 - 1 - k1);
-            C zp;
-            zp.x = __shfl(w[other].x, src_lane, 64);
-            zp.y = __shfl(w[other].y, src_lane, 64);
-            if (t == 0) zp = w[own];
-            const C zk = w[j * R1 + k1];
-            const int k = (t + R1 * j) + R2 * k1;
-            const C zc = cconj(zp);
-            C X;
-            if (k == 0) {
-                X = C{zk.x + zk.y, zk.x - zk.y};
-            } else {
-                const C e = C{T(0.5) * (zk.x + zc.x), T(0.5) * (zk.y + zc.y)};
-                const C d = csub(zk, zc);
-                const C o = C{T(0.5) * d.y, T(-0.5) * d.x};
-                X = cadd(e, cmul(o, tws[k]));
-            }
-            lds[stage_idx<R1, ROWS>(k, r)] = X.x;
-            Xi[j * R1 + k1] = X.y;
+            zp.x = __shfl(Z[other].x, src_lane, 64);
+            zp.y = __shfl(Z[other].y, src_lane, 64);
+            if (t == 0) zp = Z[own];
         }
+        const C zk = Z[i];
+        const int k = out_index<R1, R2, PAIR>(t, i);
+        const C zc = cconj(zp);
+        C X;
+        if (k == 0) {
+            X = C{zk.x + zk.y, zk.x - zk.y};
+        } else {
+            const C e = C{T(0.5) * (zk.x + zc.x), T(0.5) * (zk.y + zc.y)};
+            const C d = csub(zk, zc);
+            const C o = C{T(0.5) * d.y, T(-0.5) * d.x};
+            X = cadd(e, cmul(o, tws[k]));
+        }
+        lds[stage_idx<R1, ROWS>(k, r)] = X.x;
+        Xi[i] = X.y;
     }
 
     // transposed store: [row][kx] -> spec[level][kx][j]
@@ -201,10 +234,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < J; ++j)
-#pragma unroll
-        for (int k1 = 0; k1 < R1; ++k1)
-            lds[stage_idx<R1, ROWS>((t + R1 * j) + R2 * k1, r)] = Xi[j * R1 + k1];
+    for (int i = 0; i < R2; ++i) lds[stage_idx<R1, ROWS>(out_index<R1, R2, PAIR>(t, i), r)] = Xi[i];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < R2; ++i) {
@@ -227,7 +257,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
 // Gathers ROWS rows of the transposed spectrum through LDS, undoes the
 // packing, Z_k = (X_k + conj X_{L-k}) + i W_nx^{-k} (X_k - conj X_{L-k}),
 // transforms backwards and stores real rows (optionally accumulated).
-template <typename T, int R1, int R2, int ROWS>
+template <typename T, int R1, int R2, int ROWS, bool PAIR = false>
 __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict__ spec,
                                                       T *__restrict__ out, int ny, int nrows,
                                                       int accumulate,
@@ -235,7 +265,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
                                                       const cx_t<T> *__restrict__ tws, int swz)
 {
     using C = cx_t<T>;
-    constexpr int L = R1 * R2, NT = ROWS * R1, J = R2 / R1, S = four_step_stride<R1, R2, T>();
+    constexpr int L = R1 * R2, NT = ROWS * R1, S = row_stride<R1, R2, T, PAIR>();
     constexpr int A = ROWS * S, B = L * ROWS;
     __shared__ T lds[A > B ? A : B];
     const int r = threadIdx.x / R1, t = threadIdx.x - r * R1;
@@ -279,7 +309,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
     // t = 0: this lane, slot (R2 - q) mod R2)
     const int lane = threadIdx.x & 63;
     const int src_lane = lane - t + ((R1 - t) & (R1 - 1));
-    C v[R2], w[R2];
+    C v[R2], w[PAIR ? 1 : R2];
 #pragma unroll
     for (int q = 0; q < R2; ++q) {
         const int k = t + R1 * q;
@@ -298,18 +328,20 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
         }
     }
     __syncthreads();
-    four_step<R1, R2, 1>(v, w, t, lds + r * S, tw4);
+    if constexpr (PAIR)
+        four_step_pair<R1, R2, 1>(v, t, lds + r * S, tw4);
+    else
+        four_step<R1, R2, 1>(v, w, t, lds + r * S, tw4);
+    C *Z = PAIR ? v : w;
     if (ok) {
         C *dst = reinterpret_cast<C *>(out) + g * (long)L;
 #pragma unroll
-        for (int j = 0; j < J; ++j)
-#pragma unroll
-            for (int k1 = 0; k1 < R1; ++k1) {
-                const int n = (t + R1 * j) + R2 * k1;
-                C val = w[j * R1 + k1];
-                if (accumulate) val = cadd(val, dst[n]);
-                dst[n] = val;
-            }
+        for (int i = 0; i < R2; ++i) {
+            const int n = out_index<R1, R2, PAIR>(t, i);
+            C val = Z[i];
+            if (accumulate) val = cadd(val, dst[n]);
+            dst[n] = val;
+        }
     }
 }
 
@@ -317,11 +349,11 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
 // Rows per block of the x passes: 128-byte runs of the transposed layout
 // (16 FP32 or 8 FP64 complex values), halved until the LDS buffer fits 64 KiB;
 // WIDE: 256-byte runs within 128 KiB.
-template <typename T, int R1, int R2, bool WIDE> constexpr int x_rows()
+template <typename T, int R1, int R2, bool WIDE, bool PAIR = false> constexpr int x_rows()
 {
     int rows = (sizeof(T) == 8 ? 8 : 16) * (WIDE ? 2 : 1);
     while (rows > 1) {
-        const int a = rows * four_step_stride<R1, R2, T>(), b = R1 * R2 * rows;
+        const int a = rows * row_stride<R1, R2, T, PAIR>(), b = R1 * R2 * rows;
         if ((a > b ? a : b) * (int)sizeof(T) <= (WIDE ? 131072 : 65536)) break;
         rows /= 2;
     }
@@ -348,6 +380,7 @@ static hipError_t y_fast(cx_t<T> *spec, int nrows, int dir, const cx_t<T> *tw4, 
 
 bool fast_length(int L) { return L == 16 || L == 32 || L == 64 || L == 128 || L == 256 || L == 512 || L == 1024; }
 int fast_r1(int L) { return L <= 32 ? 4 : L <= 128 ? 8 : L <= 512 ? 16 : 32; }
+bool pair_length(int L) { return L == 32 || L == 128 || L == 512; }
 
 #define PS_FAST_SWITCH(L, F)                                                                       \
     switch (L) {                                                                                   \
@@ -395,14 +428,41 @@ static hipError_t r2c_fast_rows(const T *in, cx_t<T> *spec, double *rowsum, int 
     return hipGetLastError();
 }
 
+// The row transform with twice the lanes (four_step_pair) for L = 2 s^2,
+// whose plain split is (s, 2 s).
+template <typename T, int R1, int R2>
+static hipError_t r2c_pair(const T *in, cx_t<T> *spec, double *rowsum, int ny, int nz,
+                           const cx_t<T> *tw4, const cx_t<T> *tws, const T *pres, double idx2,
+                           double idy2, const double *rc, hipStream_t st)
+{
+    constexpr int ROWS = x_rows<T, R2, R1, false, true>();
+    const int nrows = ny * nz;
+    const int grid = (nrows + ROWS - 1) / ROWS;
+    const int korder = pres && ny % ROWS == 0;
+    if (pres)
+        hipLaunchKernelGGL((k_r2c_fast<T, R2, R1, ROWS, true, true>), dim3(grid), dim3(ROWS * R2), 0,
+                           st, in, spec, rowsum, ny, nrows, tw4, tws, pres, nz, idx2, idy2, rc, 1,
+                           korder);
+    else
+        hipLaunchKernelGGL((k_r2c_fast<T, R2, R1, ROWS, false, true>), dim3(grid), dim3(ROWS * R2),
+                           0, st, in, spec, rowsum, ny, nrows, tw4, tws, pres, nz, idx2, idy2, rc,
+                           1, 0);
+    return hipGetLastError();
+}
+
 // variant: 1 = plain block order, 2 = XCD-contiguous tiles, 3 = as 2 with
-// twice the rows per block (256-byte runs of the transposed layout).
+// twice the rows per block (256-byte runs of the transposed layout), 4 = as 2
+// with the paired row transform where L = 2 s^2 (else as 2).
 template <typename T, int R1, int R2>
 static hipError_t r2c_fast(const T *in, cx_t<T> *spec, double *rowsum, int ny, int nz,
                            const cx_t<T> *tw4, const cx_t<T> *tws, const T *pres, double idx2,
                            double idy2, const double *rc, int variant, hipStream_t st)
 {
-    if (variant >= 3)
+    if constexpr (R2 == 2 * R1)
+        if (variant == 4)
+            return r2c_pair<T, R1, R2>(in, spec, rowsum, ny, nz, tw4, tws, pres, idx2, idy2, rc,
+                                       st);
+    if (variant == 3)
         return r2c_fast_rows<T, R1, R2, true>(in, spec, rowsum, ny, nz, tw4, tws, pres, idx2,
                                               idy2, rc, 1, st);
     return r2c_fast_rows<T, R1, R2, false>(in, spec, rowsum, ny, nz, tw4, tws, pres, idx2, idy2,
@@ -435,7 +495,16 @@ template <typename T, int R1, int R2>
 static hipError_t c2r_fast(const cx_t<T> *spec, T *out, int ny, int nrows, int accumulate,
                            const cx_t<T> *tw4, const cx_t<T> *tws, int variant, hipStream_t st)
 {
-    if (variant >= 3)
+    if constexpr (R2 == 2 * R1) {
+        if (variant == 4) {
+            constexpr int ROWS = x_rows<T, R2, R1, false, true>();
+            const int grid = (nrows + ROWS - 1) / ROWS;
+            hipLaunchKernelGGL((k_c2r_fast<T, R2, R1, ROWS, true>), dim3(grid), dim3(ROWS * R2), 0,
+                               st, spec, out, ny, nrows, accumulate, tw4, tws, 1);
+            return hipGetLastError();
+        }
+    }
+    if (variant == 3)
         return c2r_fast_rows<T, R1, R2, true>(spec, out, ny, nrows, accumulate, tw4, tws, 1, st);
     return c2r_fast_rows<T, R1, R2, false>(spec, out, ny, nrows, accumulate, tw4, tws,
                                            variant >= 2, st);

@@ -313,6 +313,7 @@ static void choose_geometry(ps_plan *p)
     p->geom.rows_y = std::min(ry, p->nz * p->L);
     // register-resident kernels where the length has one (variant 1)
     p->geom.variant_x = fast_length(p->L) ? 1 : 0;
+    p->geom.variant_xi = p->geom.variant_x;
     p->geom.variant_y = fast_length(p->ny) ? 1 : 0;
     // the in-register refinement: refining uniform-half column kernel
     if (p->precision == PS_FP32_R2) p->geom.columns = 3;
@@ -472,6 +473,7 @@ extern "C" int ps_plan_query(const ps_plan *p, ps_plan_info *info)
     info->fp64_columns = p->nmask;
     info->tau = p->fp64() ? 0.0 : p->tau;
     info->fft_variant_x = p->geom.variant_x;
+    info->fft_variant_xi = p->geom.variant_xi;
     info->fft_variant_y = p->geom.variant_y;
     info->spectrum_elems = p->spec_elems();
     info->column_variant = p->geom.columns;
@@ -702,9 +704,9 @@ template <typename T> static int inv_x(ps_plan *p, cx_t<T> *spec, T *out, int ac
 {
     const Tables<T> &tb = tables<T>(p);
     PS_HIP(timed(p, K_INV_X, [&] {
-        if (p->geom.variant_x >= 1)
+        if (p->geom.variant_xi >= 1)
             return launch_c2r_fast<T>(spec, out, p->nx, p->ny, p->nz, accumulate, tb.tw4_x,
-                                      tb.tw_s, p->stream, p->geom.variant_x);
+                                      tb.tw_s, p->stream, p->geom.variant_xi);
         return launch_inv_x<T>(spec, out, p->nx, p->ny, p->nz, accumulate, p->geom, p->spx, tb,
                                p->stream);
     }));
@@ -840,6 +842,7 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
         if (it != g_tune.end()) {
             // only the tuned knobs: the tile shapes follow from the plan
             p->geom.variant_x = fast_length(p->L) ? it->second.variant_x : 0;
+            p->geom.variant_xi = fast_length(p->L) ? it->second.variant_xi : 0;
             p->geom.variant_y = fast_length(p->ny) ? it->second.variant_y : 0;
             p->geom.columns = it->second.columns;
             p->geom.special_side = it->second.special_side;
@@ -876,8 +879,10 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
     };
     std::vector<int> vx{0}, vy{0};
     if (fast_length(p->L)) vx.insert(vx.end(), {1, 2, 3});
+    if (pair_length(p->L)) vx.push_back(4);
     if (fast_length(p->ny)) vy.insert(vy.end(), {1, 2});
     pick(&FftGeom::variant_x, vx);
+    pick(&FftGeom::variant_xi, vx);
     pick(&FftGeom::variant_y, vy);
     if (p->precision != PS_FP32_R2)
         pick(&FftGeom::columns, {0, 1, 2, 3, 4, 5});
@@ -896,7 +901,8 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
 }
 
 // Text format, one line per entry: arch nx ny nz precision variant_x
-// variant_y columns special_side chunks (the last two optional on reading)
+// variant_y columns special_side chunks variant_xi (the last three optional on
+// reading; variant_xi defaults to variant_x)
 extern "C" int ps_tune_cache_save(const char *path)
 {
     if (!path) return fail(PS_EINVAL, "path is NULL");
@@ -905,8 +911,8 @@ extern "C" int ps_tune_cache_save(const char *path)
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (auto &kv : g_tune)
         f << kv.first << ' ' << kv.second.variant_x << ' ' << kv.second.variant_y << ' '
-          << kv.second.columns << ' ' << kv.second.special_side << ' ' << kv.second.chunks
-          << '\n';
+          << kv.second.columns << ' ' << kv.second.special_side << ' ' << kv.second.chunks << ' '
+          << kv.second.variant_xi << '\n';
     return f.good() ? PS_OK : fail(PS_EINVAL, "write failed");
 }
 
@@ -920,17 +926,19 @@ extern "C" int ps_tune_cache_load(const char *path)
     while (std::getline(f, line)) {
         std::istringstream is(line);
         std::string arch;
-        int nx, ny, nz, prec, vx, vy, col, side = 1, chunks = 1;
+        int nx, ny, nz, prec, vx, vy, col, side = 1, chunks = 1, vxi = -1;
         if (!(is >> arch >> nx >> ny >> nz >> prec >> vx >> vy >> col)) continue;
         if (!(is >> side)) side = 1;
         if (!(is >> chunks)) chunks = 1;
-        if (vx < 0 || vx > 3 || vy < 0 || vy > 2 || col < 0 || col > 5 || side < 0 || side > 1 ||
-            chunks < 1 || chunks > 64)
+        if (!(is >> vxi)) vxi = vx;
+        if (vx < 0 || vx > 4 || vy < 0 || vy > 2 || col < 0 || col > 5 || side < 0 || side > 1 ||
+            chunks < 1 || chunks > 64 || vxi < 0 || vxi > 4)
             continue;
         std::ostringstream k;
         k << arch << ' ' << nx << ' ' << ny << ' ' << nz << ' ' << prec;
         FftGeom g;
         g.variant_x = fast_length(nx / 2) ? vx : 0;
+        g.variant_xi = fast_length(nx / 2) ? vxi : 0;
         g.variant_y = fast_length(ny) ? vy : 0;
         g.columns = col;
         g.special_side = side;

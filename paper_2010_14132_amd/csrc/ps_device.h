@@ -200,6 +200,52 @@ __device__ __forceinline__ void four_step(C (&v)[R2], C (&w)[R2], int t, T *lds,
     for (int j = 0; j < R2 / R1; ++j) dft<R1, DIR>(&w[j * R1]);
 }
 
+// The same transform of a row of L = R1 R2 points with R1 = 2 R2: twice the
+// lanes, half the values per lane.  Lane t holds v[q] = x[t + R1 q] (q < R2)
+// on entry.  Stage 1 is the length-R2 DFT over q and the twiddle W_L^{t k2};
+// after the transposition through LDS the lane pair (2m, 2m + 1) holds
+// Y[2u][m] and Y[2u + 1][m] (u < R2) and each lane transforms its half over
+// u; a radix-2 butterfly between the two lanes (W_L^{kk R2} on the odd half)
+// finishes the length-R1 DFTs.  On exit lane t = 2m + h holds
+// v[kk] = X[m + R2 kk + R2^2 h].  Works in place (the real and imaginary
+// parts go through LDS one after the other).  tw4 is the table of the
+// (R2, R1) split, entry W_L^{a b} at b R2 + a for a < R2, b < R1.  lds is this
+// row's scratch of R2 (R1 + 2) values (the +2 spreads the pair reads over
+// the banks); every thread of the block calls this together.
+template <int R1, int R2, int DIR, typename C, typename T>
+__device__ __forceinline__ void four_step_pair(C (&v)[R2], int t, T *lds,
+                                               const C *__restrict__ tw4)
+{
+    static_assert(R1 == 2 * R2, "paired four-step: R1 = 2 R2");
+    constexpr int P = R1 + 2;
+    const int m = t >> 1, h = t & 1;
+    dft<R2, DIR>(v);
+#pragma unroll
+    for (int k2 = 1; k2 < R2; ++k2) v[k2] = ctw<DIR>(v[k2], tw4[t * R2 + k2]);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) lds[k2 * P + t] = v[k2].x;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < R2; ++u) v[u].x = lds[m * P + 2 * u + h];
+    __syncthreads();
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) lds[k2 * P + t] = v[k2].y;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < R2; ++u) v[u].y = lds[m * P + 2 * u + h];
+    dft<R2, DIR>(v);
+#pragma unroll
+    for (int kk = 0; kk < R2; ++kk) {
+        C o;
+        o.x = __shfl_xor(v[kk].x, 1, 64);
+        o.y = __shfl_xor(v[kk].y, 1, 64);
+        const C e = h ? o : v[kk];
+        C od = h ? v[kk] : o;
+        if (kk) od = ctw<DIR>(od, tw4[R2 * R2 + kk]);
+        v[kk] = h ? csub(e, od) : cadd(e, od);
+    }
+}
+
 // ---- Stockham radix pass ---------------------------------------------------
 // Factorisation of a transform length L = r_0 r_1 ... ; ns[s] = r_0...r_{s-1}.
 struct StagePlan {

@@ -44,7 +44,8 @@ template <typename T> struct Tables {
 struct FftGeom {
     int rows_x = 1;   // rows per block of the x passes
     int rows_y = 1;   // rows per block of the y passes
-    int variant_x = 0;
+    int variant_x = 0;   // forward x pass
+    int variant_xi = 0;  // backward x pass
     int variant_y = 0;
     int special_side = 1; // 1: FP64 columns on the side stream beside the main kernel
     int columns = 2;     // column-solve kernel variant (see launch_columns_impl)
@@ -76,10 +77,12 @@ hipError_t launch_inv_x(const cx_t<T> *spec, T *out, int nx, int ny, int nz, int
                         hipStream_t st);
 
 bool fast_length(int L);
+bool pair_length(int L); // L = 2 s^2 among the fast lengths (32, 128, 512)
 int fast_r1(int L); // lanes per row of the register-resident kernels
 // variant (the plan's variant_x / variant_y >= 1): 1 = plain block order,
 // 2 = XCD-contiguous tiles, 3 (x passes only) = as 2 with twice the rows per
-// block.
+// block, 4 (x passes only) = as 2 with the paired row transform when
+// nx/2 = 2 s^2 (else as 2).
 template <typename T>
 hipError_t launch_fft_y_fast(cx_t<T> *spec, int nz, int L, int kxlo, int kxcnt, int ny, int dir,
                              const cx_t<T> *tw4, hipStream_t st, int variant);

@@ -88,3 +88,27 @@ def test_status_strings(lib):
     assert lib.ps_status_string(99) == b"unknown status"
     rc, _ = _create(lib, nx=31)
     assert b"nx" in lib.ps_last_error()
+
+
+def test_tune_cache_round_trip_and_rejects_bad_lines(lib, tmp_path):
+    """The tune-cache text format (host-only code): full and short lines are
+    read with their defaults, malformed or out-of-range lines are skipped,
+    and a save writes every entry back with all fields."""
+    src = tmp_path / "in.txt"
+    src.write_text("\n".join([
+        "gfx950 512 256 64 1 2 1 5 1 4 3",   # every field
+        "gfx950 256 256 32 0 1 1 3",         # short: fp64_beside 1, chunks 1, xi = x
+        "gfx950 64 64 8 2 9 1 3",            # x variant out of range
+        "gfx950 64 64 8 3 1 1 7",            # column variant out of range
+        "gfx950 64 64 8 1 1 1 3 1 0",        # chunks out of range
+        "not a line",
+        "",
+    ]) + "\n")
+    assert lib.ps_tune_cache_load(os.fsencode(str(src))) == 0
+    out = tmp_path / "out.txt"
+    assert lib.ps_tune_cache_save(os.fsencode(str(out))) == 0
+    lines = {tuple(l.split()[:5]): l.split()[5:] for l in out.read_text().splitlines() if l}
+    assert lines[("gfx950", "512", "256", "64", "1")] == ["2", "1", "5", "1", "4", "3"]
+    assert lines[("gfx950", "256", "256", "32", "0")] == ["1", "1", "3", "1", "1", "1"]
+    assert not any(k[1:4] == ("64", "64", "8") for k in lines)
+    assert lib.ps_tune_cache_load(os.fsencode(str(tmp_path / "missing.txt"))) == 1

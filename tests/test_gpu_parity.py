@@ -318,6 +318,37 @@ def test_kernel_variants_via_tune_cache(tmp_path, precision, var):
     assert relmax(lam, lref) < (TOL64 if precision == "fp64" else TOL32)
 
 
+PAIR_SHAPES = [(6, 32, 64), (5, 24, 256), (3, 16, 1024)]  # nx/2 = 32, 128, 512 (= 2 s^2)
+
+
+@pytest.mark.parametrize("shape", PAIR_SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_r1", "fp32_r2"])
+def test_paired_row_transform(tmp_path, precision, shape):
+    """The x passes with the paired row transform (twice the lanes, a radix-2
+    step between lane pairs), forced through the tune cache: solve and
+    adjoint against the oracle."""
+    from paper_2010_14132_amd.binding import PRECISIONS, tune_cache_load
+    nz, ny, nx = shape
+    announce("paired x transform %s %s" % (precision, shape))
+    g = stretched(nx, ny, nz, seed=23 + nx)
+    f = tmp_path / "tune.txt"
+    f.write_text("%s %d %d %d %d 4 1 3 1 1\n" % (_arch(), nx, ny, nz, PRECISIONS[precision]))
+    tune_cache_load(str(f))
+    plan = make_plan(g, precision)
+    plan.autotune()
+    assert plan.info()["fft_variant_x"] == 4
+    b = np.random.default_rng(31).standard_normal((nz, ny, nx)) + 0.3
+    if precision != "fp64":
+        b = b.astype(np.float32).astype(np.float64)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    tol = TOL64 if precision == "fp64" else (2e-7 if precision == "fp32_r1" else TOL32)
+    p = plan.solve(torch.from_numpy(b).to("cuda", dt)).cpu().numpy()
+    assert relmax(p, oracle.solve(b, g.dx, g.dy, g.dz, g.rho)) < tol
+    lam = plan.solve_adjoint(torch.from_numpy(b).to("cuda", dt)).cpu().numpy()
+    assert relmax(lam, oracle.solve_adjoint(b, g.dx, g.dy, g.dz, g.rho)) < tol
+    plan.close()
+
+
 def test_autotune_and_cache_file(tmp_path):
     from paper_2010_14132_amd.binding import tune_cache_save
     nz, ny, nx = 24, 96, 256
