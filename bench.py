@@ -110,14 +110,14 @@ def sampled_oracle_error(p: np.ndarray, b: np.ndarray, g, modes) -> float:
 
 def cpu_baseline(g, nz_full: int):
     """Time the FP64 oracle (as it stands) on a bounded sample of the same
-    workload: the full 1024 x 1024 horizontal grid with one level per oracle
+    workload: the full 1024 x 1024 horizontal grid with three levels per oracle
     thread (its parallel loop runs over levels), same recipe.  The oracle's
     cost per point does not depend on nz (direct DFTs per level dominate),
     so the full-size time is scaled by nz_full / levels."""
     import oracle
     from paper_2010_14132_amd import workloads as wl
     threads = oracle.num_threads()
-    levels = int(min(max(threads, 4), 32))
+    levels = int(min(max(3 * threads, 8), 96))  # three levels per thread: ~12 s on 16 cores
     sg = wl.stretched_grid(g.nx, g.ny, levels)
     b = wl.smooth_field(np.random.default_rng(2), sg, noise=0.01)
     t0 = time.perf_counter()
