@@ -210,11 +210,11 @@ template <typename T> static int upload_coeff_tables(ps_plan *p, Tables<T> &t)
             e.D = (T)p->D[k];
             e.rs = (T)(adj ? -on : rsf[k]);
             e.os = (T)(adj ? p->D[k] : 1.0);
-            e.pad = 0;
+            e.real = 1;
             e.off = (long long)k * lvl_bytes;
         };
         for (int i = 0; i < 2 * nh + 1; ++i) {
-            c[i] = Coef{T(0), T(0), T(1), T(0), T(0), T(0), -1};
+            c[i] = Coef{T(0), T(0), T(1), T(0), T(0), 0, (long long)m * lvl_bytes};
         }
         const int nlo = m, nhi = nz - 1 - m;
         for (int i = 0; i < nlo; ++i) put(nh - nlo + i, i, p->f[i], p->f[i + 1]);
@@ -885,9 +885,9 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
     pick(&FftGeom::variant_xi, vx);
     pick(&FftGeom::variant_y, vy);
     if (p->precision != PS_FP32_R2)
-        pick(&FftGeom::columns, {0, 1, 2, 3, 4, 5});
+        pick(&FftGeom::columns, {0, 1, 2, 3, 4, 5, 6});
     else
-        pick(&FftGeom::columns, {0, 3, 5});
+        pick(&FftGeom::columns, {0, 3, 5, 6});
     pick(&FftGeom::special_side, {0, 1});
     if (p->geom.special_side) pick(&FftGeom::chunks, {1, 2, 4, 8});
     p->prof.on = prof;
@@ -931,7 +931,7 @@ extern "C" int ps_tune_cache_load(const char *path)
         if (!(is >> side)) side = 1;
         if (!(is >> chunks)) chunks = 1;
         if (!(is >> vxi)) vxi = vx;
-        if (vx < 0 || vx > 4 || vy < 0 || vy > 2 || col < 0 || col > 5 || side < 0 || side > 1 ||
+        if (vx < 0 || vx > 4 || vy < 0 || vy > 2 || col < 0 || col > 6 || side < 0 || side > 1 ||
             chunks < 1 || chunks > 64 || vxi < 0 || vxi > 4)
             continue;
         std::ostringstream k;

@@ -12,10 +12,12 @@ namespace ps {
 
 // One slot of the uniform-half column kernel's coefficient table (see
 // k_columns3): coupling to the previous and next row of the elimination,
-// D_k, right-hand-side and output factors, and the level's byte offset in
-// the spectrum (-1 for a dummy slot).
+// D_k, right-hand-side and output factors, whether the slot is a real level
+// (0 for a dummy slot, whose value is read but never written) and the
+// level's byte offset in the spectrum (a dummy slot reads the middle row).
 template <typename T> struct LevelCoef {
-    T fp, fn, D, rs, os, pad;
+    T fp, fn, D, rs, os;
+    int real;
     long long off;
 };
 

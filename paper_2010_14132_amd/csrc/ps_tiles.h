@@ -157,6 +157,47 @@ __device__ void inv_x_tile(const cx_t<T> *__restrict__ spec, T *__restrict__ out
 // Reciprocal of a pivot u > 0 in the normal range.  FP32: the hardware
 // reciprocal refined by one Newton step (within one ulp of the IEEE
 // quotient); FP64: IEEE division.
+// Column access of the uniform-half kernels through a buffer resource over
+// the spectrum: the level's byte offset (wave-uniform, from the scalar
+// table) is the instruction's scalar offset and the column's lane part its
+// 32-bit vector offset, so no 64-bit address arithmetic runs per access.
+// Both offsets stay below 2^32: the spectrum of the supported sizes is at
+// most 2 GiB.  Raw (untyped) 32-bit data format, no range clamp.
+struct ColBuf {
+    __amdgpu_buffer_rsrc_t r;
+    unsigned lane_off;
+};
+__device__ __forceinline__ ColBuf col_buf(const void *spec, unsigned lane_off)
+{
+    return ColBuf{__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(spec), 0, 0xffffffffu,
+                                                    0x00020000),
+                  lane_off};
+}
+template <typename V> __device__ __forceinline__ V col_load(const ColBuf &b, long long off)
+{
+    static_assert(sizeof(V) == 4 || sizeof(V) == 8 || sizeof(V) == 16, "element size");
+    if constexpr (sizeof(V) == 4)
+        return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(b.r, b.lane_off, (int)off, 0));
+    else if constexpr (sizeof(V) == 8)
+        return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(b.r, b.lane_off, (int)off, 0));
+    else
+        return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(b.r, b.lane_off, (int)off, 0));
+}
+template <typename V> __device__ __forceinline__ void col_store(const ColBuf &b, long long off, V v)
+{
+    if constexpr (sizeof(V) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), b.r, b.lane_off,
+                                              (int)off, 0);
+    else if constexpr (sizeof(V) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(
+            __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), b.r, b.lane_off,
+            (int)off, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b128(
+            __builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), b.r, b.lane_off,
+            (int)off, 0);
+}
+
 __device__ __forceinline__ float pivot_rcp(float u)
 {
     const float r = __builtin_amdgcn_rcpf(u);
@@ -168,12 +209,12 @@ __device__ __forceinline__ double pivot_rcp(double u) { return 1.0 / u; }
 // Per-slot coefficients in each half's elimination order (built by the plan):
 // slot [half][i], i in [0, NH), for level k = i (low half) or k = nz - 1 - i
 // (high half), with the half's real levels in the LAST n slots and dummy
-// slots in front (f_prev = f_next = 0, D = 1, rs = 0, off -> middle row).  A
-// dummy row never influences a real one: the first real row of each half is
-// a boundary row (f_prev = 0).  Slot [2 NH] is the middle row m.  rs/os are
-// the forward or adjoint right-hand-side and output factors.  `off` is the
-// byte offset of the level in the spectrum.  Wave-uniform, so they are read
-// through the scalar cache.
+// slots in front (f_prev = f_next = 0, D = 1, rs = 0, real = 0; they read
+// the middle row and are never stored).  A dummy row never influences a
+// real one: the first real row of each half is a boundary row (f_prev = 0).
+// Slot [2 NH] is the middle row m.  rs/os are the forward or adjoint
+// right-hand-side and output factors.  `off` is the byte offset of the level
+// in the spectrum.  Wave-uniform, so they are read through the scalar cache.
 // Two waves per group of 64 columns: the low-half wave eliminates levels
 // 0..m-1 and the high-half wave levels nz-1..m+1, one column per lane
 // (complex values, real pivots); they exchange their messages to the middle
@@ -205,17 +246,17 @@ __device__ void columns3_tile(cx_t<T> *__restrict__ spec, int L, int ny, const T
         const int d = min(ky, ny - ky);
         if (d < maskcnt[kx]) store = false;
     }
-    char *base = reinterpret_cast<char *>(spec + (valid ? col : 0));
+    const ColBuf cb = col_buf(spec, (unsigned)((valid ? col : 0) * sizeof(C)));
     const LevelCoef<T> *ct = coef + half * NH;
 
     C v[NH];
 #pragma unroll
     for (int i = 0; i < NH; ++i) {
-        const C x = *reinterpret_cast<const C *>(base + (ct[i].off < 0 ? coef[2 * NH].off : ct[i].off));
+        const C x = col_load<C>(cb, ct[i].off);
         v[i] = C{x.x * ct[i].rs, x.y * ct[i].rs};
     }
     const LevelCoef<T> cm = coef[2 * NH];
-    C rmv = *reinterpret_cast<const C *>(base + cm.off);
+    C rmv = col_load<C>(cb, cm.off);
     rmv = C{rmv.x * cm.rs, rmv.y * cm.rs};
 
     T qck[KEEPG ? 1 : NB];
@@ -278,11 +319,9 @@ __device__ void columns3_tile(cx_t<T> *__restrict__ spec, int L, int ny, const T
     if (store) {
 #pragma unroll
         for (int i = 0; i < NH; ++i) {
-            const long long off = ct[i].off;
-            if (off >= 0)
-                *reinterpret_cast<C *>(base + off) = C{v[i].x * ct[i].os, v[i].y * ct[i].os};
+            if (ct[i].real) col_store<C>(cb, ct[i].off, C{v[i].x * ct[i].os, v[i].y * ct[i].os});
         }
-        if (half) *reinterpret_cast<C *>(base + cm.off) = C{xm.x * cm.os, xm.y * cm.os};
+        if (half) col_store<C>(cb, cm.off, C{xm.x * cm.os, xm.y * cm.os});
     }
 }
 
@@ -322,7 +361,7 @@ __device__ void columns3r_tile(float2 *__restrict__ spec, int L, int ny, const f
         const int d = min(ky, ny - ky);
         if (d < maskcnt[kx]) store = false;
     }
-    char *base = reinterpret_cast<char *>(spec + (valid ? col : 0));
+    const ColBuf cb = col_buf(spec, (unsigned)((valid ? col : 0) * sizeof(C)));
     const LevelCoef<float> *ct = coef + half * NH;
     const LevelCoef<double> *ct64 = coef64 + half * NH;
     const LevelCoef<float> cm = coef[2 * NH];
@@ -331,10 +370,10 @@ __device__ void columns3r_tile(float2 *__restrict__ spec, int L, int ny, const f
     C raw[NH], v[NH];
 #pragma unroll
     for (int i = 0; i < NH; ++i) {
-        raw[i] = *reinterpret_cast<const C *>(base + (ct[i].off < 0 ? cm.off : ct[i].off));
+        raw[i] = col_load<C>(cb, ct[i].off);
         v[i] = C{raw[i].x * ct[i].rs, raw[i].y * ct[i].rs};
     }
-    const C rawm = *reinterpret_cast<const C *>(base + cm.off);
+    const C rawm = col_load<C>(cb, cm.off);
 
     // ---- solve M x = r
     float qck[NB];
@@ -437,12 +476,11 @@ __device__ void columns3r_tile(float2 *__restrict__ spec, int L, int ny, const f
     if (store) {
 #pragma unroll
         for (int i = 0; i < NH; ++i) {
-            const long long off = ct[i].off;
-            if (off >= 0)
-                *reinterpret_cast<C *>(base + off) =
-                    C{(v[i].x + raw[i].x) * ct[i].os, (v[i].y + raw[i].y) * ct[i].os};
+            if (ct[i].real)
+                col_store<C>(cb, ct[i].off,
+                             C{(v[i].x + raw[i].x) * ct[i].os, (v[i].y + raw[i].y) * ct[i].os});
         }
-        if (half) *reinterpret_cast<C *>(base + cm.off) = C{xm.x * cm.os, xm.y * cm.os};
+        if (half) col_store<C>(cb, cm.off, C{xm.x * cm.os, xm.y * cm.os});
     }
 }
 
@@ -454,20 +492,41 @@ __device__ void columns3r_tile(float2 *__restrict__ spec, int L, int ny, const f
 // complex form, for FP64 and for the refining FP32 form.  REFINE (FP32 only)
 // adds the refinement of columns3r_tile: FP64 residual from the FP64 table,
 // FP32 correction with the same elimination.  xa, xb, xe: LDS scratch of
-// 2 * 2 * 64 values each.
-template <typename T, int NH, bool REFINE>
+// 2 * 2 * 64 values each.  SHG: the reciprocal pivots of the first forward
+// sweep are kept in LDS (gsh, 4 waves x NH x 32 values: one per column and
+// level, written by both lanes of the column with the same value) and read
+// back by the later sweeps instead of being recomputed from checkpoints.
+template <typename T, int NH, bool REFINE, bool SHG = false>
 __device__ void columns3s_tile(cx_t<T> *__restrict__ spec, int L, int ny, const T *__restrict__ ax,
                                const T *__restrict__ ay, const LevelCoef<T> *__restrict__ coef,
                                const LevelCoef<double> *__restrict__ coef64,
                                const double *__restrict__ ax64, const double *__restrict__ ay64,
                                const int *__restrict__ maskcnt, long c0, long c1, long group, T (*xa)[2][64],
-                               T (*xb)[2][64], T (*xe)[2][64])
+                               T (*xb)[2][64], T (*xe)[2][64], T *gsh = nullptr)
 {
     constexpr int CH = NH < 8 ? NH : 8;
     constexpr int NB = (NH + CH - 1) / CH;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int pair = w >> 1, half = w & 1;
+    // this lane's pivot of slot i: gw[i * 32]
+    T *gw = SHG ? gsh + (size_t)w * NH * 32 + (lane >> 1) : nullptr;
+    // Pivot loads of the later sweeps: one chunk of GC levels is fetched
+    // while the previous chunk is computed.  The fences take the sweep's
+    // running value as an operand, so that a chunk's loads cannot be issued
+    // before the chunk two steps back has been computed (otherwise all NH
+    // loads are hoisted to the start of the sweep, NH registers live).
+    // The array's address also goes into an asm statement: an LDS array
+    // whose address never escapes is taken to be untouched by the fences,
+    // and the pivots stored by the first sweep are then forwarded in
+    // registers to the later sweeps.
+    if constexpr (SHG) __asm__ volatile("" ::"s"(gsh) : "memory");
+    constexpr int GC = NH < 4 ? NH : 4; // levels per pivot chunk
+    constexpr int NG = NH / GC;
+    auto gload = [&](T(&gd)[GC], int bb) {
+#pragma unroll
+        for (int c = 0; c < GC; ++c) gd[c] = gw[(bb * GC + c) * 32];
+    };
     const long col = c0 + (group * 2 + pair) * 32 + (lane >> 1);
     const bool valid = col < c1;
     const int kx = valid ? (int)(col / ny) : 1;
@@ -478,7 +537,8 @@ __device__ void columns3s_tile(cx_t<T> *__restrict__ spec, int L, int ny, const 
         const int d = min(ky, ny - ky);
         if (d < maskcnt[kx]) store = false;
     }
-    char *base = reinterpret_cast<char *>(spec + (valid ? col : 0)) + (lane & 1) * sizeof(T);
+    const ColBuf cb =
+        col_buf(spec, (unsigned)((valid ? col : 0) * sizeof(cx_t<T>) + (lane & 1) * sizeof(T)));
     const LevelCoef<T> *ct = coef + half * NH;
     const LevelCoef<T> cm = coef[2 * NH];
 
@@ -486,18 +546,18 @@ __device__ void columns3s_tile(cx_t<T> *__restrict__ spec, int L, int ny, const 
     T raw[REFINE ? NH : 1];
 #pragma unroll
     for (int i = 0; i < NH; ++i) {
-        const T x = *reinterpret_cast<const T *>(base + (ct[i].off < 0 ? cm.off : ct[i].off));
+        const T x = col_load<T>(cb, ct[i].off);
         if constexpr (REFINE) raw[i] = x;
         v[i] = x * ct[i].rs;
     }
-    const T rawm = *reinterpret_cast<const T *>(base + cm.off);
+    const T rawm = col_load<T>(cb, cm.off);
 
-    T qck[NB];
+    T qck[SHG ? 1 : NB];
     T q = T(0), g = T(0), y = T(0);
 #pragma unroll
     for (int i = 0; i < NH; ++i) {
         if (i % CH == 0) {
-            qck[i / CH] = q;
+            if constexpr (!SHG) qck[i / CH] = q;
             __asm__ volatile("" ::: "memory"); // keep the table loads near their use
         }
         const T e = s * ct[i].D + ct[i].fp * q;
@@ -506,6 +566,7 @@ __device__ void columns3s_tile(cx_t<T> *__restrict__ spec, int L, int ny, const 
         v[i] = y;
         q = e * gi;
         g = gi;
+        if constexpr (SHG) gw[i * 32] = gi;
     }
     const T gl = ct[NH - 1].fn * g;
     xa[pair][half][lane] = ct[NH - 1].fn * q;
@@ -514,10 +575,28 @@ __device__ void columns3s_tile(cx_t<T> *__restrict__ spec, int L, int ny, const 
     const T den = (s * cm.D + xa[pair][0][lane]) + xa[pair][1][lane];
     T xm = ((rawm * cm.rs + xb[pair][0][lane]) + xb[pair][1][lane]) / den;
     auto backward = [&](T(&a)[NH], T xn) {
+        if constexpr (SHG) {
+            T gc[GC], gn[GC];
+            gload(gc, NG - 1);
+#pragma unroll
+            for (int bb = NG - 1; bb >= 0; --bb) {
+                __asm__ volatile("" : "+v"(xn)::"memory");
+                if (bb > 0) gload(gn, bb - 1);
+#pragma unroll
+                for (int c = GC - 1; c >= 0; --c) {
+                    const int i = bb * GC + c;
+                    xn = gc[c] * (a[i] + ct[i].fn * xn);
+                    a[i] = xn;
+                }
+#pragma unroll
+                for (int c = 0; c < GC; ++c) gc[c] = gn[c];
+            }
+            return;
+        }
 #pragma unroll
         for (int bb = NB - 1; bb >= 0; --bb) {
             T gb[CH];
-            T qq = qck[bb];
+            T qq = qck[SHG ? 0 : bb];
             __asm__ volatile("" ::: "memory");
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
@@ -551,6 +630,8 @@ __device__ void columns3s_tile(cx_t<T> *__restrict__ spec, int L, int ny, const 
             const double xp = i > 0 ? (double)v[i - 1] : 0.0;
             const double xn = i + 1 < NH ? (double)v[i + 1] : (double)xm;
             raw[i] = (T)(ct64[i].rs * (double)raw[i] - (diag * (double)v[i] - fp * xp - fn * xn));
+            // (SHG) the scheduler otherwise converts most of raw to FP64 at once
+            if (SHG && i % CH == CH - 1) __builtin_amdgcn_sched_barrier(0);
         }
         const double diagm = s64 * cm64.D + cm64.fp + cm64.fn;
         const T rhom = (T)(cm64.rs * (double)rawm -
@@ -558,15 +639,34 @@ __device__ void columns3s_tile(cx_t<T> *__restrict__ spec, int L, int ny, const 
         q = T(0);
         g = T(0);
         y = T(0);
+        if constexpr (SHG) {
+            T gc[GC], gn[GC];
+            gload(gc, 0);
 #pragma unroll
-        for (int i = 0; i < NH; ++i) {
-            if (i % CH == 0) __asm__ volatile("" ::: "memory");
-            const T e = s * ct[i].D + ct[i].fp * q;
-            const T gi = pivot_rcp(e + ct[i].fn);
-            y = raw[i] + (ct[i].fp * g) * y;
-            raw[i] = y;
-            q = e * gi;
-            g = gi;
+            for (int bb = 0; bb < NG; ++bb) {
+                __asm__ volatile("" : "+v"(y)::"memory");
+                if (bb + 1 < NG) gload(gn, bb + 1);
+#pragma unroll
+                for (int c = 0; c < GC; ++c) {
+                    const int i = bb * GC + c;
+                    y = raw[i] + (ct[i].fp * g) * y;
+                    raw[i] = y;
+                    g = gc[c];
+                }
+#pragma unroll
+                for (int c = 0; c < GC; ++c) gc[c] = gn[c];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NH; ++i) {
+                if (i % CH == 0) __asm__ volatile("" ::: "memory");
+                const T e = s * ct[i].D + ct[i].fp * q;
+                const T gi = pivot_rcp(e + ct[i].fn);
+                y = raw[i] + (ct[i].fp * g) * y;
+                raw[i] = y;
+                q = e * gi;
+                g = gi;
+            }
         }
         xb[pair][half][lane] = gl * y;
         __syncthreads();
@@ -580,10 +680,9 @@ __device__ void columns3s_tile(cx_t<T> *__restrict__ spec, int L, int ny, const 
     if (store) {
 #pragma unroll
         for (int i = 0; i < NH; ++i) {
-            const long long off = ct[i].off;
-            if (off >= 0) *reinterpret_cast<T *>(base + off) = v[i] * ct[i].os;
+            if (ct[i].real) col_store<T>(cb, ct[i].off, v[i] * ct[i].os);
         }
-        if (half) *reinterpret_cast<T *>(base + cm.off) = xm * cm.os;
+        if (half) col_store<T>(cb, cm.off, xm * cm.os);
     }
 }
 

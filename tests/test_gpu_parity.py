@@ -284,7 +284,7 @@ def _arch():
 
 
 VARIANTS = [(0, 0, 0, 1), (1, 1, 1, 1), (1, 1, 2, 2), (0, 1, 2, 1), (1, 0, 1, 4), (1, 1, 3, 1),
-            (0, 0, 4, 3), (1, 1, 5, 1), (2, 2, 3, 8), (3, 2, 5, 4)]
+            (0, 0, 4, 3), (1, 1, 5, 1), (2, 2, 3, 8), (3, 2, 5, 4), (1, 1, 6, 1), (2, 1, 6, 4)]
 
 
 @pytest.mark.parametrize("var", VARIANTS, ids=lambda v: "x%d-y%d-c%d-k%d" % v)
