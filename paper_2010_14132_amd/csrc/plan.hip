@@ -311,12 +311,15 @@ static void choose_geometry(ps_plan *p)
     ry = std::max(1, std::min(64, ry));
     p->geom.rows_x = std::min(rx, p->ny * p->nz);
     p->geom.rows_y = std::min(ry, p->nz * p->L);
-    // register-resident kernels where the length has one (variant 1)
-    p->geom.variant_x = fast_length(p->L) ? 1 : 0;
-    p->geom.variant_xi = p->geom.variant_x;
+    // register-resident kernels where the length has one: the paired row
+    // transform forward where nx/2 = 2 s^2, XCD-contiguous tiles backward
+    p->geom.variant_x = pair_length(p->L) ? 4 : fast_length(p->L) ? 1 : 0;
+    p->geom.variant_xi = fast_length(p->L) ? 2 : 0;
     p->geom.variant_y = fast_length(p->ny) ? 1 : 0;
-    // the in-register refinement: refining uniform-half column kernel
-    if (p->precision == PS_FP32_R2) p->geom.columns = 3;
+    // uniform-half column kernels: split lanes with the pivots in LDS for
+    // FP64 and the in-register refinement, one complex column per lane for
+    // the other FP32 forms
+    p->geom.columns = (p->fp64() || p->precision == PS_FP32_R2) ? 6 : 3;
 }
 
 // Near-singular columns of the FP32 forms: lateral eigenvalue
