@@ -9,18 +9,6 @@
 
 namespace ps {
 
-// Block -> tile map.  Blocks are handed to the eight XCDs in turn (block b
-// to XCD b mod 8), each with its own L2; with swz set, XCD x takes one
-// contiguous range of tiles instead of every eighth one, so neighbouring
-// tiles (adjacent rows, adjacent 128-byte runs of the transposed layout)
-// meet in the same L2.  A bijection of [0, nb) for any nb.
-__device__ __forceinline__ int tile_of(int b, int nb, int swz)
-{
-    if (!swz) return b;
-    const int q = nb >> 3, r = nb & 7, x = b & 7;
-    return x * q + min(x, r) + (b >> 3);
-}
-
 // LDS slot of element (kx, rr) of the x passes' [kx][row] staging (ROWS rows
 // of L values): rows XOR-swizzled per kx so that both the column-wise writes
 // (R1 consecutive kx of each row) and the row-wise reads (ROWS consecutive

@@ -888,9 +888,9 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
     pick(&FftGeom::variant_xi, vx);
     pick(&FftGeom::variant_y, vy);
     if (p->precision != PS_FP32_R2)
-        pick(&FftGeom::columns, {0, 1, 2, 3, 4, 5, 6});
+        pick(&FftGeom::columns, {0, 1, 2, 3, 4, 5, 6, 7, 8});
     else
-        pick(&FftGeom::columns, {0, 3, 5, 6});
+        pick(&FftGeom::columns, {0, 3, 5, 6, 7, 8});
     pick(&FftGeom::special_side, {0, 1});
     if (p->geom.special_side) pick(&FftGeom::chunks, {1, 2, 4, 8});
     p->prof.on = prof;
@@ -934,7 +934,7 @@ extern "C" int ps_tune_cache_load(const char *path)
         if (!(is >> side)) side = 1;
         if (!(is >> chunks)) chunks = 1;
         if (!(is >> vxi)) vxi = vx;
-        if (vx < 0 || vx > 4 || vy < 0 || vy > 2 || col < 0 || col > 6 || side < 0 || side > 1 ||
+        if (vx < 0 || vx > 4 || vy < 0 || vy > 2 || col < 0 || col > 8 || side < 0 || side > 1 ||
             chunks < 1 || chunks > 64 || vxi < 0 || vxi > 4)
             continue;
         std::ostringstream k;

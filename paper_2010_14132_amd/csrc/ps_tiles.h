@@ -4,6 +4,7 @@
 // and the compact FP64 column task.  Each is executed by one 256-thread
 // block (the FP64 task by one lane).
 #pragma once
+#include <type_traits>
 #include "ps_internal.h"
 #include "../../include/pressure_solve.h"
 
@@ -496,7 +497,9 @@ __device__ void columns3r_tile(float2 *__restrict__ spec, int L, int ny, const f
 // sweep are kept in LDS (gsh, 4 waves x NH x 32 values: one per column and
 // level, written by both lanes of the column with the same value) and read
 // back by the later sweeps instead of being recomputed from checkpoints.
-template <typename T, int NH, bool REFINE, bool SHG = false>
+// PPB: wave pairs per block (2: 256 threads and 64 columns, 1: 128 threads
+// and 32 columns).
+template <typename T, int NH, bool REFINE, bool SHG = false, int PPB = 2>
 __device__ void columns3s_tile(cx_t<T> *__restrict__ spec, int L, int ny, const T *__restrict__ ax,
                                const T *__restrict__ ay, const LevelCoef<T> *__restrict__ coef,
                                const LevelCoef<double> *__restrict__ coef64,
@@ -527,7 +530,7 @@ __device__ void columns3s_tile(cx_t<T> *__restrict__ spec, int L, int ny, const 
 #pragma unroll
         for (int c = 0; c < GC; ++c) gd[c] = gw[(bb * GC + c) * 32];
     };
-    const long col = c0 + (group * 2 + pair) * 32 + (lane >> 1);
+    const long col = c0 + (group * PPB + pair) * 32 + (lane >> 1);
     const bool valid = col < c1;
     const int kx = valid ? (int)(col / ny) : 1;
     const int ky = valid ? (int)(col - (long)kx * ny) : 0;
@@ -574,7 +577,10 @@ __device__ void columns3s_tile(cx_t<T> *__restrict__ spec, int L, int ny, const 
     __syncthreads();
     const T den = (s * cm.D + xa[pair][0][lane]) + xa[pair][1][lane];
     T xm = ((rawm * cm.rs + xb[pair][0][lane]) + xb[pair][1][lane]) / den;
-    auto backward = [&](T(&a)[NH], T xn) {
+    // FIN (SHG only): the last backward sweep, which stores each level's
+    // result as soon as it is final (a is the correction when REFINE), so
+    // that the stores spread over the sweep instead of leaving in one burst.
+    auto backward = [&](T(&a)[NH], T xn, auto fin) {
         if constexpr (SHG) {
             T gc[GC], gn[GC];
             gload(gc, NG - 1);
@@ -587,6 +593,9 @@ __device__ void columns3s_tile(cx_t<T> *__restrict__ spec, int L, int ny, const 
                     const int i = bb * GC + c;
                     xn = gc[c] * (a[i] + ct[i].fn * xn);
                     a[i] = xn;
+                    if constexpr (decltype(fin)::value)
+                        if (ct[i].real)
+                            col_store<T>(cb, ct[i].off, (REFINE ? v[i] + xn : xn) * ct[i].os);
                 }
 #pragma unroll
                 for (int c = 0; c < GC; ++c) gc[c] = gn[c];
@@ -614,7 +623,11 @@ __device__ void columns3s_tile(cx_t<T> *__restrict__ spec, int L, int ny, const 
             }
         }
     };
-    backward(v, xm);
+    if constexpr (SHG && !REFINE) {
+        if (store) backward(v, xm, std::true_type{});
+    } else {
+        backward(v, xm, std::false_type{});
+    }
 
     if constexpr (REFINE) {
         const LevelCoef<double> *ct64 = coef64 + half * NH;
@@ -671,16 +684,22 @@ __device__ void columns3s_tile(cx_t<T> *__restrict__ spec, int L, int ny, const 
         xb[pair][half][lane] = gl * y;
         __syncthreads();
         const T dm = ((rhom + xb[pair][0][lane]) + xb[pair][1][lane]) / den;
-        backward(raw, dm);
+        if constexpr (SHG) {
+            if (store) backward(raw, dm, std::true_type{});
+        } else {
+            backward(raw, dm, std::false_type{});
 #pragma unroll
-        for (int i = 0; i < NH; ++i) v[i] += raw[i];
+            for (int i = 0; i < NH; ++i) v[i] += raw[i];
+        }
         xm += dm;
     }
 
     if (store) {
+        if constexpr (!SHG) {
 #pragma unroll
-        for (int i = 0; i < NH; ++i) {
-            if (ct[i].real) col_store<T>(cb, ct[i].off, v[i] * ct[i].os);
+            for (int i = 0; i < NH; ++i) {
+                if (ct[i].real) col_store<T>(cb, ct[i].off, v[i] * ct[i].os);
+            }
         }
         if (half) col_store<T>(cb, cm.off, xm * cm.os);
     }

@@ -405,8 +405,8 @@ __global__ __launch_bounds__(256) void k_columns3r(float2 *__restrict__ spec, in
                        xa, xb, xe);
 }
 
-template <typename T, int NH, bool REFINE, bool SHG>
-__global__ __launch_bounds__(256) void k_columns3s(cx_t<T> *__restrict__ spec, int L, int ny,
+template <typename T, int NH, bool REFINE, bool SHG, int PPB>
+__global__ __launch_bounds__(128 * PPB) void k_columns3s(cx_t<T> *__restrict__ spec, int L, int ny,
                                                    const T *__restrict__ ax,
                                                    const T *__restrict__ ay,
                                                    const LevelCoef<T> *__restrict__ coef,
@@ -414,12 +414,13 @@ __global__ __launch_bounds__(256) void k_columns3s(cx_t<T> *__restrict__ spec, i
                                                    const double *__restrict__ ax64,
                                                    const double *__restrict__ ay64,
                                                    const int *__restrict__ maskcnt, long c0,
-                                                   long c1)
+                                                   long c1, int swz)
 {
     __shared__ T xa[2][2][64], xb[2][2][64], xe[REFINE ? 2 : 1][2][64];
-    __shared__ T gsh[SHG ? 4 * NH * 32 : 1];
-    columns3s_tile<T, NH, REFINE, SHG>(spec, L, ny, ax, ay, coef, coef64, ax64, ay64, maskcnt, c0,
-                                       c1, blockIdx.x, xa, xb, xe, gsh);
+    __shared__ T gsh[SHG ? 2 * PPB * NH * 32 : 1];
+    columns3s_tile<T, NH, REFINE, SHG, PPB>(spec, L, ny, ax, ay, coef, coef64, ax64, ay64, maskcnt,
+                                            c0, c1, tile_of(blockIdx.x, gridDim.x, swz), xa, xb,
+                                            xe, gsh);
 }
 
 // These few waves carry long dependent chains and usually share their SIMDs
@@ -574,34 +575,36 @@ static hipError_t columns3r_dispatch(float2 *spec, int L, int ny, int nz, int ad
     return hipErrorInvalidValue;
 }
 
-template <typename T, int NH, bool REFINE, bool SHG>
+template <typename T, int NH, bool REFINE, bool SHG, int PPB>
 static hipError_t columns3s_nh(cx_t<T> *spec, int L, int ny, int adjoint, const int *maskcnt,
                                const Tables<T> &tb, const Tables<double> &t64, long c0, long c1,
-                               hipStream_t st)
+                               int swz, hipStream_t st)
 {
     const long ncols = c1 - c0;
     if (ncols <= 0) return hipSuccess;
-    const long grid = (ncols + 63) / 64;
+    const long grid = (ncols + 32 * PPB - 1) / (32 * PPB);
     const auto *ct = reinterpret_cast<const LevelCoef<T> *>(adjoint ? tb.coef_adj : tb.coef_fwd);
     const auto *c64 =
         reinterpret_cast<const LevelCoef<double> *>(adjoint ? t64.coef_adj : t64.coef_fwd);
-    hipLaunchKernelGGL((k_columns3s<T, NH, REFINE, SHG>), dim3((unsigned)grid), dim3(256), 0, st,
-                       spec, L, ny, tb.ax, tb.ay, ct, c64, t64.ax, t64.ay, maskcnt, c0, c1);
+    hipLaunchKernelGGL((k_columns3s<T, NH, REFINE, SHG, PPB>), dim3((unsigned)grid),
+                       dim3(128 * PPB), 0, st, spec, L, ny, tb.ax, tb.ay, ct, c64, t64.ax, t64.ay,
+                       maskcnt, c0, c1, swz);
     return hipGetLastError();
 }
 
-// SHG (pivots kept in LDS, 4 NH 32 sizeof(T) bytes per block) up to NH = 64;
-// beyond, the pivots are recomputed.
-template <typename T, bool REFINE, bool SHG>
+// SHG (pivots kept in LDS, 2 PPB NH 32 sizeof(T) bytes per block) up to
+// NH = 64; beyond, the pivots are recomputed.  PPB wave pairs per block.
+template <typename T, bool REFINE, bool SHG, int PPB = 2>
 static hipError_t columns3s_dispatch(cx_t<T> *spec, int L, int ny, int nz, int adjoint,
                                      const int *maskcnt, const Tables<T> &tb,
-                                     const Tables<double> &t64, long c0, long c1, hipStream_t st)
+                                     const Tables<double> &t64, long c0, long c1, hipStream_t st,
+                                     int swz = 0)
 {
     const int need = nz / 2;
 #define PS_NH(N)                                                                                   \
     if (need <= N)                                                                                 \
-        return columns3s_nh<T, N, REFINE, SHG && (N <= 64)>(spec, L, ny, adjoint, maskcnt, tb, t64, \
-                                                            c0, c1, st);
+        return columns3s_nh<T, N, REFINE, SHG && (N <= 64), PPB>(spec, L, ny, adjoint, maskcnt,   \
+                                                                 tb, t64, c0, c1, swz, st);
     PS_NH(1) PS_NH(2) PS_NH(4) PS_NH(8) PS_NH(16) PS_NH(32) PS_NH(64) PS_NH(128)
 #undef PS_NH
     return hipErrorInvalidValue;
@@ -628,10 +631,11 @@ static hipError_t columns_dispatch(cx_t<T> *spec, int L, int ny, int nz, const T
 // 3 = halves in separate waves with scalar coefficient tables, pivots
 // recomputed, 4 = as 3 with pivots kept.
 // 5 = as 3 with the real and imaginary parts in two lanes, 6 = as 5 with
-// the pivots of the first sweep kept in LDS.
+// the pivots of the first sweep kept in LDS, 7 = as 6 with one wave pair
+// (32 columns) per block, 8 = as 7 with XCD-contiguous column groups.
 // The in-register refinement (FP32 only) uses variant 0's refining kernel
 // for variants 0-2, the refining uniform-half kernel for 3-4 and the
-// refining split-lane kernel for 5-6.
+// refining split-lane kernel for 5-8.
 template <typename T>
 hipError_t launch_columns_impl(cx_t<T> *spec, int nx, int ny, int nz, int adjoint, int refine,
                                const int *maskcnt, const Tables<T> &tb, const Tables<double> *t64,
@@ -651,6 +655,9 @@ hipError_t launch_columns_impl(cx_t<T> *spec, int nx, int ny, int nz, int adjoin
         if (refine && variant == 6)
             return columns3s_dispatch<float, true, true>(spec, L, ny, nz, adjoint, maskcnt, tb,
                                                          *t64, c0, c1, st);
+        if (refine && (variant == 7 || variant == 8))
+            return columns3s_dispatch<float, true, true, 1>(spec, L, ny, nz, adjoint, maskcnt, tb,
+                                                            *t64, c0, c1, st, variant == 8);
         if (refine && variant >= 3)
             return columns3r_dispatch(spec, L, ny, nz, adjoint, maskcnt, tb, *t64, c0, c1, st);
         if (refine) {
@@ -673,6 +680,9 @@ hipError_t launch_columns_impl(cx_t<T> *spec, int nx, int ny, int nz, int adjoin
     if (variant == 6)
         return columns3s_dispatch<T, false, true>(spec, L, ny, nz, adjoint, maskcnt, tb, *t64, c0,
                                                   c1, st);
+    if (variant == 7 || variant == 8)
+        return columns3s_dispatch<T, false, true, 1>(spec, L, ny, nz, adjoint, maskcnt, tb, *t64,
+                                                     c0, c1, st, variant == 8);
     return columns_dispatch<T, false>(spec, L, ny, nz, rs, os, maskcnt, tb, nullptr, nullptr,
                                       nullptr, nullptr, nullptr, c0, c1, st);
 }

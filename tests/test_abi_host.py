@@ -99,7 +99,7 @@ def test_tune_cache_round_trip_and_rejects_bad_lines(lib, tmp_path):
         "gfx950 512 256 64 1 2 1 5 1 4 3",   # every field
         "gfx950 256 256 32 0 1 1 3",         # short: fp64_beside 1, chunks 1, xi = x
         "gfx950 64 64 8 2 9 1 3",            # x variant out of range
-        "gfx950 64 64 8 3 1 1 7",            # column variant out of range
+        "gfx950 64 64 8 3 1 1 9",            # column variant out of range
         "gfx950 64 64 8 1 1 1 3 1 0",        # chunks out of range
         "not a line",
         "",

@@ -113,6 +113,27 @@ def test_fp32_forms_plain_256(plain256, precision):
         assert err < 2e-7
 
 
+FP32_SHAPES = [(1, 8, 8), (2, 6, 4), (3, 1, 8), (5, 12, 18), (9, 27, 54), (33, 32, 32),
+               (3, 1024, 16), (128, 64, 96), (256, 8, 8)]
+
+
+@pytest.mark.parametrize("shape", FP32_SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("precision", ["fp32", "fp32_r2", "fp32_r1"])
+def test_fp32_forms_shapes(shape, precision):
+    """The FP32 forms with the planning defaults on degenerate and ragged
+    shapes (one level, one row, 2^a 3^b lengths, the deepest supported
+    column), incompatible right-hand side, against the oracle on the same
+    FP32-rounded input."""
+    nz, ny, nx = shape
+    announce("%s solve %s" % (precision, shape))
+    g = stretched(nx, ny, nz, seed=nz + ny + nx)
+    b = (np.random.default_rng(1).standard_normal(shape) + 0.3).astype(np.float32)
+    ref = oracle.solve(b.astype(np.float64), g.dx, g.dy, g.dz, g.rho)
+    err = relmax(run(g, b, precision), ref)
+    print("rel_max %s %s = %.3e" % (precision, shape, err))
+    assert err < TOL32
+
+
 def test_fp32_without_fp64_columns_is_worse_but_bounded(plain256):
     """tau tiny: no FP64 columns except the packed row; still within 1e-5 on
     this grid, and not better than the default threshold."""
@@ -286,7 +307,7 @@ def _arch():
 
 
 VARIANTS = [(0, 0, 0, 1), (1, 1, 1, 1), (1, 1, 2, 2), (0, 1, 2, 1), (1, 0, 1, 4), (1, 1, 3, 1),
-            (0, 0, 4, 3), (1, 1, 5, 1), (2, 2, 3, 8), (3, 2, 5, 4), (1, 1, 6, 1), (2, 1, 6, 4)]
+            (0, 0, 4, 3), (1, 1, 5, 1), (2, 2, 3, 8), (3, 2, 5, 4), (1, 1, 6, 1), (2, 1, 6, 4), (4, 1, 7, 1), (2, 2, 8, 2)]
 
 
 @pytest.mark.parametrize("var", VARIANTS, ids=lambda v: "x%d-y%d-c%d-k%d" % v)
