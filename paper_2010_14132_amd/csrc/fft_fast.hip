@@ -136,8 +136,11 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
             const T er_b = __shfl(pc[(q + 1) % R2].x, right, 64);
             const T xe = t == R1 - 1 ? er_b : er_a;
             const C bv = src[n], pn = pn_row[n], psd = ps_row[n];
-            const C pu = has_up ? pu_row[n] : C{T(0), T(0)};
-            const C pd = has_dn ? pd_row[n] : C{T(0), T(0)};
+            // unconditional: at the top and bottom levels the row pointer is
+            // this row and its coefficient (au or ad) is exactly zero, so no
+            // branch (and no wait for the load inside it) is needed
+            const C pu = pu_row[n];
+            const C pd = pd_row[n];
             const double c0 = pc[q].x, c1 = pc[q].y;
             const double lap0 = ((double)c1 - 2.0 * c0 + (double)xw) * idx2 +
                                 ((double)pn.x - 2.0 * c0 + (double)psd.x) * idy2 +
@@ -145,9 +148,10 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
             const double lap1 = ((double)xe - 2.0 * c1 + c0) * idx2 +
                                 ((double)pn.y - 2.0 * c1 + (double)psd.y) * idy2 +
                                 au * (double)pu.y + ad * (double)pd.y - ac * c1;
-            v[q] = ok ? C{(T)((double)bv.x - lap0), (T)((double)bv.y - lap1)} : C{T(0), T(0)};
-            (void)n;
-            s += (double)v[q].x + (double)v[q].y;
+            // (a row past the end reads row 0 and is transformed but never
+            // stored; no select, so that the loads need no branch)
+            v[q] = C{(T)((double)bv.x - lap0), (T)((double)bv.y - lap1)};
+            s += ok ? (double)v[q].x + (double)v[q].y : 0.0;
         }
     } else {
 #pragma unroll
