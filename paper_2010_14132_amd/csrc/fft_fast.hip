@@ -39,7 +39,7 @@ __global__ __launch_bounds__(NT) void k_fft_y_fast(cx_t<T> *__restrict__ spec, i
     C *base = spec + row * (long)L;
     C v[R2], w[R2];
 #pragma unroll
-    for (int q = 0; q < R2; ++q) v[q] = ok ? base[t + R1 * q] : C{T(0), T(0)};
+    for (int q = 0; q < R2; ++q) v[q] = base[t + R1 * q]; // past the end: row 0, not stored
     four_step<R1, R2, DIR>(v, w, t, lds + r * S, tw4);
     if (ok) {
 #pragma unroll
@@ -233,14 +233,16 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
         const int e = threadIdx.x + NT * i;
         outi[i] = lds[stage_idx<R1, ROWS>(e / ROWS, e % ROWS)];
     }
+    // as in k_c2r_fast: this thread's row rr is the same for every i
+    static_assert(NT % ROWS == 0, "rows per block must divide the block");
+    const long g2 = g0 + threadIdx.x % ROWS;
+    if (g2 < nrows) {
+        const long lev = g2 / ny, jj = g2 - lev * ny;
+        C *dst = spec + lev * L * (long)ny + jj;
 #pragma unroll
-    for (int i = 0; i < R2; ++i) {
-        const int e = threadIdx.x + NT * i;
-        const int kx = e / ROWS, rr = e % ROWS;
-        const long g2 = g0 + rr;
-        if (g2 < nrows) {
-            const long lev = g2 / ny, jj = g2 - lev * ny;
-            spec[(lev * L + kx) * (long)ny + jj] = C{outr[i], outi[i]};
+        for (int i = 0; i < R2; ++i) {
+            const int kx = threadIdx.x / ROWS + (NT / ROWS) * i;
+            dst[(long)kx * ny] = C{outr[i], outi[i]};
         }
     }
 }
@@ -265,19 +267,25 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
     const long g = tile * ROWS + r;
     const bool ok = g < nrows;
 
+    // Element i of this thread is (kx, rr) = (e / ROWS, e % ROWS) with
+    // e = threadIdx.x + NT i; NT is a multiple of ROWS, so rr (and with it
+    // the spectrum row's level and j) is the same for every i and is
+    // computed once.  A row past the end reads row 0: it is transformed but
+    // never stored.
+    static_assert(NT % ROWS == 0, "rows per block must divide the block");
     T inr[R2], ini[R2];
+    {
+        const int rr = threadIdx.x % ROWS;
+        const long g2 = tile * ROWS + rr < nrows ? tile * ROWS + rr : 0;
+        const long lev = g2 / ny, jj = g2 - lev * ny;
+        const C *src = spec + lev * L * (long)ny + jj;
 #pragma unroll
-    for (int i = 0; i < R2; ++i) {
-        const int e = threadIdx.x + NT * i;
-        const int kx = e / ROWS, rr = e % ROWS;
-        const long g2 = tile * ROWS + rr;
-        C x = C{T(0), T(0)};
-        if (g2 < nrows) {
-            const long lev = g2 / ny, jj = g2 - lev * ny;
-            x = spec[(lev * L + kx) * (long)ny + jj];
+        for (int i = 0; i < R2; ++i) {
+            const int kx = threadIdx.x / ROWS + (NT / ROWS) * i;
+            const C x = src[(long)kx * ny];
+            inr[i] = x.x;
+            ini[i] = x.y;
         }
-        inr[i] = x.x;
-        ini[i] = x.y;
     }
     C xa[R2];
 #pragma unroll
@@ -327,12 +335,22 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
     C *Z = PAIR ? v : w;
     if (ok) {
         C *dst = reinterpret_cast<C *>(out) + g * (long)L;
+        if (accumulate) {
+            // the old values are read GA at a time, so that their loads are
+            // waited on once per group rather than once per store
+            constexpr int GA = R2 < 8 ? R2 : 8;
 #pragma unroll
-        for (int i = 0; i < R2; ++i) {
-            const int n = out_index<R1, R2, PAIR>(t, i);
-            C val = Z[i];
-            if (accumulate) val = cadd(val, dst[n]);
-            dst[n] = val;
+            for (int i0 = 0; i0 < R2; i0 += GA) {
+                C old[GA];
+#pragma unroll
+                for (int c = 0; c < GA; ++c) old[c] = dst[out_index<R1, R2, PAIR>(t, i0 + c)];
+#pragma unroll
+                for (int c = 0; c < GA; ++c)
+                    dst[out_index<R1, R2, PAIR>(t, i0 + c)] = cadd(Z[i0 + c], old[c]);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < R2; ++i) dst[out_index<R1, R2, PAIR>(t, i)] = Z[i];
         }
     }
 }
