@@ -148,8 +148,9 @@ typedef struct ps_plan_info {
 int ps_plan_query(const ps_plan *plan, ps_plan_info *info);
 
 /* Time the implemented kernel variants (x transform, y transform, column
- * solve) for this plan on its stream, reps timed solves per candidate, by
- * coordinate descent, and keep the fastest.  Uses two temporary device fields
+ * solve) for this plan on its stream by coordinate descent, each candidate
+ * in two interleaved rounds of reps timed solves (the faster round counts),
+ * and keep the fastest.  Uses two temporary device fields
  * of the plan's size.  Choices are cached per (device architecture, nx, ny,
  * nz, precision) for the life of the process -- a later autotune of an equal
  * plan just applies them -- and can be saved to / loaded from a text file
