@@ -35,7 +35,8 @@ __global__ __launch_bounds__(NT) void k_fft_y_fast(cx_t<T> *__restrict__ spec, i
     const int r = threadIdx.x / R1, t = threadIdx.x - r * R1;
     const long rr = (long)tile_of(blockIdx.x, gridDim.x, swz) * RB + r;
     const bool ok = rr < nrows;
-    const long row = ok ? (rr / kxcnt) * nkx + kxlo + rr % kxcnt : 0;
+    const unsigned ur = ok ? (unsigned)rr : 0u; // rows < 2^31
+    const long row = ok ? (long)(ur / (unsigned)kxcnt) * nkx + kxlo + ur % (unsigned)kxcnt : 0;
     C *base = spec + row * (long)L;
     C v[R2], w[R2];
 #pragma unroll
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
     double s = 0.0;
     if constexpr (RES) {
         const long gg = ok ? g : 0;
-        const int lev = (int)(gg / ny), j = (int)(gg - (long)lev * ny);
+        const int lev = (int)((unsigned)gg / (unsigned)ny), j = (int)(gg - (long)lev * ny);
         const double au = rc[3 * lev], ad = rc[3 * lev + 1], ac = rc[3 * lev + 2];
         const C *P = reinterpret_cast<const C *>(pres);
         const C *pc_row = P + gg * L;
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
     static_assert(NT % ROWS == 0, "rows per block must divide the block");
     const long g2 = g0 + threadIdx.x % ROWS;
     if (g2 < nrows) {
-        const long lev = g2 / ny, jj = g2 - lev * ny;
+        const long lev = (unsigned)g2 / (unsigned)ny, jj = g2 - lev * ny; // rows < 2^31
         C *dst = spec + lev * L * (long)ny + jj;
 #pragma unroll
         for (int i = 0; i < R2; ++i) {
@@ -277,7 +278,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
     {
         const int rr = threadIdx.x % ROWS;
         const long g2 = tile * ROWS + rr < nrows ? tile * ROWS + rr : 0;
-        const long lev = g2 / ny, jj = g2 - lev * ny;
+        const long lev = (unsigned)g2 / (unsigned)ny, jj = g2 - lev * ny; // rows < 2^31
         const C *src = spec + lev * L * (long)ny + jj;
 #pragma unroll
         for (int i = 0; i < R2; ++i) {

@@ -239,7 +239,7 @@ __device__ void columns3_tile(cx_t<T> *__restrict__ spec, int L, int ny, const T
     const int pair = w >> 1, half = w & 1;
     const long col = c0 + (group * 2 + pair) * 64 + lane;
     const bool valid = col < c1;
-    const int kx = valid ? (int)(col / ny) : 1;
+    const int kx = valid ? (int)((unsigned)col / (unsigned)ny) : 1; // col < 2^31
     const int ky = valid ? (int)(col - (long)kx * ny) : 0;
     const T s = ax[kx] + ay[ky];
     bool store = valid;
@@ -353,7 +353,7 @@ __device__ void columns3r_tile(float2 *__restrict__ spec, int L, int ny, const f
     const int pair = w >> 1, half = w & 1;
     const long col = c0 + (group * 2 + pair) * 64 + lane;
     const bool valid = col < c1;
-    const int kx = valid ? (int)(col / ny) : 1;
+    const int kx = valid ? (int)((unsigned)col / (unsigned)ny) : 1; // col < 2^31
     const int ky = valid ? (int)(col - (long)kx * ny) : 0;
     const float s = ax[kx] + ay[ky];
     const double s64 = ax64[kx] + ay64[ky];
@@ -532,7 +532,7 @@ __device__ void columns3s_tile(cx_t<T> *__restrict__ spec, int L, int ny, const 
     };
     const long col = c0 + (group * PPB + pair) * 32 + (lane >> 1);
     const bool valid = col < c1;
-    const int kx = valid ? (int)(col / ny) : 1;
+    const int kx = valid ? (int)((unsigned)col / (unsigned)ny) : 1; // col < 2^31
     const int ky = valid ? (int)(col - (long)kx * ny) : 0;
     const T s = ax[kx] + ay[ky];
     bool store = valid;

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void k_columns(cx_t<T> *__restrict__ spec, int
     const int half = lane >> 5, comp = lane & 1, cl = (lane & 31) >> 1;
     const long col = c0 + ((long)blockIdx.x * 4 + wave) * 16 + cl;
     const bool valid = col < c1;
-    const int kx = valid ? (int)(col / ny) : 1;
+    const int kx = valid ? (int)((unsigned)col / (unsigned)ny) : 1; // col < 2^31
     const int ky = valid ? (int)(col - (long)kx * ny) : 0;
     const T s = ax[kx] + ay[ky];
     bool store = valid;
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(256) void k_columns2(cx_t<T> *__restrict__ spec, in
     const int half = lane >> 5, cl = lane & 31;
     const long col = c0 + ((long)blockIdx.x * 4 + wave) * 32 + cl;
     const bool valid = col < c1;
-    const int kx = valid ? (int)(col / ny) : 1;
+    const int kx = valid ? (int)((unsigned)col / (unsigned)ny) : 1; // col < 2^31
     const int ky = valid ? (int)(col - (long)kx * ny) : 0;
     const T s = ax[kx] + ay[ky];
     bool store = valid;
