@@ -155,9 +155,10 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
             s += ok ? (double)v[q].x + (double)v[q].y : 0.0;
         }
     } else {
+        // a row past the end reads row 0: transformed, never stored
 #pragma unroll
         for (int q = 0; q < R2; ++q) {
-            v[q] = ok ? src[t + R1 * q] : C{T(0), T(0)};
+            v[q] = src[t + R1 * q];
             s += (double)v[q].x + (double)v[q].y;
         }
     }
