@@ -9,6 +9,22 @@
 
 namespace ps {
 
+// Loads and stores of data that the solve does not touch again (the
+// right-hand side in the forward x pass, the spectrum and the result in the
+// backward x pass), marked non-temporal.
+template <typename T> __device__ __forceinline__ cx_t<T> nt_load(const cx_t<T> *p)
+{
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 r = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
+    return cx_t<T>{r.x, r.y};
+}
+template <typename T> __device__ __forceinline__ void nt_store(cx_t<T> v, cx_t<T> *p)
+{
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 r = {v.x, v.y};
+    __builtin_nontemporal_store(r, reinterpret_cast<v2 *>(p));
+}
+
 // LDS slot of element (kx, rr) of the x passes' [kx][row] staging (ROWS rows
 // of L values): rows XOR-swizzled per kx so that both the column-wise writes
 // (R1 consecutive kx of each row) and the row-wise reads (ROWS consecutive
@@ -158,7 +174,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
         // a row past the end reads row 0: transformed, never stored
 #pragma unroll
         for (int q = 0; q < R2; ++q) {
-            v[q] = src[t + R1 * q];
+            v[q] = nt_load<T>(&src[t + R1 * q]);
             s += (double)v[q].x + (double)v[q].y;
         }
     }
@@ -284,7 +300,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
 #pragma unroll
         for (int i = 0; i < R2; ++i) {
             const int kx = threadIdx.x / ROWS + (NT / ROWS) * i;
-            const C x = src[(long)kx * ny];
+            const C x = nt_load<T>(&src[(long)kx * ny]);
             inr[i] = x.x;
             ini[i] = x.y;
         }
@@ -352,7 +368,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < R2; ++i) dst[out_index<R1, R2, PAIR>(t, i)] = Z[i];
+            for (int i = 0; i < R2; ++i) nt_store<T>(Z[i], &dst[out_index<R1, R2, PAIR>(t, i)]);
         }
     }
 }
