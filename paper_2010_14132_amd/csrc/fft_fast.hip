@@ -9,6 +9,17 @@
 
 namespace ps {
 
+// LDS slot of element (kx, rr) of the x passes' [kx][row] staging (ROWS rows
+// of L values): rows XOR-swizzled per kx so that both the column-wise writes
+// (R1 consecutive kx of each row) and the row-wise reads (ROWS consecutive
+// rows of each kx) hit distinct banks.
+template <int R1, int ROWS> __device__ __forceinline__ int stage_idx(int kx, int rr)
+{
+    constexpr int KB = R1 / ROWS > 1 ? R1 / ROWS : 1;
+    constexpr int KM = ROWS / R1 > 1 ? ROWS / R1 : 1;
+    return kx * ROWS + (rr ^ (((kx / KB) * KM) & (ROWS - 1)));
+}
+
 // Loads and stores of data that the solve does not touch again (the
 // right-hand side in the forward x pass, the spectrum and the result in the
 // backward x pass), marked non-temporal.
@@ -23,17 +34,6 @@ template <typename T> __device__ __forceinline__ void nt_store(cx_t<T> v, cx_t<T
     typedef T v2 __attribute__((ext_vector_type(2)));
     const v2 r = {v.x, v.y};
     __builtin_nontemporal_store(r, reinterpret_cast<v2 *>(p));
-}
-
-// LDS slot of element (kx, rr) of the x passes' [kx][row] staging (ROWS rows
-// of L values): rows XOR-swizzled per kx so that both the column-wise writes
-// (R1 consecutive kx of each row) and the row-wise reads (ROWS consecutive
-// rows of each kx) hit distinct banks.
-template <int R1, int ROWS> __device__ __forceinline__ int stage_idx(int kx, int rr)
-{
-    constexpr int KB = R1 / ROWS > 1 ? R1 / ROWS : 1;
-    constexpr int KM = ROWS / R1 > 1 ? ROWS / R1 : 1;
-    return kx * ROWS + (rr ^ (((kx / KB) * KM) & (ROWS - 1)));
 }
 
 // ---------------------------------------------------------------- y pass

@@ -163,7 +163,9 @@ __device__ void inv_x_tile(const cx_t<T> *__restrict__ spec, T *__restrict__ out
 // table) is the instruction's scalar offset and the column's lane part its
 // 32-bit vector offset, so no 64-bit address arithmetic runs per access.
 // Both offsets stay below 2^32: the spectrum of the supported sizes is at
-// most 2 GiB.  Raw (untyped) 32-bit data format, no range clamp.
+// most 2 GiB.  Raw (untyped) 32-bit data format, no range clamp.  The loads
+// are non-temporal: the kernel overwrites what it reads.
+constexpr int kNonTemporal = 2; // buffer instruction cache policy: nt
 struct ColBuf {
     __amdgpu_buffer_rsrc_t r;
     unsigned lane_off;
@@ -178,11 +180,11 @@ template <typename V> __device__ __forceinline__ V col_load(const ColBuf &b, lon
 {
     static_assert(sizeof(V) == 4 || sizeof(V) == 8 || sizeof(V) == 16, "element size");
     if constexpr (sizeof(V) == 4)
-        return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(b.r, b.lane_off, (int)off, 0));
+        return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(b.r, b.lane_off, (int)off, kNonTemporal));
     else if constexpr (sizeof(V) == 8)
-        return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(b.r, b.lane_off, (int)off, 0));
+        return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(b.r, b.lane_off, (int)off, kNonTemporal));
     else
-        return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(b.r, b.lane_off, (int)off, 0));
+        return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(b.r, b.lane_off, (int)off, kNonTemporal));
 }
 template <typename V> __device__ __forceinline__ void col_store(const ColBuf &b, long long off, V v)
 {
