@@ -21,8 +21,9 @@ template <int R1, int ROWS> __device__ __forceinline__ int stage_idx(int kx, int
 }
 
 // Loads and stores of data that the solve does not touch again (the
-// right-hand side in the forward x pass, the spectrum and the result in the
-// backward x pass), marked non-temporal.
+// right-hand side in the forward x pass and in the residual transform, the
+// spectrum, the result and the accumulated old values in the backward x
+// pass), marked non-temporal.
 template <typename T> __device__ __forceinline__ cx_t<T> nt_load(const cx_t<T> *p)
 {
     typedef T v2 __attribute__((ext_vector_type(2)));
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
             const T er_a = __shfl(pc[q].x, right, 64);
             const T er_b = __shfl(pc[(q + 1) % R2].x, right, 64);
             const T xe = t == R1 - 1 ? er_b : er_a;
-            const C bv = src[n], pn = pn_row[n], psd = ps_row[n];
+            const C bv = nt_load<T>(&src[n]), pn = pn_row[n], psd = ps_row[n];
             // unconditional: at the top and bottom levels the row pointer is
             // this row and its coefficient (au or ad) is exactly zero, so no
             // branch (and no wait for the load inside it) is needed
@@ -361,10 +362,11 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
             for (int i0 = 0; i0 < R2; i0 += GA) {
                 C old[GA];
 #pragma unroll
-                for (int c = 0; c < GA; ++c) old[c] = dst[out_index<R1, R2, PAIR>(t, i0 + c)];
+                for (int c = 0; c < GA; ++c)
+                    old[c] = nt_load<T>(&dst[out_index<R1, R2, PAIR>(t, i0 + c)]);
 #pragma unroll
                 for (int c = 0; c < GA; ++c)
-                    dst[out_index<R1, R2, PAIR>(t, i0 + c)] = cadd(Z[i0 + c], old[c]);
+                    nt_store<T>(cadd(Z[i0 + c], old[c]), &dst[out_index<R1, R2, PAIR>(t, i0 + c)]);
             }
         } else {
 #pragma unroll
