@@ -20,10 +20,10 @@ template <int R1, int ROWS> __device__ __forceinline__ int stage_idx(int kx, int
     return kx * ROWS + (rr ^ (((kx / KB) * KM) & (ROWS - 1)));
 }
 
-// Loads and stores of data that the solve does not touch again (the
-// right-hand side in the forward x pass and in the residual transform, the
-// spectrum, the result and the accumulated old values in the backward x
-// pass), marked non-temporal.
+// Non-temporal loads and stores: of data that the solve does not touch
+// again (the right-hand side in the forward x pass and in the residual
+// transform, the spectrum, the result and the accumulated old values in the
+// backward x pass), and the forward y pass's stores.
 template <typename T> __device__ __forceinline__ cx_t<T> nt_load(const cx_t<T> *p)
 {
     typedef T v2 __attribute__((ext_vector_type(2)));
@@ -60,10 +60,19 @@ __global__ __launch_bounds__(NT) void k_fft_y_fast(cx_t<T> *__restrict__ spec, i
     for (int q = 0; q < R2; ++q) v[q] = base[t + R1 * q]; // past the end: row 0, not stored
     four_step<R1, R2, DIR>(v, w, t, lds + r * S, tw4);
     if (ok) {
+        // the forward pass stores non-temporally: its rows are read next by
+        // the column kernel, which then does not pay for writing back this
+        // pass's dirty lines (measured; the backward pass measured better
+        // with plain stores)
 #pragma unroll
         for (int j = 0; j < R2 / R1; ++j)
 #pragma unroll
-            for (int k1 = 0; k1 < R1; ++k1) base[(t + R1 * j) + R2 * k1] = w[j * R1 + k1];
+            for (int k1 = 0; k1 < R1; ++k1) {
+                if constexpr (DIR < 0)
+                    nt_store<T>(w[j * R1 + k1], &base[(t + R1 * j) + R2 * k1]);
+                else
+                    base[(t + R1 * j) + R2 * k1] = w[j * R1 + k1];
+            }
     }
 }
 

@@ -163,8 +163,10 @@ __device__ void inv_x_tile(const cx_t<T> *__restrict__ spec, T *__restrict__ out
 // table) is the instruction's scalar offset and the column's lane part its
 // 32-bit vector offset, so no 64-bit address arithmetic runs per access.
 // Both offsets stay below 2^32: the spectrum of the supported sizes is at
-// most 2 GiB.  Raw (untyped) 32-bit data format, no range clamp.  The loads
-// are non-temporal: the kernel overwrites what it reads.
+// most 2 GiB.  Raw (untyped) 32-bit data format, no range clamp.  Loads and
+// stores are non-temporal: the kernel overwrites what it reads, and its
+// stores, written through rather than left dirty in the caches, no longer
+// cost the next pass their write-back.
 constexpr int kNonTemporal = 2; // buffer instruction cache policy: nt
 struct ColBuf {
     __amdgpu_buffer_rsrc_t r;
@@ -190,15 +192,15 @@ template <typename V> __device__ __forceinline__ void col_store(const ColBuf &b,
 {
     if constexpr (sizeof(V) == 4)
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), b.r, b.lane_off,
-                                              (int)off, 0);
+                                              (int)off, kNonTemporal);
     else if constexpr (sizeof(V) == 8)
         __builtin_amdgcn_raw_buffer_store_b64(
             __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), b.r, b.lane_off,
-            (int)off, 0);
+            (int)off, kNonTemporal);
     else
         __builtin_amdgcn_raw_buffer_store_b128(
             __builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), b.r, b.lane_off,
-            (int)off, 0);
+            (int)off, kNonTemporal);
 }
 
 __device__ __forceinline__ float pivot_rcp(float u)
