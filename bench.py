@@ -132,20 +132,26 @@ def cpu_baseline(g, nz_full: int):
             "mpts_per_s": g.nx * g.ny * nz_full / t_full / 1e6}
 
 
-def time_solves(plan, b, out, steps, warmup):
+def time_calls(call, steps, warmup):
+    """Mean ms per call of `call` (work enqueued on the current stream),
+    after `warmup` untimed calls."""
     import torch
     for _ in range(warmup):
-        plan.solve(b, out=out)
+        call()
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(st)
     for _ in range(steps):
-        plan.solve(b, out=out)
+        call()
     e1.record(st)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def time_solves(plan, b, out, steps, warmup):
+    return time_calls(lambda: plan.solve(b, out=out), steps, warmup)
 
 
 def main():
@@ -223,6 +229,18 @@ def main():
                                       "column_variant", "chunks")}}
         outputs[form] = out
         print("bench: %-8s %.4f ms/solve" % (form, ms), file=sys.stderr, flush=True)
+        if form == args.precision:
+            # the differentiation path of the same form: the adjoint solve
+            # (gp = the right-hand side) and the density gradient from the
+            # adjoint field and the solution
+            lam = torch.empty_like(b)
+            results[form]["adjoint_ms_per_solve"] = time_calls(
+                lambda: plan.solve_adjoint(b, out=lam), steps, args.warmup)
+            results[form]["grad_rho_ms"] = time_calls(
+                lambda: plan.grad_coeffs(lam, out), steps, args.warmup)
+            print("bench: %-8s adjoint %.4f ms, grad-rho %.4f ms"
+                  % (form, results[form]["adjoint_ms_per_solve"], results[form]["grad_rho_ms"]),
+                  file=sys.stderr, flush=True)
         # per-kernel event timing (a separate pass: events add a little per launch)
         plan.profile(True)
         for _ in range(steps):

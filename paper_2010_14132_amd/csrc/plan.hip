@@ -290,11 +290,13 @@ static int upload_residual_table(ps_plan *p)
 static int upload_grad_table(ps_plan *p)
 {
     const int nz = p->nz;
-    std::vector<double> gk(4 * (size_t)nz + 2, 0.0);
+    std::vector<double> gk(6 * (size_t)nz + 2, 0.0);
     for (int k = 0; k <= nz; ++k) gk[k] = p->f[k];
     for (int k = 0; k < nz; ++k) {
         gk[nz + 1 + k] = p->D[k];
         gk[2 * nz + 1 + k] = p->rho[k];
+        gk[4 * nz + 2 + k] = 1.0 / p->D[k];
+        gk[5 * nz + 2 + k] = 1.0 / p->rho[k];
     }
     for (int k = 1; k < nz; ++k) gk[3 * nz + 1 + k] = 2.0 / (p->dz[k - 1] + p->dz[k]);
     return upload(p->d_gk, gk);
@@ -414,7 +416,7 @@ extern "C" int ps_plan_create(ps_plan **out, int nx, int ny, int nz, double dx, 
     step(dev_alloc(p, &p->d_rowsum, (size_t)ny * nz));
     step(dev_alloc(p, &p->d_S, (size_t)nz));
     step(dev_alloc(p, &p->d_ws, 6 * (size_t)nz * ntask));
-    step(dev_alloc(p, &p->d_gk, 4 * (size_t)nz + 2));
+    step(dev_alloc(p, &p->d_gk, 6 * (size_t)nz + 2));
     step(dev_alloc(p, &p->d_partial, (size_t)nz * p->nblk));
     step(dev_alloc(p, &p->d_rc, 6 * (size_t)nz));
     step(dev_alloc(p, &p->d_maskcnt, (size_t)p->L));

@@ -12,6 +12,8 @@
 // ends towards the middle row m = nz/2 (a "twisted" factorisation), each half
 // in dominance-excess form (pivot u = e + f_next with
 // e_i = s D_i + f_prev e_{i-1}/u_{i-1}, built from positive terms only).
+#include <algorithm>
+
 #include "ps_internal.h"
 #include "ps_tiles.h"
 #include "../../include/pressure_solve.h"
@@ -724,10 +726,14 @@ template hipError_t launch_special<double>(cx_t<double> *, int, int, int, int, c
 //                 + 1/2 gam_{k-1/2} (lam_{k-1}/D_{k-1} - lam_k/D_k) ],
 // gam_{k+1/2} = (p_{k+1} - p_k) / h_{k+1/2}: the derivative of the vertical
 // operator's three rho-dependent ingredients (1/D_k of row k and the face
-// densities on either side of level k).  Thread per horizontal point, a
-// chunk of GK levels per block row; per-level block sums are written in
-// fixed order and reduced by k_grad_reduce (no atomics).
-// gk = [f (nz+1) | D (nz) | rho (nz) | 1/h (nz+1, same indexing as f)].
+// densities on either side of level k).  A block row handles a chunk of GK
+// levels; each thread walks a fixed set of horizontal points (grid stride)
+// and sums its terms per level in registers, so that the wave reduction runs
+// once per thread, not once per point.  Per-level block sums are written in
+// fixed order and reduced by k_grad_reduce (no atomics): the result is the
+// same on every run.
+// gk = [f (nz+1) | D (nz) | rho (nz) | 1/h (nz+1, same indexing as f) |
+//       1/D (nz) | 1/rho (nz)].
 constexpr int GK = 16;
 
 template <typename T>
@@ -737,30 +743,41 @@ __global__ __launch_bounds__(256) void k_grad_rho(const T *__restrict__ lam, con
 {
     __shared__ double red[4][GK];
     const double *f = gk, *D = gk + nz + 1, *rho = D + nz, *ih = rho + nz;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const double *iD = ih + nz + 1, *irho = iD + nz;
+    (void)D;
+    (void)rho;
     const int k0 = blockIdx.y * GK;
-    const bool ok = c < nxy;
-    auto P = [&](int k) { return ok && k >= 0 && k < nz ? (double)p[(size_t)k * nxy + c] : 0.0; };
-    auto Lm = [&](int k) { return ok && k >= 0 && k < nz ? (double)lam[(size_t)k * nxy + c] : 0.0; };
-    double pm = P(k0 - 1), pc = P(k0), lm = Lm(k0 - 1), lc = Lm(k0);
+    double acc[GK];
+#pragma unroll
+    for (int kk = 0; kk < GK; ++kk) acc[kk] = 0.0;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nxy; c += gridDim.x * blockDim.x) {
+        auto P = [&](int k) { return k >= 0 && k < nz ? (double)p[(size_t)k * nxy + c] : 0.0; };
+        auto Lm = [&](int k) { return k >= 0 && k < nz ? (double)lam[(size_t)k * nxy + c] : 0.0; };
+        double pm = P(k0 - 1), pc = P(k0), lm = Lm(k0 - 1), lc = Lm(k0);
+#pragma unroll
+        for (int kk = 0; kk < GK; ++kk) {
+            const int k = k0 + kk;
+            if (k < nz) { // uniform: the last chunk may hold fewer levels
+                const double pp = P(k + 1), lp = Lm(k + 1);
+                const double up = k + 1 < nz ? f[k + 1] * (pp - pc) : 0.0;
+                const double dn = k > 0 ? f[k] * (pc - pm) : 0.0;
+                const double Vp = (up - dn) * iD[k];
+                double t = -lc * Vp * irho[k];
+                if (k + 1 < nz) t += 0.5 * (pp - pc) * ih[k + 1] * (lc * iD[k] - lp * iD[k + 1]);
+                if (k > 0) t += 0.5 * (pc - pm) * ih[k] * (lm * iD[k - 1] - lc * iD[k]);
+                acc[kk] += t;
+                pm = pc;
+                pc = pp;
+                lm = lc;
+                lc = lp;
+            }
+        }
+    }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
     for (int kk = 0; kk < GK; ++kk) {
-        const int k = k0 + kk;
-        if (k >= nz) break;
-        const double pp = P(k + 1), lp = Lm(k + 1);
-        double Vp = 0.0, t = 0.0;
-        if (k + 1 < nz) Vp += f[k + 1] * (pp - pc);
-        if (k > 0) Vp -= f[k] * (pc - pm);
-        Vp /= D[k];
-        t = -lc * Vp / rho[k];
-        if (k + 1 < nz) t += 0.5 * (pp - pc) * ih[k + 1] * (lc / D[k] - lp / D[k + 1]);
-        if (k > 0) t += 0.5 * (pc - pm) * ih[k] * (lm / D[k - 1] - lc / D[k]);
-        t = wave_sum(ok ? t : 0.0);
+        const double t = wave_sum(acc[kk]);
         if (lane == 0) red[wv][kk] = t;
-        pm = pc;
-        pc = pp;
-        lm = lc;
-        lc = lp;
     }
     __syncthreads();
     if (threadIdx.x < GK && k0 + (int)threadIdx.x < nz) {
@@ -770,17 +787,27 @@ __global__ __launch_bounds__(256) void k_grad_rho(const T *__restrict__ lam, con
     }
 }
 
-__global__ void k_grad_reduce(const double *__restrict__ partial, int nblk, int nz,
-                              double *__restrict__ g)
+// One block per level: a fixed-order strided sum of the block partials per
+// thread, then a fixed tree over the block.
+__global__ __launch_bounds__(256) void k_grad_reduce(const double *__restrict__ partial, int nblk,
+                                                     int nz, double *__restrict__ g)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nz) return;
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partial[(size_t)k * nblk + b];
-    g[k] = -s;
+    __shared__ double s[256];
+    const int k = blockIdx.x;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) v += partial[(size_t)k * nblk + b];
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && k < nz) g[k] = -s[0];
 }
 
-int grad_blocks(int nx, int ny) { return (nx * ny + 255) / 256; }
+// Blocks per level chunk: one thread per point up to 1024 blocks, beyond
+// which threads take several points.
+int grad_blocks(int nx, int ny) { return std::min((nx * ny + 255) / 256, 1024); }
 
 template <typename T>
 hipError_t launch_grad_rho(const T *lam, const T *p, int nx, int ny, int nz, const double *gk,
@@ -791,8 +818,7 @@ hipError_t launch_grad_rho(const T *lam, const T *p, int nx, int ny, int nz, con
                        nblk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_grad_reduce, dim3((nz + 63) / 64), dim3(64), 0, st, partial, nblk, nz,
-                       grho);
+    hipLaunchKernelGGL(k_grad_reduce, dim3(nz), dim3(256), 0, st, partial, nblk, nz, grho);
     return hipGetLastError();
 }
 
