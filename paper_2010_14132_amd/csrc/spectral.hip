@@ -751,14 +751,23 @@ __global__ __launch_bounds__(256) void k_grad_rho(const T *__restrict__ lam, con
 #pragma unroll
     for (int kk = 0; kk < GK; ++kk) acc[kk] = 0.0;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nxy; c += gridDim.x * blockDim.x) {
-        auto P = [&](int k) { return k >= 0 && k < nz ? (double)p[(size_t)k * nxy + c] : 0.0; };
-        auto Lm = [&](int k) { return k >= 0 && k < nz ? (double)lam[(size_t)k * nxy + c] : 0.0; };
-        double pm = P(k0 - 1), pc = P(k0), lm = Lm(k0 - 1), lc = Lm(k0);
+        // All GK + 2 levels of the chunk are loaded up front from clamped
+        // indices, so that every load is issued before the first is waited
+        // for; a clamped value only enters terms that the k > 0 and
+        // k + 1 < nz conditions below leave out.
+        T pv[GK + 2], lv[GK + 2];
+#pragma unroll
+        for (int j = 0; j < GK + 2; ++j) {
+            const int k = min(max(k0 - 1 + j, 0), nz - 1);
+            pv[j] = p[(size_t)k * nxy + c];
+            lv[j] = lam[(size_t)k * nxy + c];
+        }
 #pragma unroll
         for (int kk = 0; kk < GK; ++kk) {
             const int k = k0 + kk;
             if (k < nz) { // uniform: the last chunk may hold fewer levels
-                const double pp = P(k + 1), lp = Lm(k + 1);
+                const double pm = pv[kk], pc = pv[kk + 1], pp = pv[kk + 2];
+                const double lm = lv[kk], lc = lv[kk + 1], lp = lv[kk + 2];
                 const double up = k + 1 < nz ? f[k + 1] * (pp - pc) : 0.0;
                 const double dn = k > 0 ? f[k] * (pc - pm) : 0.0;
                 const double Vp = (up - dn) * iD[k];
@@ -766,10 +775,6 @@ __global__ __launch_bounds__(256) void k_grad_rho(const T *__restrict__ lam, con
                 if (k + 1 < nz) t += 0.5 * (pp - pc) * ih[k + 1] * (lc * iD[k] - lp * iD[k + 1]);
                 if (k > 0) t += 0.5 * (pc - pm) * ih[k] * (lm * iD[k - 1] - lc * iD[k]);
                 acc[kk] += t;
-                pm = pc;
-                pc = pp;
-                lm = lc;
-                lc = lp;
             }
         }
     }
