@@ -301,6 +301,52 @@ def test_full_size_precision_1024_spectral_samples():
         del p
 
 
+def test_full_size_adjoint_spectral_samples():
+    """Adjoint solve at 1024^2 x 128 in the configuration the benchmark times
+    (FP32 + in-register refinement, autotuned, the right-hand side as input):
+    sampled wavenumber columns against D (-sI + V)^-1 (D^-1 w_hat), the
+    transposed column system (identity checked against the oracle's full
+    adjoint in tests/test_sampling_identities.py)."""
+    from tests import sampling
+    prob = wl.precision_1024("f32")
+    g = prob.grid
+    w32 = prob.rhs_as("f32")
+    w = w32.astype(np.float64)
+    announce("full size 1024^2x128 adjoint fp32_r2")
+    lam = run(g, w32, "fp32_r2", adjoint=True, autotune=True)
+    scale, errs = 0.0, []
+    for kx, ky in SAMPLE_MODES:
+        want = sampling.adjoint_column(w, kx, ky, g.dx, g.dy, g.dz, g.rho)
+        got = sampling.dft_at(lam, kx, ky)
+        scale = max(scale, np.abs(want).max())
+        errs.append(np.abs(got - want).max())
+    err = max(errs) / scale
+    print("adjoint sampled spectral rel err %.3e" % err)
+    assert err < TOL32
+
+
+def test_full_size_grad_coeffs():
+    """Density gradient at 1024^2 x 128 (four horizontal points per thread,
+    eight full 16-level chunks) against the oracle on every level, for
+    seeded FP32 fields promoted exactly to FP64.  Both sides accumulate in
+    FP64; the bound leaves three orders of magnitude over the summation
+    error of a million terms per level."""
+    prob = wl.precision_1024("f32")
+    g = prob.grid
+    rng = np.random.default_rng(31)
+    shape = (g.nz, g.ny, g.nx)
+    lam = rng.standard_normal(shape, dtype=np.float32)
+    p = rng.standard_normal(shape, dtype=np.float32) + np.float32(0.5)
+    announce("full size 1024^2x128 grad_coeffs fp32_r2")
+    ref = oracle.grad_rho(lam.astype(np.float64), p.astype(np.float64), g.dx, g.dy, g.dz, g.rho)
+    plan = make_plan(g, "fp32_r2")
+    gk = plan.grad_coeffs(torch.from_numpy(lam).cuda(), torch.from_numpy(p).cuda()).cpu().numpy()
+    plan.close()
+    err = np.abs(gk - ref).max() / np.abs(ref).max()
+    print("grad_coeffs full size rel err %.3e" % err)
+    assert err < 1e-10
+
+
 # ----------------------------------------------------------------- variants
 def _arch():
     return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
