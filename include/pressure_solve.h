@@ -114,7 +114,12 @@ int ps_plan_set_coeffs(ps_plan *plan, const double *rho);
  * tridiagonal solve per wavenumber column, backward transform).
  *   rhs : device [nz][ny][nx], read only.
  *   p   : device [nz][ny][nx], written.  May alias rhs except for
- *         PS_FP32_R1 (PS_EINVAL).  rhs is not modified. */
+ *         PS_FP32_R1 (PS_EINVAL).  rhs is not modified.
+ * ps_solve, ps_solve_adjoint and ps_grad_coeffs only enqueue kernels and
+ * event records / waits on the plan's stream (the FP64 columns fork onto the
+ * plan's second stream and join back): no allocation, no memset, no
+ * synchronisation, so a caller may capture them into a HIP graph on that
+ * stream and replay it with the same pointers. */
 int ps_solve(ps_plan *plan, const void *rhs, void *p);
 
 /* Adjoint solve: grhs = S^T gp, the lambda-block of
