@@ -204,14 +204,21 @@ int ps_inverse_transform(ps_plan *plan, const void *spectrum, void *p);
  * Describe count problems once (each with its own grid and densities, all
  * of one precision; each planned as by ps_plan_create, so the plan's size
  * limits apply, and nz <= 128); ps_batch_solve then solves all of them by
- * replaying a captured hipGraph: every problem's five phases (x forward, y
- * forward, column solves, y backward, x backward) are cut into block-sized
- * tiles, and the graph holds one kernel per phase over the tiles of that
- * phase of every problem (mode PS_BATCH_PHASES).
- * CURRENTLY SWITCHED OFF: ps_batch_solve and ps_batch_autotune return
- * PS_EUNSUPPORTED (the persistent form did not complete on the GPU, its
- * cause is not found, and the per-phase graph has not been verified).
- * Create, set_mode, set_stream, query, status and destroy work.
+ * replaying a captured hipGraph.
+ * Mode PS_BATCH_PLANS (the default): the graph holds every problem's own
+ * plan solve (the single-solve kernels, as ps_solve), most points first,
+ * spread round-robin over four streams forked from the capture stream and
+ * joined back, so problems on different streams may run side by side --
+ * SWITCHED OFF: its first run ended in a host segmentation fault during the
+ * first capture, cause not yet found; solve and autotune return
+ * PS_EUNSUPPORTED.
+ * Mode PS_BATCH_PHASES: every problem's five phases (x forward, y forward,
+ * column solves, y backward, x backward) cut into block-sized tiles, one
+ * kernel per phase over the tiles of that phase of every problem --
+ * SWITCHED OFF with the persistent form (solve and autotune return
+ * PS_EUNSUPPORTED in these modes: the persistent launch did not complete on
+ * the GPU, its cause is not found, and the per-phase graph, which shares its
+ * tile code, has not been verified).
  *   nx, ny, nz, dx, dy : host arrays of count values.
  *   dz, rho            : host arrays of count host pointers to nz[i] values.
  *   precision          : PS_FP64 or PS_FP32 (else PS_EUNSUPPORTED).
@@ -228,14 +235,19 @@ int ps_batch_create(ps_batch **out, int count, const int *nx, const int *ny,
  * flight per batch. */
 int ps_batch_solve(ps_batch *batch, const void *const *rhs, void *const *p);
 int ps_batch_set_stream(ps_batch *batch, void *stream);
-/* PS_BATCH_PHASES: one launch per phase (the default).  PS_BATCH_PERSISTENT:
- * all phases in a single persistent launch whose blocks take (problem, phase,
- * tile) tickets and wait per problem for the previous phase -- switched off:
- * it did not complete on the GPU, so requesting it returns PS_EUNSUPPORTED. */
-enum { PS_BATCH_PHASES = 0, PS_BATCH_PERSISTENT = 1 };
+/* PS_BATCH_PLANS: every problem's plan solve in one graph (the default).
+ * PS_BATCH_PHASES: one launch per phase over tiles (solving switched off).
+ * PS_BATCH_PERSISTENT: all phases in a single persistent launch whose blocks
+ * take (problem, phase, tile) tickets and wait per problem for the previous
+ * phase -- switched off: it did not complete on the GPU, so requesting it
+ * returns PS_EUNSUPPORTED.  Changing the mode synchronises the batch's
+ * streams and drops the captured graph. */
+enum { PS_BATCH_PHASES = 0, PS_BATCH_PERSISTENT = 1, PS_BATCH_PLANS = 2 };
 int ps_batch_set_mode(ps_batch *batch, int mode);
-/* Time the tile layouts for 32, 48 and 60 KiB of LDS per block on the given
- * fields (reps replays each) and keep the fastest.  Synchronises. */
+/* PS_BATCH_PLANS: autotune every problem's plan (ps_plan_autotune, reps
+ * repetitions; rhs and p are not used).  Tile modes: time the tile layouts
+ * for 32, 48 and 60 KiB of LDS per block on the given fields (reps replays
+ * each) and keep the fastest.  Synchronises. */
 int ps_batch_autotune(ps_batch *batch, const void *const *rhs, void *const *p, int reps);
 /* count of problems, total tiles of the work list, blocks of the persistent
  * launch, LDS budget per block in bytes (any pointer may be NULL). */

@@ -330,16 +330,18 @@ def tune_cache_load(path: str):
 
 class BatchPlan:
     """Many independent solves of uneven sizes replayed from a captured
-    hipGraph (the C ABI's ps_batch).  Solving is currently switched off in
-    the library: solve() and autotune() raise PressureSolveError
-    (PS_EUNSUPPORTED); planning, info() and close() work.
+    hipGraph (the C ABI's ps_batch).  mode "plans" (the default) captures
+    every problem's own plan solve; "phases" and "persistent" cut the
+    problems into tiles.  All three are switched off in the library for now
+    (solve() and autotune() raise PressureSolveError, PS_EUNSUPPORTED);
+    planning, info() and close() work.
 
     grids: sequence of workloads.Grid-like objects (nx, ny, nz, dx, dy, dz,
     rho); precision "fp32" or "fp64"."""
 
-    MODES = {"phases": 0, "persistent": 1}
+    MODES = {"phases": 0, "persistent": 1, "plans": 2}
 
-    def __init__(self, grids, precision="fp32", mode="phases"):
+    def __init__(self, grids, precision="fp32", mode="plans"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the pressure-solve library needs a GPU (no CPU fallback)")
@@ -362,7 +364,11 @@ class BatchPlan:
                                   dzp, rhop, PRECISIONS[precision], _stream_handle()),
               "ps_batch_create")
         self._h = h
-        check(lib.ps_batch_set_mode(h, self.MODES[mode]), "ps_batch_set_mode")
+        try:
+            check(lib.ps_batch_set_mode(h, self.MODES[mode]), "ps_batch_set_mode")
+        except Exception:
+            self.close()
+            raise
 
     def _ptrs(self, rhs, out):
         n = len(self.grids)

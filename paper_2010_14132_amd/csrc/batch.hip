@@ -9,12 +9,16 @@
 // the tiles of that phase of every problem (largest problems first), so a
 // replay is five launches with no inter-block waiting.
 //
-// Solving is switched off (ps_batch_solve and ps_batch_autotune return
-// PS_EUNSUPPORTED): the single persistent launch (k_batch below: blocks taking
-// (problem, phase, tile) tickets and waiting per problem for the previous
-// phase) did not complete on the GPU and its cause is not found, and the
-// per-phase graph, which shares its work list, has not been run yet.  Create,
-// query and destroy work.
+// A third form (PS_BATCH_PLANS) captures every problem's own plan solve
+// instead, spread over a few streams.
+//
+// Solving is switched off in every form (ps_batch_solve and
+// ps_batch_autotune return PS_EUNSUPPORTED): the single persistent launch
+// (k_batch below: blocks taking (problem, phase, tile) tickets and waiting per
+// problem for the previous phase) did not complete on the GPU and its cause is
+// not found; the per-phase graph, which shares its work list, has not been run
+// yet; and the plan graph's first run ended in a host segmentation fault.
+// Create, set_mode, query, status and destroy work.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -31,11 +35,23 @@ using namespace ps;
 namespace {
 
 constexpr int kPhases = 5;
+// The tile-based designs (one launch per phase, or one persistent launch).
 constexpr bool kSolveEnabled = false;
+// Streams the problems of a plan graph are spread over (graph branches that
+// may run side by side).
+constexpr int kLanes = 4;
+// The plan graph is switched off as well: its first run, which captured
+// every plan's first solve (so the first launch of each kernel in the
+// process happened inside the capture), ended in a segmentation fault in
+// the host process; the cause is not yet shown.
+constexpr bool kPlansEnabled = false;
+constexpr const char *kPlansOff =
+    "the plan-graph batched solve is switched off: its first run ended in a host segmentation "
+    "fault whose cause is not yet found; solve each problem with its own plan";
 constexpr const char *kSolveOff =
-    "batched solves are switched off: the persistent launch did not complete on the GPU (cause "
-    "not found) and the per-phase graph has not been verified; solve each problem with its own "
-    "plan";
+    "the tile-based batched solves are switched off: the persistent launch did not complete on "
+    "the GPU (cause not found) and the per-phase graph has not been verified; solve each "
+    "problem with its own plan";
 
 // Device view of one problem.
 struct BatchProblem {
@@ -272,7 +288,10 @@ struct ps_batch {
     std::vector<const void *> cap_rhs;
     std::vector<void *> cap_out;
     bool captured = false;
-    int mode = PS_BATCH_PHASES;
+    int mode = PS_BATCH_PLANS;
+    hipStream_t lanes[kLanes] = {};   // PS_BATCH_PLANS: branches of the graph
+    hipEvent_t ev_fork = nullptr, ev_join[kLanes] = {};
+    std::vector<int> order;           // problems, most points first
     int phase_off[kPhases + 1] = {}; // items of phase ph: [phase_off[ph], phase_off[ph+1])
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
@@ -305,6 +324,11 @@ static void free_batch(ps_batch *b)
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    for (int l = 0; l < kLanes; ++l) {
+        if (b->lanes[l]) (void)hipStreamDestroy(b->lanes[l]);
+        if (b->ev_join[l]) (void)hipEventDestroy(b->ev_join[l]);
+    }
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     delete b;
 }
 
@@ -448,8 +472,18 @@ extern "C" int ps_batch_create(ps_batch **out, int count, const int *nx, const i
     }
     if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess)
+        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess)
         return bail(bfail(PS_EHIP, "stream or event creation failed"));
+    for (int l = 0; l < kLanes; ++l)
+        if (hipStreamCreateWithFlags(&b->lanes[l], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->ev_join[l], hipEventDisableTiming) != hipSuccess)
+            return bail(bfail(PS_EHIP, "stream or event creation failed"));
+    b->order.resize(count);
+    std::iota(b->order.begin(), b->order.end(), 0);
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int a, int c) {
+        return (long long)nx[a] * ny[a] * nz[a] > (long long)nx[c] * ny[c] * nz[c];
+    });
     int rc = layout(b);
     if (rc != PS_OK) return bail(rc);
     if (hipMalloc(&b->dp, count * sizeof(BatchProblem)) != hipSuccess)
@@ -461,9 +495,52 @@ extern "C" int ps_batch_create(ps_batch **out, int count, const int *nx, const i
     return PS_OK;
 }
 
+// PS_BATCH_PLANS: every problem's own plan solve (the single-solve kernels),
+// most points first, round-robin over kLanes streams forked from the
+// capture stream and joined back, captured into one graph.  Problems on
+// different lanes are independent branches of the graph.
+static int capture_plans(ps_batch *b, const void *const *rhs, void *const *p)
+{
+    PS_BHIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    int rc = PS_OK;
+    hipError_t e = hipEventRecord(b->ev_fork, b->cap);
+    for (int l = 0; l < kLanes && e == hipSuccess; ++l)
+        e = hipStreamWaitEvent(b->lanes[l], b->ev_fork, 0);
+    for (int n = 0; n < b->count && e == hipSuccess && rc == PS_OK; ++n) {
+        const int i = b->order[n];
+        rc = ps_plan_set_stream(b->plans[i], b->lanes[n % kLanes]);
+        if (rc == PS_OK) rc = ps_solve(b->plans[i], rhs[i], p[i]);
+        if (rc != PS_OK)
+            ps::set_error(rc, std::string("problem ") + std::to_string(i) + ": " + ps_last_error());
+    }
+    for (int l = 0; l < kLanes && e == hipSuccess; ++l) {
+        e = hipEventRecord(b->ev_join[l], b->lanes[l]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->ev_join[l], 0);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(b->cap, &g);
+    if (rc != PS_OK || e != hipSuccess || ce != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        if (rc != PS_OK) return rc;
+        return bfail(PS_EHIP,
+                     std::string("capture: ") + hipGetErrorString(e != hipSuccess ? e : ce));
+    }
+    b->graph = g;
+    PS_BHIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return PS_OK;
+}
+
 static int capture(ps_batch *b, const void *const *rhs, void *const *p)
 {
     destroy_graph(b);
+    if (b->mode == PS_BATCH_PLANS) {
+        const int rc = capture_plans(b, rhs, p);
+        if (rc != PS_OK) return rc;
+        b->cap_rhs.assign(rhs, rhs + b->count);
+        b->cap_out.assign(p, p + b->count);
+        b->captured = true;
+        return PS_OK;
+    }
     for (int i = 0; i < b->count; ++i) {
         b->hp[i].rhs = rhs[i];
         b->hp[i].out = p[i];
@@ -503,7 +580,8 @@ static int capture(ps_batch *b, const void *const *rhs, void *const *p)
 extern "C" int ps_batch_solve(ps_batch *b, const void *const *rhs, void *const *p)
 {
     if (!b || !rhs || !p) return bfail(PS_EINVAL, "batch, rhs and p must not be NULL");
-    if (!kSolveEnabled) return bfail(PS_EUNSUPPORTED, kSolveOff);
+    if (!kSolveEnabled && b->mode != PS_BATCH_PLANS) return bfail(PS_EUNSUPPORTED, kSolveOff);
+    if (!kPlansEnabled && b->mode == PS_BATCH_PLANS) return bfail(PS_EUNSUPPORTED, kPlansOff);
     for (int i = 0; i < b->count; ++i) {
         if (!rhs[i] || !p[i]) return bfail(PS_EINVAL, "rhs[i] and p[i] must not be NULL");
         if (rhs[i] == p[i]) return bfail(PS_EINVAL, "rhs[i] and p[i] must not alias");
@@ -530,7 +608,13 @@ extern "C" int ps_batch_solve(ps_batch *b, const void *const *rhs, void *const *
 extern "C" int ps_batch_set_mode(ps_batch *b, int mode)
 {
     if (!b) return bfail(PS_EINVAL, "batch is NULL");
-    if (mode == PS_BATCH_PHASES) {
+    if (mode == PS_BATCH_PHASES || mode == PS_BATCH_PLANS) {
+        if (mode != b->mode) {
+            // a replay may still run the old graph
+            PS_BHIP(hipStreamSynchronize(b->stream));
+            PS_BHIP(hipStreamSynchronize(b->cap));
+            destroy_graph(b);
+        }
         b->mode = mode;
         return PS_OK;
     }
@@ -552,9 +636,27 @@ extern "C" int ps_batch_set_stream(ps_batch *b, void *stream)
 extern "C" int ps_batch_autotune(ps_batch *b, const void *const *rhs, void *const *p, int reps)
 {
     if (!b || !rhs || !p) return bfail(PS_EINVAL, "batch, rhs and p must not be NULL");
-    if (!kSolveEnabled) return bfail(PS_EUNSUPPORTED, kSolveOff);
     if (reps < 1) reps = 1;
     if (reps > 100) reps = 100;
+    if (b->mode == PS_BATCH_PLANS) {
+        if (!kPlansEnabled) return bfail(PS_EUNSUPPORTED, kPlansOff);
+        // each problem's plan times its own kernel variants (equal shapes
+        // share the choice through the tune cache); the graph is captured
+        // again on the next solve
+        PS_BHIP(hipStreamSynchronize(b->stream));
+        PS_BHIP(hipStreamSynchronize(b->cap));
+        destroy_graph(b);
+        for (int n = 0; n < b->count; ++n) {
+            const int i = b->order[n];
+            int rc = ps_plan_set_stream(b->plans[i], b->stream);
+            if (rc == PS_OK) rc = ps_plan_autotune(b->plans[i], reps);
+            if (rc != PS_OK)
+                return ps::set_error(rc, std::string("problem ") + std::to_string(i) + ": " +
+                                             ps_last_error());
+        }
+        return PS_OK;
+    }
+    if (!kSolveEnabled) return bfail(PS_EUNSUPPORTED, kSolveOff);
     hipEvent_t e0, e1;
     PS_BHIP(hipEventCreate(&e0));
     PS_BHIP(hipEventCreate(&e1));
@@ -603,7 +705,7 @@ extern "C" int ps_batch_status(ps_batch *b)
 {
     if (!b) return bfail(PS_EINVAL, "batch is NULL");
     if (!b->captured) return PS_OK;
-    if (b->mode == PS_BATCH_PHASES) {
+    if (b->mode != PS_BATCH_PERSISTENT) {
         PS_BHIP(hipStreamSynchronize(b->stream));
         return PS_OK;
     }
