@@ -564,7 +564,7 @@ static hipError_t y_pass(ps_plan *p, cx_t<T> *spec, int dir, int kxlo = 0, int k
     });
 }
 
-// Forward x transform and level sums (no y pass).
+// Forward x transform, recording the row sums (no y pass).
 template <typename T> static int fwd_x(ps_plan *p, const T *rhs, cx_t<T> *spec)
 {
     const Tables<T> &tb = tables<T>(p);
@@ -576,8 +576,6 @@ template <typename T> static int fwd_x(ps_plan *p, const T *rhs, cx_t<T> *spec)
         return launch_fwd_x<T>(rhs, spec, p->d_rowsum, p->nx, p->ny, p->nz, p->geom, p->spx, tb,
                                p->stream);
     }));
-    PS_HIP(timed(p, K_LEVEL_SUMS,
-                 [&] { return launch_level_sums(p->d_rowsum, p->d_S, p->ny, p->nz, p->stream); }));
     return PS_OK;
 }
 
@@ -603,8 +601,6 @@ static int fwd_residual_x(ps_plan *p, const T *b, const T *x, cx_t<T> *spec, int
                                         p->t64.D, adjoint, p->geom, p->spx, tables<T>(p),
                                         p->stream);
     }));
-    PS_HIP(timed(p, K_LEVEL_SUMS,
-                 [&] { return launch_level_sums(p->d_rowsum, p->d_S, p->ny, p->nz, p->stream); }));
     return PS_OK;
 }
 
@@ -622,10 +618,16 @@ static hipError_t main_columns(ps_plan *p, cx_t<T> *spec, int adjoint, int refin
 }
 
 // The FP64 columns (packed kx = 0 row, mean column, near-singular columns)
-// on stream st.
+// on stream st.  The level sums of the row sums that the forward x pass
+// recorded feed only the mean column, so they are formed here, on the same
+// stream, off the main stream's path.
 template <typename T>
 static hipError_t special_columns(ps_plan *p, cx_t<T> *spec, int adjoint, hipStream_t st)
 {
+    const hipError_t e = timed(
+        p, K_LEVEL_SUMS,
+        [&] { return launch_level_sums(p->d_rowsum, p->d_S, p->ny, p->nz, st); }, st);
+    if (e != hipSuccess) return e;
     return timed(
         p, K_SPECIAL,
         [&] {
