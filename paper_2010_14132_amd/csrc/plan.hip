@@ -351,6 +351,7 @@ static void free_plan(ps_plan *p)
     p->allocs.clear();
     if (p->fork) (void)hipEventDestroy(p->fork);
     if (p->join) (void)hipEventDestroy(p->join);
+    if (p->ydone) (void)hipEventDestroy(p->ydone);
     if (p->side) (void)hipStreamDestroy(p->side);
     delete p;
 }
@@ -397,7 +398,8 @@ extern "C" int ps_plan_create(ps_plan **out, int nx, int ny, int nz, double dx, 
     }
     if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&p->join, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&p->join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ydone, hipEventDisableTiming) != hipSuccess) {
         free_plan(p);
         return fail(PS_EHIP, "stream or event creation failed");
     }
@@ -550,18 +552,23 @@ template <> Tables<float> &tables<float>(ps_plan *p) { return p->t32; }
 template <> Tables<double> &tables<double>(ps_plan *p) { return p->t64; }
 
 template <typename T>
-static hipError_t y_pass(ps_plan *p, cx_t<T> *spec, int dir, int kxlo = 0, int kxcnt = -1)
+static hipError_t y_pass(ps_plan *p, cx_t<T> *spec, int dir, int kxlo = 0, int kxcnt = -1,
+                         hipStream_t st = nullptr)
 {
     const Tables<T> &tb = tables<T>(p);
     if (kxcnt < 0) kxcnt = p->L - kxlo;
     if (kxcnt <= 0) return hipSuccess;
-    return timed(p, dir < 0 ? K_FFT_Y_FWD : K_FFT_Y_INV, [&] {
-        if (p->geom.variant_y >= 1)
-            return launch_fft_y_fast<T>(spec, p->nz, p->L, kxlo, kxcnt, p->ny, dir, tb.tw4_y,
-                                        p->stream, p->geom.variant_y);
-        return launch_fft_y<T>(spec, p->nz, p->L, kxlo, kxcnt, p->ny, dir, p->geom, p->spy, tb,
-                               p->stream);
-    });
+    if (!st) st = p->stream;
+    return timed(
+        p, dir < 0 ? K_FFT_Y_FWD : K_FFT_Y_INV,
+        [&] {
+            if (p->geom.variant_y >= 1)
+                return launch_fft_y_fast<T>(spec, p->nz, p->L, kxlo, kxcnt, p->ny, dir, tb.tw4_y,
+                                            st, p->geom.variant_y);
+            return launch_fft_y<T>(spec, p->nz, p->L, kxlo, kxcnt, p->ny, dir, p->geom, p->spy,
+                                   tb, st);
+        },
+        st);
 }
 
 // Forward x transform, recording the row sums (no y pass).
@@ -664,10 +671,12 @@ template <typename T> static int columns(ps_plan *p, cx_t<T> *spec, int adjoint,
 }
 
 // y forward, column solves and y backward.  With the FP64 kernel beside the
-// main one, the y pass first transforms only the rows kx < kmask (which hold
-// every FP64 column), the FP64 kernel is forked onto the side stream, and the
-// rest runs meanwhile; the streams join before those rows are transformed
-// back.  With chunks > 1 the rows kx >= kmask are processed in that many
+// main one, the rows kx < kmask (which hold every FP64 column) are
+// transformed apart from the rest -- by the side stream itself when the rest
+// is not chunked, else first, on the plan's stream, before the fork -- the
+// FP64 kernel runs on the side stream, and the rest runs meanwhile; the
+// streams join before those rows are transformed back.  With chunks > 1 the
+// rows kx >= kmask are processed in that many
 // ranges, each y forward -> columns -> y backward in turn, so that a range's
 // spectrum (nz ny (range) values) can still be in the last-level cache (the
 // 256 MB Infinity Cache) when the column kernel and the backward y pass read
@@ -683,16 +692,28 @@ template <typename T> static int middle(ps_plan *p, cx_t<T> *spec, int adjoint, 
         return PS_OK;
     }
     const int km = std::min(p->kmask, L);
-    PS_HIP(y_pass<T>(p, spec, -1, 0, km));
-    PS_TRY(fork_special<T>(p, spec, adjoint));
     const int nch = std::max(1, std::min(p->geom.chunks, L - km));
     if (nch <= 1) {
+        // The side stream transforms the rows kx < km itself, then forms the
+        // level sums and solves the FP64 columns; the main stream transforms
+        // the other rows meanwhile (disjoint rows) and waits for the side
+        // stream's y pass before its column kernel, which also covers the
+        // ordinary columns of the rows kx < km.
+        PS_HIP(hipEventRecord(p->fork, p->stream));
+        PS_HIP(hipStreamWaitEvent(p->side, p->fork, 0));
+        PS_HIP(y_pass<T>(p, spec, -1, 0, km, p->side));
+        PS_HIP(hipEventRecord(p->ydone, p->side));
+        PS_HIP(special_columns<T>(p, spec, adjoint, p->side));
+        PS_HIP(hipEventRecord(p->join, p->side));
         PS_HIP(y_pass<T>(p, spec, -1, km));
+        PS_HIP(hipStreamWaitEvent(p->stream, p->ydone, 0));
         PS_HIP(main_columns<T>(p, spec, adjoint, refine, 1, L));
         PS_HIP(hipStreamWaitEvent(p->stream, p->join, 0));
         PS_HIP(y_pass<T>(p, spec, 1));
         return PS_OK;
     }
+    PS_HIP(y_pass<T>(p, spec, -1, 0, km));
+    PS_TRY(fork_special<T>(p, spec, adjoint));
     PS_HIP(main_columns<T>(p, spec, adjoint, refine, 1, km));
     const long rest = L - km;
     for (int c = 0; c < nch; ++c) {

@@ -55,7 +55,7 @@ struct ps_plan {
     std::vector<double> dz, rho;
     hipStream_t stream = nullptr;
     hipStream_t side = nullptr;        // the FP64 column kernel runs here, beside the main one
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr, ydone = nullptr;
     int device = 0;
     std::vector<double> ax, ay, f, D;
     StagePlan spx{}, spy{};
