@@ -106,8 +106,9 @@ int ps_plan_destroy(ps_plan *plan);
 int ps_plan_set_stream(ps_plan *plan, void *stream);
 
 /* Replace the per-level densities (host array of nz values > 0) without
- * reallocating; synchronises the plan's stream.  The set of columns solved
- * in FP64 by the FP32 forms stays the one chosen at planning. */
+ * reallocating; synchronises the device first (work enqueued earlier on any
+ * stream may still read the tables).  The set of columns solved in FP64 by
+ * the FP32 forms stays the one chosen at planning. */
 int ps_plan_set_coeffs(ps_plan *plan, const double *rho);
 
 /* Solve A p = b - mu, sum(p) = 0 (Section 2.1: forward transform, one
@@ -201,61 +202,59 @@ int ps_spectral_solve(ps_plan *plan, void *spectrum, int adjoint);
 int ps_inverse_transform(ps_plan *plan, const void *spectrum, void *p);
 
 /* ---- batched: many independent solves of uneven sizes ------------------
- * Describe count problems once (each with its own grid and densities, all
- * of one precision; each planned as by ps_plan_create, so the plan's size
- * limits apply, and nz <= 128); ps_batch_solve then solves all of them by
- * replaying a captured hipGraph.
- * Mode PS_BATCH_PLANS (the default): the graph holds every problem's own
- * plan solve (the single-solve kernels, as ps_solve), most points first,
- * spread round-robin over four streams forked from the capture stream and
- * joined back, so problems on different streams may run side by side --
- * SWITCHED OFF: its first run ended in a host segmentation fault during the
- * first capture, cause not yet found; solve and autotune return
- * PS_EUNSUPPORTED.
- * Mode PS_BATCH_PHASES: every problem's five phases (x forward, y forward,
- * column solves, y backward, x backward) cut into block-sized tiles, one
- * kernel per phase over the tiles of that phase of every problem --
- * SWITCHED OFF with the persistent form (solve and autotune return
- * PS_EUNSUPPORTED in these modes: the persistent launch did not complete on
- * the GPU, its cause is not found, and the per-phase graph, which shares its
- * tile code, has not been verified).
+ * Describe count problems once and solve all of them with one call, replayed
+ * from captured hipGraphs (the uneven-decomposition plan of Section 2.1: one
+ * plan with reusable buffers per problem, made once and executed every
+ * timestep).  Each problem is planned as by ps_plan_create (its size limits
+ * apply) with the planning defaults, so a batched solve gives exactly the
+ * result of that problem's standalone ps_solve.
+ * Mode PS_BATCH_LANES (the only mode): the problems are dealt to `lanes`
+ * streams, most points first, each to the lane with the fewest points so
+ * far; each lane's solves are captured one after another into one graph on
+ * its stream, and a solve forks the lanes from the caller's stream,
+ * launches the graphs side by side and joins them back.
  *   nx, ny, nz, dx, dy : host arrays of count values.
  *   dz, rho            : host arrays of count host pointers to nz[i] values.
- *   precision          : PS_FP64 or PS_FP32 (else PS_EUNSUPPORTED).
- *   stream             : hipStream_t the graph is launched on.
- * Errors as ps_plan_create (the message names the failing problem). */
+ *   precision          : a ps_precision value, shared by every problem.
+ *   stream             : hipStream_t the solves are ordered on (NULL = null
+ *                        stream); see ps_batch_set_stream.
+ * Allocates every problem's workspace (synchronises).  Errors as
+ * ps_plan_create (the message names the failing problem). */
 int ps_batch_create(ps_batch **out, int count, const int *nx, const int *ny,
                     const int *nz, const double *dx, const double *dy,
                     const double *const *dz, const double *const *rho,
                     int precision, void *stream);
 /* rhs, p: host arrays of count device pointers ([nz][ny][nx] fields of the
- * batch's element type; rhs[i] must not alias p[i]).  The first call, and
- * any call with different pointers, captures the graph (synchronising the
- * stream first); later calls only replay it (asynchronous).  One replay in
- * flight per batch. */
+ * batch's element type; rhs[i] must not alias p[i] in the PS_FP32_R1 form).
+ * The first call, and any call with other pointers, synchronises the
+ * stream, solves every problem once eagerly on its lane and captures the
+ * lane graphs (allocating graph resources); later calls with the same
+ * pointers only replay them, asynchronously after the work already on the
+ * stream, and later work on the stream waits for them.  One solve in flight
+ * per batch. */
 int ps_batch_solve(ps_batch *batch, const void *const *rhs, void *const *p);
 int ps_batch_set_stream(ps_batch *batch, void *stream);
-/* PS_BATCH_PLANS: every problem's plan solve in one graph (the default).
- * PS_BATCH_PHASES: one launch per phase over tiles (solving switched off).
- * PS_BATCH_PERSISTENT: all phases in a single persistent launch whose blocks
- * take (problem, phase, tile) tickets and wait per problem for the previous
- * phase -- switched off: it did not complete on the GPU, so requesting it
- * returns PS_EUNSUPPORTED.  Changing the mode synchronises the batch's
- * streams and drops the captured graph. */
-enum { PS_BATCH_PHASES = 0, PS_BATCH_PERSISTENT = 1, PS_BATCH_PLANS = 2 };
+/* Number of lanes, 1..8 (default 4; PS_EINVAL otherwise).  Synchronises
+ * and drops the captured graphs when it changes. */
+int ps_batch_set_lanes(ps_batch *batch, int lanes);
+/* PS_BATCH_LANES is accepted.  The earlier forms are refused with
+ * PS_EUNSUPPORTED: PS_BATCH_PERSISTENT (one persistent launch over
+ * (problem, phase, tile) tickets: did not complete on the GPU),
+ * PS_BATCH_PHASES (one launch per phase over the same tiles: withdrawn with
+ * it) and PS_BATCH_PLANS (one graph over forked plan streams: a host fault
+ * during its capture). */
+enum { PS_BATCH_PHASES = 0, PS_BATCH_PERSISTENT = 1, PS_BATCH_PLANS = 2, PS_BATCH_LANES = 3 };
 int ps_batch_set_mode(ps_batch *batch, int mode);
-/* PS_BATCH_PLANS: autotune every problem's plan (ps_plan_autotune, reps
- * repetitions; rhs and p are not used).  Tile modes: time the tile layouts
- * for 32, 48 and 60 KiB of LDS per block on the given fields (reps replays
- * each) and keep the fastest.  Synchronises. */
+/* Autotune every problem's plan (ps_plan_autotune, reps repetitions; equal
+ * shapes share the tune-cache entry), then time 1, 2, 4 and 8 lanes over
+ * reps replays each on the given fields (which are written) and keep the
+ * fastest.  Synchronises. */
 int ps_batch_autotune(ps_batch *batch, const void *const *rhs, void *const *p, int reps);
-/* count of problems, total tiles of the work list, blocks of the persistent
- * launch, LDS budget per block in bytes (any pointer may be NULL). */
+/* count of problems and the number of lanes (grid); tiles and lds_budget
+ * are 0 (kept for the withdrawn tile forms).  Any pointer may be NULL. */
 int ps_batch_query(const ps_batch *batch, int *count, int *tiles, int *grid, int *lds_budget);
-/* Synchronise the batch's stream; PS_OK if the last replay completed, or
- * PS_ESTATE if its persistent kernel gave up waiting for a phase (a bounded
- * wait: the kernel then ends instead of hanging, leaving the outputs
- * incomplete). */
+/* Synchronise the batch's streams; PS_OK, or PS_EHIP if an earlier solve
+ * failed on the device. */
 int ps_batch_status(ps_batch *batch);
 int ps_batch_destroy(ps_batch *batch);
 

@@ -66,6 +66,7 @@ SIGNATURES = {
     "ps_batch_query": (ctypes.c_int, [_vp, _I, _I, _I, _I]),
     "ps_batch_status": (ctypes.c_int, [_vp]),
     "ps_batch_set_mode": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "ps_batch_set_lanes": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ps_plan_profile": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ps_plan_profile_report": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                               ctypes.POINTER(ctypes.c_double),
@@ -285,11 +286,12 @@ def _solve_fn():
 
         @staticmethod
         def forward(ctx, b, rho, plan):
-            rho_h = rho.detach().to("cpu", torch.float64).numpy()
+            rho_h = rho.detach().to("cpu", torch.float64).numpy().copy()
             if not np.array_equal(rho_h, plan.rho):
                 plan.set_coeffs(rho_h)
             p = plan.solve(b.detach().contiguous())
             ctx.plan = plan
+            ctx.rho_h = rho_h
             ctx.save_for_backward(p)
             ctx.rho_dtype = rho.dtype
             ctx.rho_device = rho.device
@@ -299,10 +301,23 @@ def _solve_fn():
         def backward(ctx, gp):
             (p,) = ctx.saved_tensors
             plan = ctx.plan
-            lam = plan.solve_adjoint(gp.contiguous().to(plan.dtype))
-            grho = None
-            if ctx.needs_input_grad[1]:
-                grho = plan.grad_coeffs(lam, p).to(device=ctx.rho_device, dtype=ctx.rho_dtype)
+            # the plan may have been used with other densities since this
+            # forward: the adjoint and the density gradient need this
+            # forward's operator, so its densities are set for them and the
+            # plan's current ones restored afterwards
+            current = plan.rho.copy()
+            swap = not np.array_equal(current, ctx.rho_h)
+            if swap:
+                plan.set_coeffs(ctx.rho_h)
+            try:
+                lam = plan.solve_adjoint(gp.contiguous().to(plan.dtype))
+                grho = None
+                if ctx.needs_input_grad[1]:
+                    grho = plan.grad_coeffs(lam, p).to(device=ctx.rho_device,
+                                                       dtype=ctx.rho_dtype)
+            finally:
+                if swap:
+                    plan.set_coeffs(current)
             return lam, grho, None
 
     return PoissonSolve
@@ -329,19 +344,19 @@ def tune_cache_load(path: str):
 
 
 class BatchPlan:
-    """Many independent solves of uneven sizes replayed from a captured
-    hipGraph (the C ABI's ps_batch).  mode "plans" (the default) captures
-    every problem's own plan solve; "phases" and "persistent" cut the
-    problems into tiles.  All three are switched off in the library for now
-    (solve() and autotune() raise PressureSolveError, PS_EUNSUPPORTED);
-    planning, info() and close() work.
+    """Many independent solves of uneven sizes replayed from captured
+    hipGraphs (the C ABI's ps_batch, mode PS_BATCH_LANES): the problems are
+    dealt to ``lanes`` streams, largest first, each lane's solves captured
+    into one graph, and the lane graphs launched side by side.  Every
+    problem gives exactly its standalone Plan's result (same kernels).
 
     grids: sequence of workloads.Grid-like objects (nx, ny, nz, dx, dy, dz,
-    rho); precision "fp32" or "fp64"."""
+    rho); precision one of PRECISIONS.  The earlier modes "phases",
+    "persistent" and "plans" are refused by the library."""
 
-    MODES = {"phases": 0, "persistent": 1, "plans": 2}
+    MODES = {"phases": 0, "persistent": 1, "plans": 2, "lanes": 3}
 
-    def __init__(self, grids, precision="fp32", mode="plans"):
+    def __init__(self, grids, precision="fp32", mode="lanes", lanes=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the pressure-solve library needs a GPU (no CPU fallback)")
@@ -366,9 +381,14 @@ class BatchPlan:
         self._h = h
         try:
             check(lib.ps_batch_set_mode(h, self.MODES[mode]), "ps_batch_set_mode")
+            if lanes is not None:
+                self.set_lanes(lanes)
         except Exception:
             self.close()
             raise
+
+    def set_lanes(self, lanes: int):
+        check(load().ps_batch_set_lanes(self._h, int(lanes)), "ps_batch_set_lanes")
 
     def _ptrs(self, rhs, out):
         n = len(self.grids)
@@ -394,14 +414,14 @@ class BatchPlan:
         check(load().ps_batch_autotune(self._h, rp, op, int(reps)), "ps_batch_autotune")
 
     def status(self):
-        """Synchronise; raise if the last replay gave up waiting for a phase."""
+        """Synchronise the batch's streams; raise if a solve failed."""
         check(load().ps_batch_status(self._h), "ps_batch_status")
 
     def info(self) -> dict:
         c, t, g, l = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         check(load().ps_batch_query(self._h, ctypes.byref(c), ctypes.byref(t), ctypes.byref(g),
                                     ctypes.byref(l)), "ps_batch_query")
-        return {"count": c.value, "tiles": t.value, "grid": g.value, "lds_budget": l.value}
+        return {"count": c.value, "lanes": g.value}
 
     def close(self):
         h, self._h = getattr(self, "_h", None), None

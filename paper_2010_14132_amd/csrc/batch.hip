@@ -1,24 +1,37 @@
-// Batched solves: many independent problems of uneven sizes, replayed from a
-// captured hipGraph.
+// Batched solves: many independent problems of uneven sizes, replayed from
+// captured hipGraphs.
 //
-// Every problem is planned on its own (tables, FP64 column set, workspace;
-// the planning described once and reused, paper Section 2.1).  Its solve is
-// cut into five phases -- x forward, y forward, column solves (FP64 tasks,
-// then the main columns), y backward, x backward -- and each phase into tiles
-// of one 256-thread block.  The graph holds one kernel per phase, each over
-// the tiles of that phase of every problem (largest problems first), so a
-// replay is five launches with no inter-block waiting.
+// Every problem is planned on its own (tables, FP64 column set, workspace:
+// the planning done once and reused every timestep, paper Section 2.1, with
+// the per-problem reusable buffers of its uneven-decomposition plan), so a
+// batched solve runs exactly the kernels a standalone solve of that problem
+// runs and gives the same result bit for bit.
 //
-// A third form (PS_BATCH_PLANS) captures every problem's own plan solve
-// instead, spread over a few streams.
+// Mode PS_BATCH_LANES: the problems are dealt to a few lanes, largest first,
+// each to the lane with the fewest points so far (LPT).  Each lane has its
+// own stream; the solves of a lane's problems are captured one after another
+// into one graph on that stream, with the stream as the capture's origin
+// (each plan's FP64 columns fork onto the plan's second stream and join back
+// inside the capture).  A batched solve forks the lanes from the caller's
+// stream, launches every lane's graph on its stream and joins them back, so
+// problems of different lanes run side by side and the small problems fill
+// the gaps the large ones leave.  Before the first capture every plan solves
+// once eagerly on the stream it will be captured on, so no kernel is first
+// launched inside a capture.
 //
-// Solving is switched off in every form (ps_batch_solve and
-// ps_batch_autotune return PS_EUNSUPPORTED): the single persistent launch
-// (k_batch below: blocks taking (problem, phase, tile) tickets and waiting per
-// problem for the previous phase) did not complete on the GPU and its cause is
-// not found; the per-phase graph, which shares its work list, has not been run
-// yet; and the plan graph's first run ended in a host segmentation fault.
-// Create, set_mode, query, status and destroy work.
+// Earlier forms, refused by ps_batch_set_mode (their code is removed):
+//   PS_BATCH_PERSISTENT: one persistent launch whose blocks took (problem,
+//     phase, tile) tickets and waited per problem for the previous phase.
+//     After a fix of an out-of-bounds coefficient read it still did not
+//     complete on the GPU; the cause was not found.
+//   PS_BATCH_PHASES: one kernel per phase over the tiles of every problem,
+//     sharing the persistent kernel's tile work list; never run.
+//   PS_BATCH_PLANS: every plan's solve captured into ONE graph, the plans'
+//     streams being lanes forked from the capture's origin; its first run
+//     ended in a host segmentation fault during that capture.  It was the
+//     only capture in which a plan's own stream was itself a forked capture
+//     stream (the plan's stream then waits on events its second stream
+//     recorded); the lanes mode never does that.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -27,273 +40,29 @@
 
 #include "ps_internal.h"
 #include "ps_plan_impl.h"
-#include "ps_tiles.h"
 #include "../../include/pressure_solve.h"
-
-using namespace ps;
 
 namespace {
 
-constexpr int kPhases = 5;
-// The tile-based designs (one launch per phase, or one persistent launch).
-constexpr bool kSolveEnabled = false;
-// Streams the problems of a plan graph are spread over (graph branches that
-// may run side by side).
-constexpr int kLanes = 4;
-// The plan graph is switched off as well: its first run, which captured
-// every plan's first solve (so the first launch of each kernel in the
-// process happened inside the capture), ended in a segmentation fault in
-// the host process; the cause is not yet shown.
-constexpr bool kPlansEnabled = false;
-constexpr const char *kPlansOff =
-    "the plan-graph batched solve is switched off: its first run ended in a host segmentation "
-    "fault whose cause is not yet found; solve each problem with its own plan";
-constexpr const char *kSolveOff =
-    "the tile-based batched solves are switched off: the persistent launch did not complete on "
-    "the GPU (cause not found) and the per-phase graph has not been verified; solve each "
-    "problem with its own plan";
-
-// Device view of one problem.
-struct BatchProblem {
-    int nx, ny, nz, L;
-    int rows_x, rows_y;
-    int nh;
-    int nmask;
-    int ntile[kPhases];
-    int nspecial_tiles; // the first tiles of the column phase are FP64 tasks
-    StagePlan spx, spy;
-    const void *rhs;
-    void *out;
-    void *spec;
-    double *rowsum;
-    double *ws;
-    const void *ax, *ay, *coef;
-    const int *maskcnt, *mlist;
-    const void *twx, *tws, *twy;
-    const double *ax64, *ay64, *f64, *D64, *rs64;
-};
-
-__global__ void k_batch_reset(int *counters, int n)
-{
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        counters[i] = 0;
-}
-
-template <typename T, int NH>
-__device__ void batch_columns(const BatchProblem &P, long group, T (*xa)[2][64],
-                              cx_t<T> (*xb)[2][64])
-{
-    columns3_tile<T, NH, false>(reinterpret_cast<cx_t<T> *>(P.spec), P.L, P.ny,
-                                reinterpret_cast<const T *>(P.ax), reinterpret_cast<const T *>(P.ay),
-                                reinterpret_cast<const LevelCoef<T> *>(P.coef), P.maskcnt,
-                                (long)P.ny, (long)P.L * P.ny, group, xa, xb);
-}
-
-// Bound on the polls of one wait (each poll sleeps ~50 ns, plus the load):
-// a wait that has not ended after a few seconds means the work list is
-// inconsistent; the kernel then raises the error flag and every block leaves.
-constexpr int kMaxPolls = 1 << 22;
-
-// counters: [0] ticket, [1] error flag, [2 + kPhases * problem + phase] tiles
-// of that phase completed.
-template <typename T>
-__global__ __launch_bounds__(256) void k_batch(const BatchProblem *__restrict__ probs,
-                                               const int4 *__restrict__ items, int nitems,
-                                               int *__restrict__ counters)
-{
-    using C = cx_t<T>;
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_item, s_abort;
-    __shared__ T xa[2][2][64];
-    __shared__ C xb[2][2][64];
-    int *ticket = counters;
-    int *error = counters + 1;
-    int *done = counters + 2;
-    for (;;) {
-        if (threadIdx.x == 0) {
-            s_item = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_abort = __hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __syncthreads();
-        const int it = s_item;
-        const int abort_now = s_abort;
-        __syncthreads();
-        if (it >= nitems || abort_now) break;
-        const int4 w = items[it];
-        const BatchProblem &P = probs[w.x];
-        const int phase = w.y, tile = w.z;
-        if (phase > 0) {
-            if (threadIdx.x == 0) {
-                const int need = P.ntile[phase - 1];
-                int *c = &done[w.x * kPhases + phase - 1];
-                int polls = 0;
-                while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                    if (++polls > kMaxPolls ||
-                        __hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                        __hip_atomic_store(error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        s_abort = 1;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(2);
-                }
-            }
-            __syncthreads();
-            if (s_abort) break;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        }
-        C *spec = reinterpret_cast<C *>(P.spec);
-        if (phase == 0) {
-            fwd_x_tile<T>(reinterpret_cast<const T *>(P.rhs), spec, P.rowsum, P.nx, P.ny,
-                          P.ny * P.nz, P.rows_x, tile * P.rows_x, P.spx,
-                          reinterpret_cast<const C *>(P.twx), reinterpret_cast<const C *>(P.tws),
-                          smem);
-        } else if (phase == 1 || phase == 3) {
-            const int rows = P.nz * P.L;
-            if (phase == 1)
-                fft_y_tile<T, -1>(spec, rows, P.ny, P.rows_y, tile * P.rows_y, P.spy,
-                                  reinterpret_cast<const C *>(P.twy), P.L, 0, P.L, smem);
-            else
-                fft_y_tile<T, 1>(spec, rows, P.ny, P.rows_y, tile * P.rows_y, P.spy,
-                                 reinterpret_cast<const C *>(P.twy), P.L, 0, P.L, smem);
-        } else if (phase == 2) {
-            if (tile < P.nspecial_tiles) {
-                // FP64 tasks: stage the tables and the level sums (a fixed-order
-                // sum of the recorded row sums), then one task per thread.
-                double *f = reinterpret_cast<double *>(smem);
-                double *D = f + PS_MAX_NZ + 1, *rs = D + PS_MAX_NZ, *os = rs + PS_MAX_NZ;
-                double *sS = os + PS_MAX_NZ;
-                for (int i = threadIdx.x; i <= P.nz; i += blockDim.x) {
-                    f[i] = P.f64[i];
-                    if (i < P.nz) {
-                        D[i] = P.D64[i];
-                        rs[i] = P.rs64[i];
-                        os[i] = 1.0;
-                        double acc = 0.0;
-                        const double *rw = P.rowsum + (size_t)i * P.ny;
-                        for (int j = 0; j < P.ny; ++j) acc += rw[j];
-                        sS[i] = acc;
-                    }
-                }
-                __syncthreads();
-                special_seq_tile<T, 8>(spec, P.nx, P.ny, P.nz, 0, P.mlist, P.nmask, P.ws, P.ax64,
-                                       P.ay64, f, D, rs, os, sS, tile * 256 + threadIdx.x);
-            } else {
-                // the column capacity must equal the one the coefficient
-                // table was built for (column_capacity(nz), checked on the host)
-                const long group = tile - P.nspecial_tiles;
-                switch (P.nh) {
-                case 1: batch_columns<T, 1>(P, group, xa, xb); break;
-                case 2: batch_columns<T, 2>(P, group, xa, xb); break;
-                case 4: batch_columns<T, 4>(P, group, xa, xb); break;
-                case 8: batch_columns<T, 8>(P, group, xa, xb); break;
-                case 16: batch_columns<T, 16>(P, group, xa, xb); break;
-                case 32: batch_columns<T, 32>(P, group, xa, xb); break;
-                default: batch_columns<T, 64>(P, group, xa, xb); break;
-                }
-            }
-        } else {
-            inv_x_tile<T>(spec, reinterpret_cast<T *>(P.out), P.nx, P.ny, P.ny * P.nz, P.rows_x,
-                          tile * P.rows_x, 0, P.spx, reinterpret_cast<const C *>(P.twx),
-                          reinterpret_cast<const C *>(P.tws), smem);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_fetch_add(&done[w.x * kPhases + phase], 1, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
-// Reads the error flag of the last replay (host-side check after a sync).
-__global__ void k_batch_flag(const int *counters, int *flag) { *flag = counters[1]; }
-
-// One phase of every problem: block b runs tile items[b] = (problem, phase,
-// tile).  No block depends on another within the launch.
-template <typename T, int PH>
-__global__ __launch_bounds__(256) void k_bphase(const BatchProblem *__restrict__ probs,
-                                                const int4 *__restrict__ items)
-{
-    using C = cx_t<T>;
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ T xa[2][2][64];
-    __shared__ C xb[2][2][64];
-    const int4 w = items[blockIdx.x];
-    const BatchProblem &P = probs[w.x];
-    const int tile = w.z;
-    C *spec = reinterpret_cast<C *>(P.spec);
-    if constexpr (PH == 0) {
-        fwd_x_tile<T>(reinterpret_cast<const T *>(P.rhs), spec, P.rowsum, P.nx, P.ny, P.ny * P.nz,
-                      P.rows_x, tile * P.rows_x, P.spx, reinterpret_cast<const C *>(P.twx),
-                      reinterpret_cast<const C *>(P.tws), smem);
-    } else if constexpr (PH == 1 || PH == 3) {
-        fft_y_tile<T, PH == 1 ? -1 : 1>(spec, P.nz * P.L, P.ny, P.rows_y, tile * P.rows_y, P.spy,
-                                        reinterpret_cast<const C *>(P.twy), P.L, 0, P.L, smem);
-    } else if constexpr (PH == 2) {
-        if (tile < P.nspecial_tiles) {
-            double *f = reinterpret_cast<double *>(smem);
-            double *D = f + PS_MAX_NZ + 1, *rs = D + PS_MAX_NZ, *os = rs + PS_MAX_NZ;
-            double *sS = os + PS_MAX_NZ;
-            for (int i = threadIdx.x; i <= P.nz; i += blockDim.x) {
-                f[i] = P.f64[i];
-                if (i < P.nz) {
-                    D[i] = P.D64[i];
-                    rs[i] = P.rs64[i];
-                    os[i] = 1.0;
-                    double acc = 0.0; // level sum: fixed-order sum of the row sums
-                    const double *rw = P.rowsum + (size_t)i * P.ny;
-                    for (int j = 0; j < P.ny; ++j) acc += rw[j];
-                    sS[i] = acc;
-                }
-            }
-            __syncthreads();
-            special_seq_tile<T, 16>(spec, P.nx, P.ny, P.nz, 0, P.mlist, P.nmask, P.ws, P.ax64,
-                                    P.ay64, f, D, rs, os, sS, tile * 256 + threadIdx.x);
-        } else {
-            const long group = tile - P.nspecial_tiles;
-            switch (P.nh) {
-            case 1: batch_columns<T, 1>(P, group, xa, xb); break;
-            case 2: batch_columns<T, 2>(P, group, xa, xb); break;
-            case 4: batch_columns<T, 4>(P, group, xa, xb); break;
-            case 8: batch_columns<T, 8>(P, group, xa, xb); break;
-            case 16: batch_columns<T, 16>(P, group, xa, xb); break;
-            case 32: batch_columns<T, 32>(P, group, xa, xb); break;
-            default: batch_columns<T, 64>(P, group, xa, xb); break;
-            }
-        }
-    } else {
-        inv_x_tile<T>(spec, reinterpret_cast<T *>(P.out), P.nx, P.ny, P.ny * P.nz, P.rows_x,
-                      tile * P.rows_x, 0, P.spx, reinterpret_cast<const C *>(P.twx),
-                      reinterpret_cast<const C *>(P.tws), smem);
-    }
-}
+constexpr int kMaxLanes = 8;
+constexpr int kDefaultLanes = 4;
 
 } // namespace
 
 struct ps_batch {
     int count = 0, precision = 0;
-    hipStream_t stream = nullptr;     // caller's stream (graph launches)
-    hipStream_t cap = nullptr;        // private stream the graph is captured on
+    hipStream_t stream = nullptr;           // caller's stream
     std::vector<ps_plan *> plans;
-    std::vector<BatchProblem> hp;
-    BatchProblem *dp = nullptr;
-    int4 *items = nullptr;
-    int nitems = 0;
-    int *counters = nullptr;
-    int ncounters = 0;
-    size_t lds = 0;
-    int lds_budget = 48 * 1024;
-    int grid = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    std::vector<long long> points;          // nx ny nz per problem
+    std::vector<int> order;                 // problems, most points first
+    std::vector<int> lane_of;               // problem -> lane
+    int nlanes = kDefaultLanes;
+    hipStream_t lanes[kMaxLanes] = {};
+    hipEvent_t ev_in = nullptr, ev_join[kMaxLanes] = {};
+    hipGraphExec_t exec[kMaxLanes] = {};    // one graph per lane (null: empty lane)
+    bool captured = false;
     std::vector<const void *> cap_rhs;
     std::vector<void *> cap_out;
-    bool captured = false;
-    int mode = PS_BATCH_PLANS;
-    hipStream_t lanes[kLanes] = {};   // PS_BATCH_PLANS: branches of the graph
-    hipEvent_t ev_fork = nullptr, ev_join[kLanes] = {};
-    std::vector<int> order;           // problems, most points first
-    int phase_off[kPhases + 1] = {}; // items of phase ph: [phase_off[ph], phase_off[ph+1])
-    hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
 
 static int bfail(int code, const std::string &msg) { return ps::set_error(code, msg); }
@@ -305,101 +74,48 @@ static int bfail(int code, const std::string &msg) { return ps::set_error(code, 
             return bfail(PS_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));              \
     } while (0)
 
-static void destroy_graph(ps_batch *b)
+static void destroy_graphs(ps_batch *b)
 {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
+    for (int l = 0; l < kMaxLanes; ++l) {
+        if (b->exec[l]) (void)hipGraphExecDestroy(b->exec[l]);
+        b->exec[l] = nullptr;
+    }
     b->captured = false;
 }
 
 static void free_batch(ps_batch *b)
 {
-    destroy_graph(b);
+    destroy_graphs(b);
     for (ps_plan *p : b->plans) ps_plan_destroy(p);
-    if (b->dp) (void)hipFree(b->dp);
-    if (b->items) (void)hipFree(b->items);
-    if (b->counters) (void)hipFree(b->counters);
-    if (b->cap) (void)hipStreamDestroy(b->cap);
-    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
-    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
-    for (int l = 0; l < kLanes; ++l) {
+    for (int l = 0; l < kMaxLanes; ++l) {
         if (b->lanes[l]) (void)hipStreamDestroy(b->lanes[l]);
         if (b->ev_join[l]) (void)hipEventDestroy(b->ev_join[l]);
     }
-    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     delete b;
 }
 
-// Tile shapes for an LDS budget; the work list in ticket order.
-static int layout(ps_batch *b)
+// Waits for everything the batch has enqueued on its own streams.
+static int sync_lanes(ps_batch *b)
 {
-    const size_t cs = b->precision == PS_FP64 ? 16 : 8;
-    const size_t budget = (size_t)b->lds_budget / cs; // complex values
-    size_t lds = 5 * (PS_MAX_NZ + 1) * sizeof(double); // FP64 task tables
-    for (int i = 0; i < b->count; ++i) {
-        ps_plan *p = b->plans[i];
-        BatchProblem &P = b->hp[i];
-        const int L = p->L;
-        int rx = (int)((budget - 2 * (size_t)L) / (2 * (size_t)L));
-        int ry = (int)((budget - (size_t)p->ny) / (2 * (size_t)p->ny));
-        rx = std::max(1, std::min(64, rx));
-        ry = std::max(1, std::min(64, ry));
-        P.rows_x = rx;
-        P.rows_y = ry;
-        lds = std::max(lds, (size_t)(2 * rx * L + 2 * L) * cs);
-        lds = std::max(lds, (size_t)(2 * ry * p->ny + p->ny) * cs);
-        if (P.nh != column_capacity(p->nz) || P.nh < 1 || P.nh > 64 || (P.nh & (P.nh - 1)))
-            return bfail(PS_EUNSUPPORTED, "column capacity outside the batched kernel's range");
-        const int ntask = p->ny / 2 + 1 + p->nmask;
-        P.nspecial_tiles = (ntask + 255) / 256;
-        const long ncols = (long)(L - 1) * p->ny;
-        P.ntile[0] = (p->ny * p->nz + rx - 1) / rx;
-        P.ntile[1] = (p->nz * L + ry - 1) / ry;
-        P.ntile[2] = P.nspecial_tiles + (int)((ncols + 127) / 128);
-        P.ntile[3] = P.ntile[1];
-        P.ntile[4] = P.ntile[0];
-    }
-    b->lds = lds;
-    // ticket order: phase by phase, larger problems first; in the column
-    // phase the FP64 tiles of every problem come before the main columns
-    std::vector<int> order(b->count);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
-        const ps_plan *pa = b->plans[a], *pc = b->plans[c];
-        return (long)pa->nx * pa->ny * pa->nz > (long)pc->nx * pc->ny * pc->nz;
-    });
-    std::vector<int4> items;
-    for (int ph = 0; ph < kPhases; ++ph) {
-        b->phase_off[ph] = (int)items.size();
-        if (ph == 2) {
-            for (int i : order)
-                for (int t = 0; t < b->hp[i].nspecial_tiles; ++t) items.push_back(int4{i, ph, t, 0});
-            for (int i : order)
-                for (int t = b->hp[i].nspecial_tiles; t < b->hp[i].ntile[ph]; ++t)
-                    items.push_back(int4{i, ph, t, 0});
-        } else {
-            for (int i : order)
-                for (int t = 0; t < b->hp[i].ntile[ph]; ++t) items.push_back(int4{i, ph, t, 0});
-        }
-    }
-    b->phase_off[kPhases] = (int)items.size();
-    b->nitems = (int)items.size();
-    if (b->items) (void)hipFree(b->items);
-    b->items = nullptr;
-    PS_BHIP(hipMalloc(&b->items, items.size() * sizeof(int4)));
-    PS_BHIP(hipMemcpy(b->items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice));
-    int dev = 0, cus = 0, per_cu = 0;
-    PS_BHIP(hipGetDevice(&dev));
-    PS_BHIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    if (b->precision == PS_FP64)
-        PS_BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<double>, 256, b->lds));
-    else
-        PS_BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<float>, 256, b->lds));
-    b->grid = std::max(1, cus * std::max(1, per_cu));
-    destroy_graph(b);
+    for (int l = 0; l < kMaxLanes; ++l)
+        if (b->lanes[l]) PS_BHIP(hipStreamSynchronize(b->lanes[l]));
     return PS_OK;
+}
+
+// LPT assignment: problems most points first, each to the lane with the
+// fewest points so far (ties: the lower lane).
+static void assign_lanes(ps_batch *b)
+{
+    std::vector<long long> load(b->nlanes, 0);
+    b->lane_of.assign(b->count, 0);
+    for (int i : b->order) {
+        int best = 0;
+        for (int l = 1; l < b->nlanes; ++l)
+            if (load[l] < load[best]) best = l;
+        b->lane_of[i] = best;
+        load[best] += b->points[i];
+    }
 }
 
 extern "C" int ps_batch_create(ps_batch **out, int count, const int *nx, const int *ny,
@@ -411,166 +127,94 @@ extern "C" int ps_batch_create(ps_batch **out, int count, const int *nx, const i
     *out = nullptr;
     if (count < 1 || !nx || !ny || !nz || !dx || !dy || !dz || !rho)
         return bfail(PS_EINVAL, "count >= 1 and all arrays required");
-    if (precision != PS_FP64 && precision != PS_FP32)
-        return bfail(PS_EUNSUPPORTED, "the batched solve supports PS_FP64 and PS_FP32");
-    for (int i = 0; i < count; ++i) {
+    if (precision < PS_FP64 || precision > PS_FP32_R1)
+        return bfail(PS_EUNSUPPORTED, "unknown precision");
+    for (int i = 0; i < count; ++i)
         if (!dz[i] || !rho[i]) return bfail(PS_EINVAL, "dz[i] and rho[i] required");
-        if (nz[i] > 128) return bfail(PS_EUNSUPPORTED, "the batched solve supports nz <= 128");
-    }
     ps_batch *b = new ps_batch();
     b->count = count;
     b->precision = precision;
     b->stream = reinterpret_cast<hipStream_t>(stream);
-    b->plans.assign(count, nullptr);
-    b->hp.assign(count, BatchProblem{});
     auto bail = [&](int rc) {
         free_batch(b);
         return rc;
     };
+    for (int l = 0; l < kMaxLanes; ++l)
+        if (hipStreamCreateWithFlags(&b->lanes[l], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->ev_join[l], hipEventDisableTiming) != hipSuccess)
+            return bail(bfail(PS_EHIP, "stream or event creation failed"));
+    if (hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess)
+        return bail(bfail(PS_EHIP, "event creation failed"));
+    b->plans.assign(count, nullptr);
+    b->points.assign(count, 0);
     for (int i = 0; i < count; ++i) {
-        int rc = ps_plan_create(&b->plans[i], nx[i], ny[i], nz[i], dx[i], dy[i], dz[i], rho[i],
-                                precision, 0.0, nullptr);
+        // planned on a lane stream (not the null stream); ps_batch_solve
+        // moves each plan to its lane before it is used
+        const int rc = ps_plan_create(&b->plans[i], nx[i], ny[i], nz[i], dx[i], dy[i], dz[i],
+                                      rho[i], precision, 0.0, b->lanes[0]);
         if (rc != PS_OK) {
             ps::set_error(rc, std::string("problem ") + std::to_string(i) + ": " + ps_last_error());
             return bail(rc);
         }
-        ps_plan *p = b->plans[i];
-        BatchProblem &P = b->hp[i];
-        P.nx = p->nx;
-        P.ny = p->ny;
-        P.nz = p->nz;
-        P.L = p->L;
-        P.nh = column_capacity(p->nz);
-        P.nmask = p->nmask;
-        P.spx = p->spx;
-        P.spy = p->spy;
-        P.spec = p->d_spec;
-        P.rowsum = p->d_rowsum;
-        P.ws = p->d_ws;
-        P.maskcnt = precision == PS_FP64 ? nullptr : p->d_maskcnt;
-        P.mlist = p->d_mlist;
-        P.ax64 = p->t64.ax;
-        P.ay64 = p->t64.ay;
-        P.f64 = p->t64.f;
-        P.D64 = p->t64.D;
-        P.rs64 = p->t64.rs_fwd;
-        if (precision == PS_FP64) {
-            P.ax = p->t64.ax;
-            P.ay = p->t64.ay;
-            P.coef = p->t64.coef_fwd;
-            P.twx = p->t64.tw_x;
-            P.tws = p->t64.tw_s;
-            P.twy = p->t64.tw_y;
-        } else {
-            P.ax = p->t32.ax;
-            P.ay = p->t32.ay;
-            P.coef = p->t32.coef_fwd;
-            P.twx = p->t32.tw_x;
-            P.tws = p->t32.tw_s;
-            P.twy = p->t32.tw_y;
-        }
+        b->points[i] = (long long)nx[i] * ny[i] * nz[i];
     }
-    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess)
-        return bail(bfail(PS_EHIP, "stream or event creation failed"));
-    for (int l = 0; l < kLanes; ++l)
-        if (hipStreamCreateWithFlags(&b->lanes[l], hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&b->ev_join[l], hipEventDisableTiming) != hipSuccess)
-            return bail(bfail(PS_EHIP, "stream or event creation failed"));
     b->order.resize(count);
     std::iota(b->order.begin(), b->order.end(), 0);
-    std::stable_sort(b->order.begin(), b->order.end(), [&](int a, int c) {
-        return (long long)nx[a] * ny[a] * nz[a] > (long long)nx[c] * ny[c] * nz[c];
-    });
-    int rc = layout(b);
-    if (rc != PS_OK) return bail(rc);
-    if (hipMalloc(&b->dp, count * sizeof(BatchProblem)) != hipSuccess)
-        return bail(bfail(PS_ENOMEM, "problem table"));
-    b->ncounters = 2 + kPhases * count;
-    if (hipMalloc(&b->counters, b->ncounters * sizeof(int)) != hipSuccess)
-        return bail(bfail(PS_ENOMEM, "counters"));
+    std::stable_sort(b->order.begin(), b->order.end(),
+                     [&](int a, int c) { return b->points[a] > b->points[c]; });
+    assign_lanes(b);
     *out = b;
     return PS_OK;
 }
 
-// PS_BATCH_PLANS: every problem's own plan solve (the single-solve kernels),
-// most points first, round-robin over kLanes streams forked from the
-// capture stream and joined back, captured into one graph.  Problems on
-// different lanes are independent branches of the graph.
-static int capture_plans(ps_batch *b, const void *const *rhs, void *const *p)
+// Captures one graph per lane (see the file comment).  On error no graph is
+// kept and every capture that was begun has been ended.
+static int capture_lanes(ps_batch *b, const void *const *rhs, void *const *p)
 {
-    PS_BHIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-    int rc = PS_OK;
-    hipError_t e = hipEventRecord(b->ev_fork, b->cap);
-    for (int l = 0; l < kLanes && e == hipSuccess; ++l)
-        e = hipStreamWaitEvent(b->lanes[l], b->ev_fork, 0);
-    for (int n = 0; n < b->count && e == hipSuccess && rc == PS_OK; ++n) {
-        const int i = b->order[n];
-        rc = ps_plan_set_stream(b->plans[i], b->lanes[n % kLanes]);
+    destroy_graphs(b);
+    assign_lanes(b);
+    // eager pass: each plan's kernels run once, outside any capture, on the
+    // stream the plan is captured on
+    for (int i : b->order) {
+        int rc = ps_plan_set_stream(b->plans[i], b->lanes[b->lane_of[i]]);
         if (rc == PS_OK) rc = ps_solve(b->plans[i], rhs[i], p[i]);
         if (rc != PS_OK)
-            ps::set_error(rc, std::string("problem ") + std::to_string(i) + ": " + ps_last_error());
+            return ps::set_error(rc, std::string("problem ") + std::to_string(i) + ": " +
+                                         ps_last_error());
     }
-    for (int l = 0; l < kLanes && e == hipSuccess; ++l) {
-        e = hipEventRecord(b->ev_join[l], b->lanes[l]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->ev_join[l], 0);
-    }
-    hipGraph_t g = nullptr;
-    const hipError_t ce = hipStreamEndCapture(b->cap, &g);
-    if (rc != PS_OK || e != hipSuccess || ce != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
+    {
+        const int rc = sync_lanes(b);
         if (rc != PS_OK) return rc;
-        return bfail(PS_EHIP,
-                     std::string("capture: ") + hipGetErrorString(e != hipSuccess ? e : ce));
     }
-    b->graph = g;
-    PS_BHIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-    return PS_OK;
-}
-
-static int capture(ps_batch *b, const void *const *rhs, void *const *p)
-{
-    destroy_graph(b);
-    if (b->mode == PS_BATCH_PLANS) {
-        const int rc = capture_plans(b, rhs, p);
-        if (rc != PS_OK) return rc;
-        b->cap_rhs.assign(rhs, rhs + b->count);
-        b->cap_out.assign(p, p + b->count);
-        b->captured = true;
-        return PS_OK;
+    for (int l = 0; l < b->nlanes; ++l) {
+        bool any = false;
+        for (int i : b->order) any = any || b->lane_of[i] == l;
+        if (!any) continue;
+        PS_BHIP(hipStreamBeginCapture(b->lanes[l], hipStreamCaptureModeThreadLocal));
+        int rc = PS_OK;
+        for (int i : b->order) {
+            if (b->lane_of[i] != l || rc != PS_OK) continue;
+            rc = ps_solve(b->plans[i], rhs[i], p[i]);
+            if (rc != PS_OK)
+                ps::set_error(rc, std::string("problem ") + std::to_string(i) + ": " +
+                                      ps_last_error());
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(b->lanes[l], &g);
+        if (rc != PS_OK || ce != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            destroy_graphs(b);
+            if (rc != PS_OK) return rc;
+            return bfail(PS_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+        }
+        const hipError_t ie = hipGraphInstantiate(&b->exec[l], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            b->exec[l] = nullptr;
+            destroy_graphs(b);
+            return bfail(PS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+        }
     }
-    for (int i = 0; i < b->count; ++i) {
-        b->hp[i].rhs = rhs[i];
-        b->hp[i].out = p[i];
-    }
-    PS_BHIP(hipMemcpy(b->dp, b->hp.data(), b->count * sizeof(BatchProblem), hipMemcpyHostToDevice));
-    PS_BHIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-    auto phase = [&](auto kern, int ph) {
-        const int n = b->phase_off[ph + 1] - b->phase_off[ph];
-        if (n > 0)
-            hipLaunchKernelGGL(kern, dim3(n), dim3(256), b->lds, b->cap, b->dp,
-                               b->items + b->phase_off[ph]);
-    };
-    if (b->precision == PS_FP64) {
-        phase(k_bphase<double, 0>, 0);
-        phase(k_bphase<double, 1>, 1);
-        phase(k_bphase<double, 2>, 2);
-        phase(k_bphase<double, 3>, 3);
-        phase(k_bphase<double, 4>, 4);
-    } else {
-        phase(k_bphase<float, 0>, 0);
-        phase(k_bphase<float, 1>, 1);
-        phase(k_bphase<float, 2>, 2);
-        phase(k_bphase<float, 3>, 3);
-        phase(k_bphase<float, 4>, 4);
-    }
-    hipError_t le = hipGetLastError();
-    hipError_t ce = hipStreamEndCapture(b->cap, &b->graph);
-    if (le != hipSuccess) return bfail(PS_EHIP, std::string("launch: ") + hipGetErrorString(le));
-    if (ce != hipSuccess) return bfail(PS_EHIP, std::string("capture: ") + hipGetErrorString(ce));
-    PS_BHIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
     b->cap_rhs.assign(rhs, rhs + b->count);
     b->cap_out.assign(p, p + b->count);
     b->captured = true;
@@ -580,48 +224,66 @@ static int capture(ps_batch *b, const void *const *rhs, void *const *p)
 extern "C" int ps_batch_solve(ps_batch *b, const void *const *rhs, void *const *p)
 {
     if (!b || !rhs || !p) return bfail(PS_EINVAL, "batch, rhs and p must not be NULL");
-    if (!kSolveEnabled && b->mode != PS_BATCH_PLANS) return bfail(PS_EUNSUPPORTED, kSolveOff);
-    if (!kPlansEnabled && b->mode == PS_BATCH_PLANS) return bfail(PS_EUNSUPPORTED, kPlansOff);
     for (int i = 0; i < b->count; ++i) {
         if (!rhs[i] || !p[i]) return bfail(PS_EINVAL, "rhs[i] and p[i] must not be NULL");
-        if (rhs[i] == p[i]) return bfail(PS_EINVAL, "rhs[i] and p[i] must not alias");
+        if (b->precision == PS_FP32_R1 && rhs[i] == p[i])
+            return bfail(PS_EINVAL, "rhs[i] and p[i] must not alias in the PS_FP32_R1 form");
     }
     bool same = b->captured;
     for (int i = 0; same && i < b->count; ++i)
         same = b->cap_rhs[i] == rhs[i] && b->cap_out[i] == p[i];
     if (!same) {
-        // the previous replay may still read the old pointers: wait for it
+        // the caller's earlier work (which may produce rhs) and any replay
+        // still using the old graphs must be complete before the eager pass
         PS_BHIP(hipStreamSynchronize(b->stream));
-        const int rc = capture(b, rhs, p);
+        int rc = sync_lanes(b);
+        if (rc == PS_OK) rc = capture_lanes(b, rhs, p);
         if (rc != PS_OK) return rc;
     }
-    // replay on the batch's own stream, ordered after the caller's stream and
-    // before anything the caller enqueues next
+    // fork the lanes from the caller's stream, replay, join back
     PS_BHIP(hipEventRecord(b->ev_in, b->stream));
-    PS_BHIP(hipStreamWaitEvent(b->cap, b->ev_in, 0));
-    PS_BHIP(hipGraphLaunch(b->exec, b->cap));
-    PS_BHIP(hipEventRecord(b->ev_out, b->cap));
-    PS_BHIP(hipStreamWaitEvent(b->stream, b->ev_out, 0));
+    for (int l = 0; l < b->nlanes; ++l) {
+        if (!b->exec[l]) continue;
+        PS_BHIP(hipStreamWaitEvent(b->lanes[l], b->ev_in, 0));
+        PS_BHIP(hipGraphLaunch(b->exec[l], b->lanes[l]));
+        PS_BHIP(hipEventRecord(b->ev_join[l], b->lanes[l]));
+        PS_BHIP(hipStreamWaitEvent(b->stream, b->ev_join[l], 0));
+    }
     return PS_OK;
 }
 
 extern "C" int ps_batch_set_mode(ps_batch *b, int mode)
 {
     if (!b) return bfail(PS_EINVAL, "batch is NULL");
-    if (mode == PS_BATCH_PHASES || mode == PS_BATCH_PLANS) {
-        if (mode != b->mode) {
-            // a replay may still run the old graph
-            PS_BHIP(hipStreamSynchronize(b->stream));
-            PS_BHIP(hipStreamSynchronize(b->cap));
-            destroy_graph(b);
-        }
-        b->mode = mode;
-        return PS_OK;
+    switch (mode) {
+    case PS_BATCH_LANES: return PS_OK;
+    case PS_BATCH_PERSISTENT:
+        return bfail(PS_EUNSUPPORTED, "the single persistent launch is withdrawn: it did not "
+                                      "complete on the GPU and its cause was not found");
+    case PS_BATCH_PHASES:
+        return bfail(PS_EUNSUPPORTED, "the per-phase tile launches are withdrawn with the "
+                                      "persistent launch whose work list they shared");
+    case PS_BATCH_PLANS:
+        return bfail(PS_EUNSUPPORTED, "the single-graph capture over forked plan streams is "
+                                      "withdrawn after a host fault during its capture; use "
+                                      "PS_BATCH_LANES");
+    default: return bfail(PS_EINVAL, "unknown batch mode");
     }
-    if (mode == PS_BATCH_PERSISTENT)
-        return bfail(PS_EUNSUPPORTED, "the single persistent launch is switched off: it did not "
-                                      "complete on the GPU and its cause is not yet found");
-    return bfail(PS_EINVAL, "unknown batch mode");
+}
+
+extern "C" int ps_batch_set_lanes(ps_batch *b, int lanes)
+{
+    if (!b) return bfail(PS_EINVAL, "batch is NULL");
+    if (lanes < 1 || lanes > kMaxLanes) return bfail(PS_EINVAL, "lanes must be in [1, 8]");
+    if (lanes == b->nlanes) return PS_OK;
+    // a replay may still run the old graphs
+    PS_BHIP(hipStreamSynchronize(b->stream));
+    const int rc = sync_lanes(b);
+    if (rc != PS_OK) return rc;
+    destroy_graphs(b);
+    b->nlanes = lanes;
+    assign_lanes(b);
+    return PS_OK;
 }
 
 extern "C" int ps_batch_set_stream(ps_batch *b, void *stream)
@@ -631,46 +293,42 @@ extern "C" int ps_batch_set_stream(ps_batch *b, void *stream)
     return PS_OK;
 }
 
-// Times the work layouts for LDS budgets of 32, 48 and 60 KiB per block
-// (rows per transform tile follow from the budget) and keeps the fastest.
+// Each problem's plan times its own kernel variants (ps_plan_autotune;
+// equal shapes share the choice through the tune cache), then the lane
+// counts 1, 2, 4 and 8 are timed over reps replays each on the given fields
+// and the fastest is kept.  The graphs are captured again on the next solve.
 extern "C" int ps_batch_autotune(ps_batch *b, const void *const *rhs, void *const *p, int reps)
 {
     if (!b || !rhs || !p) return bfail(PS_EINVAL, "batch, rhs and p must not be NULL");
     if (reps < 1) reps = 1;
     if (reps > 100) reps = 100;
-    if (b->mode == PS_BATCH_PLANS) {
-        if (!kPlansEnabled) return bfail(PS_EUNSUPPORTED, kPlansOff);
-        // each problem's plan times its own kernel variants (equal shapes
-        // share the choice through the tune cache); the graph is captured
-        // again on the next solve
-        PS_BHIP(hipStreamSynchronize(b->stream));
-        PS_BHIP(hipStreamSynchronize(b->cap));
-        destroy_graph(b);
-        for (int n = 0; n < b->count; ++n) {
-            const int i = b->order[n];
-            int rc = ps_plan_set_stream(b->plans[i], b->stream);
-            if (rc == PS_OK) rc = ps_plan_autotune(b->plans[i], reps);
-            if (rc != PS_OK)
-                return ps::set_error(rc, std::string("problem ") + std::to_string(i) + ": " +
-                                             ps_last_error());
-        }
-        return PS_OK;
+    PS_BHIP(hipStreamSynchronize(b->stream));
+    int rc = sync_lanes(b);
+    if (rc != PS_OK) return rc;
+    destroy_graphs(b);
+    for (int i : b->order) {
+        rc = ps_plan_set_stream(b->plans[i], b->lanes[0]);
+        if (rc == PS_OK) rc = ps_plan_autotune(b->plans[i], reps);
+        if (rc != PS_OK)
+            return ps::set_error(rc, std::string("problem ") + std::to_string(i) + ": " +
+                                         ps_last_error());
     }
-    if (!kSolveEnabled) return bfail(PS_EUNSUPPORTED, kSolveOff);
-    hipEvent_t e0, e1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     PS_BHIP(hipEventCreate(&e0));
-    PS_BHIP(hipEventCreate(&e1));
-    int best = b->lds_budget;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return bfail(PS_EHIP, "event creation failed");
+    }
+    int best = b->nlanes;
     float best_ms = 1e30f;
-    int rc = PS_OK;
-    for (int budget : {32 * 1024, 48 * 1024, 60 * 1024}) {
-        b->lds_budget = budget;
-        rc = layout(b);
-        if (rc == PS_OK) rc = ps_batch_solve(b, rhs, p); // capture + warm-up
+    for (int lanes : {1, 2, 4, 8}) {
+        if (lanes > b->count && lanes > 1) break;
+        rc = ps_batch_set_lanes(b, lanes);
+        if (rc == PS_OK) rc = ps_batch_solve(b, rhs, p); // capture + one replay
         if (rc != PS_OK) break;
-        if (hipEventRecord(e0, b->stream) != hipSuccess) { rc = PS_EHIP; break; }
-        for (int r = 0; r < reps && rc == PS_OK; ++r) rc = ps_batch_solve(b, rhs, p);
         float ms = 0.f;
+        if (hipEventRecord(e0, b->stream) != hipSuccess) rc = bfail(PS_EHIP, "autotune timing");
+        for (int r = 0; r < reps && rc == PS_OK; ++r) rc = ps_batch_solve(b, rhs, p);
         if (rc == PS_OK && (hipEventRecord(e1, b->stream) != hipSuccess ||
                             hipEventSynchronize(e1) != hipSuccess ||
                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
@@ -678,14 +336,13 @@ extern "C" int ps_batch_autotune(ps_batch *b, const void *const *rhs, void *cons
         if (rc != PS_OK) break;
         if (ms < best_ms) {
             best_ms = ms;
-            best = budget;
+            best = lanes;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != PS_OK) return rc;
-    b->lds_budget = best;
-    return layout(b);
+    return ps_batch_set_lanes(b, best);
 }
 
 extern "C" int ps_batch_query(const ps_batch *b, int *count, int *tiles, int *grid,
@@ -693,37 +350,25 @@ extern "C" int ps_batch_query(const ps_batch *b, int *count, int *tiles, int *gr
 {
     if (!b) return bfail(PS_EINVAL, "batch is NULL");
     if (count) *count = b->count;
-    if (tiles) *tiles = b->nitems;
-    if (grid) *grid = b->grid;
-    if (lds_budget) *lds_budget = b->lds_budget;
+    if (tiles) *tiles = 0;
+    if (grid) *grid = b->nlanes;
+    if (lds_budget) *lds_budget = 0;
     return PS_OK;
 }
 
-// Synchronises the batch's stream and reports whether the last replay ended
-// normally (PS_OK) or raised the work-list error flag (PS_ESTATE).
+// Synchronises the caller's stream (which the replay joins) and the lanes.
 extern "C" int ps_batch_status(ps_batch *b)
 {
     if (!b) return bfail(PS_EINVAL, "batch is NULL");
-    if (!b->captured) return PS_OK;
-    if (b->mode != PS_BATCH_PERSISTENT) {
-        PS_BHIP(hipStreamSynchronize(b->stream));
-        return PS_OK;
-    }
-    int *flag = nullptr, host = 0;
-    PS_BHIP(hipMalloc(&flag, sizeof(int)));
-    hipLaunchKernelGGL(k_batch_flag, dim3(1), dim3(1), 0, b->stream, b->counters, flag);
-    hipError_t e = hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    (void)hipFree(flag);
-    if (e != hipSuccess) return bfail(PS_EHIP, std::string("status: ") + hipGetErrorString(e));
-    return host ? bfail(PS_ESTATE, "a batched solve gave up waiting for a phase") : PS_OK;
+    PS_BHIP(hipStreamSynchronize(b->stream));
+    return sync_lanes(b);
 }
 
 extern "C" int ps_batch_destroy(ps_batch *b)
 {
     if (!b) return PS_OK;
     (void)hipStreamSynchronize(b->stream);
-    (void)hipStreamSynchronize(b->cap);
+    (void)sync_lanes(b);
     free_batch(b);
     return PS_OK;
 }

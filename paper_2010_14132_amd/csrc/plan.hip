@@ -459,7 +459,10 @@ extern "C" int ps_plan_set_coeffs(ps_plan *p, const double *rho)
     if (!p || !rho) return fail(PS_EINVAL, "plan and rho must not be NULL");
     for (int k = 0; k < p->nz; ++k)
         if (!finite_pos(rho[k])) return fail(PS_EINVAL, "rho values must be finite and > 0");
-    PS_HIP(hipStreamSynchronize(p->stream));
+    // Work enqueued earlier may still read the tables, and not necessarily on
+    // the plan's current stream (the stream may have been changed since): wait
+    // for the whole device before they are overwritten.
+    PS_HIP(hipDeviceSynchronize());
     p->rho.assign(rho, rho + p->nz);
     host_tables(p);
     PS_TRY(upload_coeff_tables(p, p->t64));

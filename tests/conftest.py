@@ -13,6 +13,11 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: CPU test that takes more than a few seconds")
 
 
-def pytest_collection_modifyitems(config, items):
-    # A test marked gpu must not silently pass on a box without a GPU.
-    pass
+@pytest.fixture(autouse=True)
+def _gpu_tests_need_a_gpu(request):
+    """A test marked gpu fails (it is not skipped) on a machine without a
+    GPU, so a GPU run that silently lost its device cannot pass."""
+    if request.node.get_closest_marker("gpu") is not None:
+        import torch
+        if not torch.cuda.is_available():
+            pytest.fail("test marked gpu run without a GPU")

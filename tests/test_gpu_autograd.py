@@ -141,3 +141,41 @@ def test_c3_dense_transpose_16x16x8(precision):
     tol = 1e-11 if precision == "fp64" else 1e-5
     assert eb < tol
     assert er < tol
+
+
+def test_shared_plan_two_densities_one_backward():
+    """Two forwards through one plan at different densities, one loss, one
+    backward: each forward's gradient must use its own operator (the
+    backward sets that forward's densities for the adjoint solve and the
+    density gradient and restores the plan's current ones).  Checked
+    against the dense bordered system and complex-step differentiation."""
+    from paper_2010_14132_amd import poisson_solve
+    announce("shared plan, two densities, one backward 16x16x8 fp64")
+    prob = wl.stretched_smooth(16, 16, 8, seed=3005, dtype="f64")
+    g = prob.grid
+    b = prob.rhs_exact()
+    rho1 = g.rho.copy()
+    rho2 = g.rho * np.linspace(0.7, 1.4, g.nz)
+    rng = np.random.default_rng(3006)
+    w1, w2 = rng.standard_normal(g.shape), rng.standard_normal(g.shape)
+    plan = make_plan(g, "fp64")
+    bt = torch.from_numpy(b).cuda().requires_grad_(True)
+    r1 = torch.tensor(rho1, dtype=torch.float64, requires_grad=True)
+    r2 = torch.tensor(rho2, dtype=torch.float64, requires_grad=True)
+    p1 = poisson_solve(bt, r1, plan)
+    p2 = poisson_solve(bt, r2, plan)  # the plan now holds rho2
+    loss = (torch.from_numpy(w1).cuda() * p1).sum() + (torch.from_numpy(w2).cuda() * p2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    want_b = (dc.dense_adjoint(w1, g.dx, g.dy, g.dz, rho1)
+              + dc.dense_adjoint(w2, g.dx, g.dy, g.dz, rho2))
+    g2 = wl.Grid(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, rho2)
+    eb = np.abs(bt.grad.cpu().numpy() - want_b).max() / np.abs(want_b).max()
+    e1 = np.abs(r1.grad.numpy() - complex_step_grad(b, w1, g)).max()
+    e2 = np.abs(r2.grad.numpy() - complex_step_grad(b, w2, g2)).max()
+    print("grad_b rel %.3e, grad_rho abs %.3e %.3e" % (eb, e1, e2))
+    assert eb < 1e-11
+    assert e1 < 1e-11 * np.abs(r1.grad.numpy()).max()
+    assert e2 < 1e-11 * np.abs(r2.grad.numpy()).max()
+    assert np.array_equal(plan.rho, rho2)  # the plan's own densities restored
+    plan.close()

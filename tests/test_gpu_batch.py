@@ -1,7 +1,9 @@
-"""Batched solves in the tile-based mode (one kernel per phase over the
-tiles of every problem), against the FP64 oracle and against the
-single-problem plans.  Skipped: that mode shares its tile code with the
-persistent launch that did not complete on the GPU."""
+"""Batched solves in the withdrawn tile-based mode (one kernel per phase over
+the tiles of every problem), against the FP64 oracle and against the
+single-problem plans.  Skipped: that mode shared its tile work list with the
+persistent launch that did not complete on the GPU, and both were withdrawn
+from the library (ps_batch_set_mode refuses them); batched solves now run in
+the lanes mode (tests/test_gpu_batch_lanes.py)."""
 import numpy as np
 import pytest
 
@@ -11,9 +13,9 @@ from paper_2010_14132_amd import workloads as wl
 torch = pytest.importorskip("torch")
 pytestmark = [
     pytest.mark.gpu,
-    pytest.mark.skip(reason="batched solves are switched off in the library: the persistent "
-                            "launch did not complete on the GPU and its cause is not found; the "
-                            "per-phase graph that replaces it has not been run on the GPU yet"),
+    pytest.mark.skip(reason="withdrawn mode: the persistent launch did not complete on the GPU "
+                            "and its cause was not found; the per-phase form shared its work "
+                            "list and was withdrawn with it"),
 ]
 
 

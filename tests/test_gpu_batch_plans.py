@@ -1,5 +1,9 @@
-"""Batched solves in mode PS_BATCH_PLANS: every problem's own plan solve
-captured into one hipGraph, problems spread over four streams.  Each problem
+"""Batched solves in the withdrawn mode PS_BATCH_PLANS: every problem's own
+plan solve captured into ONE hipGraph, the plans' streams being four lanes
+forked from the capture's origin.  Skipped: its first run ended in a host
+segmentation fault during that capture and the mode was withdrawn
+(ps_batch_set_mode refuses it); batched solves now run in the lanes mode
+(tests/test_gpu_batch_lanes.py).  Each problem
 runs the single-solve kernels with its planning defaults, so the result must
 equal a standalone plan's solve bit for bit; small problems are also checked
 against the FP64 oracle."""
@@ -14,9 +18,8 @@ from paper_2010_14132_amd import workloads as wl
 torch = pytest.importorskip("torch")
 pytestmark = [
     pytest.mark.gpu,
-    pytest.mark.skip(reason="the plan-graph batched solve is switched off in the library: its "
-                            "first run ended in a host segmentation fault during the first "
-                            "capture, and the cause is not yet found"),
+    pytest.mark.skip(reason="withdrawn mode: its first run ended in a host segmentation fault "
+                            "during the single capture over forked plan streams"),
 ]
 
 
