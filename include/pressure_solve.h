@@ -136,6 +136,16 @@ int ps_solve_adjoint(ps_plan *plan, const void *gp, void *grhs);
  * Deterministic (fixed-order reductions, no atomics). */
 int ps_grad_coeffs(ps_plan *plan, const void *lam, const void *p, double *grho);
 
+/* ps_grad_coeffs for callers that cannot allocate device memory during the
+ * call (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same kernels and the same result, with the
+ * per-block partial sums in a fixed device array of the library (2 MiB per
+ * GPU, held until the process ends; every valid plan fits, larger needs
+ * would give PS_EUNSUPPORTED) instead of the plan's buffer.  Allocates
+ * nothing.  All calls on one GPU share that GPU's array: calls that overlap
+ * on one GPU (on different streams, or from several host threads) race. */
+int ps_grad_coeffs_noalloc(ps_plan *plan, const void *lam, const void *p, double *grho);
+
 /* Device workspace owned by the plan, in bytes. */
 size_t ps_workspace_bytes(const ps_plan *plan);
 

@@ -49,6 +49,7 @@ SIGNATURES = {
     "ps_solve": (ctypes.c_int, [_vp, _vp, _vp]),
     "ps_solve_adjoint": (ctypes.c_int, [_vp, _vp, _vp]),
     "ps_grad_coeffs": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "ps_grad_coeffs_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "ps_workspace_bytes": (ctypes.c_size_t, [_vp]),
     "ps_plan_query": (ctypes.c_int, [_vp, ctypes.POINTER(PlanInfo)]),
     "ps_plan_autotune": (ctypes.c_int, [_vp, ctypes.c_int]),
