@@ -11,7 +11,12 @@ side, already resident in HBM.
 Prints ONE JSON line: the headline value is solves/s of the FP32 form with
 refinement (precision "fp32_r2" by default), with the plain FP64 GPU solve
 and the other precision forms measured on the same grid beside it, the
-roofline of the dominant kernel, and the CPU oracle timed on a bounded sample.
+roofline of the dominant kernel, the whole solve's share of HBM peak, the
+other workloads (32^2 x 16 plain, 256^2 x 64 plain, 512^2 x 128
+differentiation, the 48-problem uneven batch) under "configs", and on the
+CPU side the oracle timed on a bounded sample (all cores, and one core for
+the two small workloads) next to a fast FP64 CPU solve (scipy FFTs and a
+vectorised column sweep), which is labelled apart from the oracle.
 """
 from __future__ import annotations
 
@@ -154,6 +159,260 @@ def time_solves(plan, b, out, steps, warmup):
     return time_calls(lambda: plan.solve(b, out=out), steps, warmup)
 
 
+def time_distribution(call, reps):
+    """Per-call device times (ms) of `reps` calls, each bracketed by its own
+    pair of events on the current stream: (median, min, mean)."""
+    import torch
+    st = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record(st)
+        call()
+        b.record(st)
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in ev])
+    return {"median_ms": float(np.median(t)), "min_ms": float(t.min()),
+            "mean_ms": float(t.mean()), "reps": reps}
+
+
+# ------------------------------------------------------------ fast CPU reference
+def fast_cpu_solve(b, dx, dy, dz, rho, workers):
+    """The same discrete problem solved on the CPU in FP64 the fast way, as a
+    speed reference next to the oracle (whose direct DFTs make it slow): the
+    D-weighted mean removed, scipy.fft real 2D transforms of all levels with
+    `workers` threads, the dominance-excess column sweep vectorised over all
+    wavenumbers (numpy), the mean column by flux prefix sums with the
+    zero-mean gauge, and the inverse transform."""
+    import scipy.fft as sfft
+    b = np.asarray(b, dtype=np.float64)
+    nz, ny, nx = b.shape
+    dz = np.asarray(dz, dtype=np.float64)
+    rho = np.asarray(rho, dtype=np.float64)
+    f = np.zeros(nz + 1)                       # f[k] = f_{k-1/2}, zero at both ends
+    f[1:nz] = 0.5 * (rho[:-1] + rho[1:]) / (0.5 * (dz[:-1] + dz[1:]))
+    D = rho * dz
+    S = b.sum(axis=(1, 2))
+    mu = float((D * S).sum() / (nx * ny * D.sum()))
+    B = sfft.rfft2(b, axes=(1, 2), workers=workers)   # [nz][ny][nx/2+1]
+    B[:, 0, 0] -= mu * nx * ny
+    kx = np.arange(nx // 2 + 1)
+    ky = np.arange(ny)
+    s = (4 * np.sin(np.pi * ky / ny) ** 2 / dy ** 2)[:, None] \
+        + (4 * np.sin(np.pi * kx / nx) ** 2 / dx ** 2)[None, :]
+    mean_col = B[:, 0, 0].real.copy()
+    s[0, 0] = 1.0                               # placeholder: the mean column is done apart
+    # forward elimination of (-D T) x = -D b_hat, pivots u_k from positive terms
+    U = np.empty((nz,) + s.shape)
+    eps = s * D[0]
+    U[0] = eps + f[1]
+    B[0] *= -D[0]
+    for k in range(1, nz):
+        g = f[k] / U[k - 1]
+        eps = s * D[k] + g * eps
+        U[k] = eps + f[k + 1]
+        B[k] *= -D[k]
+        B[k] += g * B[k - 1]
+    B[nz - 1] /= U[nz - 1]
+    for k in range(nz - 2, -1, -1):
+        B[k] += f[k + 1] * B[k + 1]
+        B[k] /= U[k]
+    # mean column: V x = c by flux prefix sums, then zero mean over levels
+    x = np.zeros(nz)
+    flux = 0.0
+    for k in range(nz - 1):
+        flux += D[k] * mean_col[k]
+        x[k + 1] = x[k] + flux / f[k + 1]
+    B[:, 0, 0] = x - x.mean()
+    return sfft.irfft2(B, s=(ny, nx), axes=(1, 2), workers=workers)
+
+
+def fast_cpu_reference(prob, p_gpu64=None):
+    """Times fast_cpu_solve on the full workload with every host core (the
+    better of two runs) and, given the FP64 GPU solution, reports the two
+    solutions' relative difference."""
+    g = prob.grid
+    workers = os.cpu_count() or 1
+    b = prob.rhs_exact()
+    best = None
+    for _ in range(2):
+        t0 = time.perf_counter()
+        p = fast_cpu_solve(b, g.dx, g.dy, g.dz, g.rho, workers)
+        t = time.perf_counter() - t0
+        best = t if best is None else min(best, t)
+    out = {"kind": "fast_cpu_reference (not the oracle)", "value": 1.0 / best,
+           "unit": "solves/s", "ms_per_solve": best * 1e3, "cores": workers,
+           "mpts_per_s": g.points / best / 1e6,
+           "method": "FP64: scipy.fft rfft2/irfft2 over all levels (workers=%d), "
+                     "dominance-excess column sweep vectorised over wavenumbers (numpy), "
+                     "mean column by prefix sums; best of 2 full solves" % workers}
+    if p_gpu64 is not None:
+        out["rel_max_vs_fp64_gpu"] = float(np.abs(p - p_gpu64).max() / np.abs(p_gpu64).max())
+    return out
+
+
+_ORACLE_1CORE = r"""
+import json, sys, time
+sys.path.insert(0, %r)
+import numpy as np
+import oracle
+from paper_2010_14132_amd import workloads as wl
+out = {}
+for name, prob in (("uniform_32x32x16", wl.uniform_white(seed=0)), ("plain_256x256x64", wl.plain_256())):
+    g = prob.grid
+    b = prob.rhs_exact()
+    oracle.solve(b, g.dx, g.dy, g.dz, g.rho)
+    t0 = time.perf_counter()
+    oracle.solve(b, g.dx, g.dy, g.dz, g.rho)
+    t = time.perf_counter() - t0
+    out[name] = {"s_per_solve": t, "solves_per_s": 1.0 / t, "mpts_per_s": g.points / t / 1e6}
+out["threads"] = oracle.num_threads()
+print(json.dumps(out))
+"""
+
+
+def oracle_small_configs():
+    """The oracle on the 32^2 x 16 and 256^2 x 64 workloads, on one core (a
+    child process with OMP_NUM_THREADS=1, which touches no GPU) and on every
+    core (this process)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", _ORACLE_1CORE % ROOT], env=env,
+                       capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-400:]}
+    one = json.loads(r.stdout.strip().splitlines()[-1])
+    env["OMP_NUM_THREADS"] = str(os.cpu_count() or 1)
+    r = subprocess.run([sys.executable, "-c", _ORACLE_1CORE % ROOT], env=env,
+                       capture_output=True, text=True, timeout=600)
+    allc = json.loads(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else {}
+    return {"kind": "oracle", "one_core": one, "all_cores": allc}
+
+
+# ------------------------------------------------------------ other workloads
+def rel_max(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def config_forms(prob, forms, steps, warmup, oracle_ref=True):
+    """Solves/s and Mpts/s of each precision form on one workload (autotuned
+    plans), the per-solve time distribution, and rel_max against the oracle
+    (whole field) when oracle_ref."""
+    import torch
+    import oracle
+    from paper_2010_14132_amd import Plan
+    g = prob.grid
+    b64 = prob.rhs_exact() if prob.dtype == "f32" else prob.rhs
+    ref = oracle.solve(b64, g.dx, g.dy, g.dz, g.rho) if oracle_ref else None
+    res = {}
+    for form in forms:
+        plan = Plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.rho, precision=form)
+        plan.autotune(reps=5)
+        dt = torch.float64 if form == "fp64" else torch.float32
+        b = torch.from_numpy(b64).to("cuda", dt)
+        out = torch.empty_like(b)
+        ms = time_calls(lambda: plan.solve(b, out=out), steps, warmup)
+        d = time_distribution(lambda: plan.solve(b, out=out), max(50, steps))
+        r = {"ms_per_solve": ms, "solves_per_s": 1e3 / ms, "mpts_per_s": g.points / ms / 1e3,
+             "median_ms": d["median_ms"], "min_ms": d["min_ms"], "mean_ms": d["mean_ms"],
+             "reps": d["reps"]}
+        if ref is not None:
+            r["rel_max_vs_oracle"] = rel_max(out.double().cpu().numpy(), ref)
+        res[form] = r
+        plan.close()
+    return res
+
+
+def config_differentiation(steps, warmup):
+    """512^2 x 128 differentiation workload: forward solve, adjoint solve and
+    density gradient (one differentiation step = all three), FP32 form with
+    FP64 mean / near-singular columns, and the FP64 forward solve beside it."""
+    import torch
+    from paper_2010_14132_amd import Plan
+    from paper_2010_14132_amd import workloads as wl
+    prob = wl.differentiation_512()
+    g = prob.grid
+    res = {"workload": "512x512x128 stretched grid, smooth RHS (seed 3), loss weights seed 1003"}
+    for form in ("fp32", "fp64"):
+        plan = Plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.rho, precision=form)
+        plan.autotune(reps=5)
+        dt = torch.float64 if form == "fp64" else torch.float32
+        b = torch.from_numpy(prob.rhs_exact()).to("cuda", dt)
+        w = torch.from_numpy(prob.extra["w"]).to("cuda", dt)
+        p, lam = torch.empty_like(b), torch.empty_like(b)
+
+        def step():
+            plan.solve(b, out=p)
+            plan.solve_adjoint(w, out=lam)
+            plan.grad_coeffs(lam, p)
+
+        fwd = time_calls(lambda: plan.solve(b, out=p), steps, warmup)
+        adj = time_calls(lambda: plan.solve_adjoint(w, out=lam), steps, warmup)
+        stp = time_calls(step, steps, warmup)
+        res[form] = {"forward_ms": fwd, "solves_per_s": 1e3 / fwd,
+                     "mpts_per_s": g.points / fwd / 1e3, "adjoint_ms": adj,
+                     "differentiation_step_ms": stp, "steps_per_s": 1e3 / stp}
+        plan.close()
+    return res
+
+
+def config_batch(steps, warmup):
+    """The 48-problem uneven batch (FP32): autotuned (each plan's kernels and
+    the lane count), latency = median device time of one batched solve
+    (events on the caller's stream around the whole replay) over >= 50
+    replays, aggregate Mpts/s = total points / latency; beside it the same
+    48 solves issued one after another on one stream, and rel_max against
+    the oracle on the four smallest problems."""
+    import torch
+    import oracle
+    from paper_2010_14132_amd import BatchPlan, Plan
+    from paper_2010_14132_amd import workloads as wl
+    probs = wl.batch_problems()
+    npts = sum(p.grid.points for p in probs)
+    batch = BatchPlan([p.grid for p in probs], precision="fp32")
+    rhs = [torch.from_numpy(p.rhs_as("f32")).cuda() for p in probs]
+    out = [torch.empty_like(r) for r in rhs]
+    batch.autotune(rhs, out, reps=3)
+    ms = time_calls(lambda: batch.solve(rhs, out), steps, warmup)
+    d = time_distribution(lambda: batch.solve(rhs, out), max(50, steps))
+    alg = sum(40.0 * p.grid.points for p in probs)  # five passes of 2 e bytes per point, e = 4
+    res = {"workload": "48 problems, nx = ny in {64..512}, nz in {32..128}, stretch U[1, 1.05], "
+                       "seed 4; problem i smooth RHS seed 4000+i",
+           "problems": len(probs), "points": npts, "lanes": batch.info()["lanes"],
+           "latency_median_ms": d["median_ms"], "latency_min_ms": d["min_ms"],
+           "latency_mean_ms": d["mean_ms"], "reps": d["reps"], "ms_per_batch_mean": ms,
+           "aggregate_mpts_per_s": npts / d["median_ms"] / 1e3,
+           "batches_per_s": 1e3 / d["median_ms"],
+           "alg_bytes": alg, "hbm_frac": alg / (d["median_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    small = sorted(range(len(probs)), key=lambda i: probs[i].grid.points)[:4]
+    errs = []
+    for i in small:
+        g = probs[i].grid
+        ref = oracle.solve(probs[i].rhs_exact(), g.dx, g.dy, g.dz, g.rho)
+        errs.append(rel_max(out[i].double().cpu().numpy(), ref))
+    res["rel_max_vs_oracle_smallest4"] = max(errs)
+    plans = []
+    for p in probs:
+        q = Plan(p.grid.nx, p.grid.ny, p.grid.nz, p.grid.dx, p.grid.dy, p.grid.dz, p.grid.rho,
+                 precision="fp32")
+        q.autotune(reps=3)  # the tune cache: the batch's own choices
+        plans.append(q)
+    seq = [torch.empty_like(r) for r in rhs]
+
+    def sequential():
+        for q, r, o in zip(plans, rhs, seq):
+            q.solve(r, out=o)
+
+    ds = time_distribution(sequential, max(20, steps // 2))
+    res["sequential_one_stream_median_ms"] = ds["median_ms"]
+    res["speedup_vs_sequential"] = ds["median_ms"] / d["median_ms"]
+    for q in plans:
+        q.close()
+    batch.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +429,10 @@ def main():
                          "(so that profiled runs use the same kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM counters)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workloads (32^2x16, 256^2x64, 512^2x128, the batch)")
+    ap.add_argument("--no-fast-cpu", action="store_true",
+                    help="skip the fast CPU reference and the small-workload oracle timings")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -228,7 +491,11 @@ def main():
                                      ("fft_variant_x", "fft_variant_xi", "fft_variant_y",
                                       "column_variant", "chunks")}}
         outputs[form] = out
-        print("bench: %-8s %.4f ms/solve" % (form, ms), file=sys.stderr, flush=True)
+        dist = time_distribution(lambda: plan.solve(b, out=out), max(50, steps))
+        results[form].update({"median_ms": dist["median_ms"], "min_ms": dist["min_ms"],
+                              "mean_ms": dist["mean_ms"], "reps": dist["reps"]})
+        print("bench: %-8s %.4f ms/solve (median %.4f over %d)"
+              % (form, ms, dist["median_ms"], dist["reps"]), file=sys.stderr, flush=True)
         if form == args.precision:
             # the differentiation path of the same form: the adjoint solve
             # (gp = the right-hand side) and the density gradient from the
@@ -269,6 +536,13 @@ def main():
                         "alg_bytes_per_solve": alg,
                         "gbs": (alg / (per_solve_ms * 1e-3) / 1e9) if bpp else None}
         results[form]["kernel_times"] = kt
+        # the whole solve against HBM peak: the algorithmic bytes of all its
+        # passes over the solve's wall time (streams overlapped)
+        alg_total = sum(v["alg_bytes_per_solve"] for v in kt.values())
+        results[form]["whole_solve"] = {
+            "alg_bytes": alg_total, "bytes_per_point": alg_total / N,
+            "gbs": alg_total / (results[form]["ms_per_solve"] * 1e-3) / 1e9,
+            "hbm_frac": alg_total / (results[form]["ms_per_solve"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
         if form == args.precision:
             kernels = kt
         plan.close()
@@ -330,9 +604,39 @@ def main():
         line["device_copy_gbs"] = copy_gbs
     if "fp64" in results and args.precision != "fp64":
         line["speedup_vs_fp64"] = results["fp64"]["ms_per_solve"] / results[args.precision]["ms_per_solve"]
+    line["whole_solve_hbm"] = results[args.precision]["whole_solve"]
+    line["timing"] = {k: results[args.precision][k] for k in ("median_ms", "min_ms", "mean_ms",
+                                                               "reps")}
+    if not args.no_fast_cpu:
+        print("bench: fast CPU reference (FP64 scipy FFT + vectorised sweep)", file=sys.stderr,
+              flush=True)
+        p64 = outputs["fp64"].cpu().numpy() if "fp64" in outputs else None
+        line["fast_cpu_reference"] = fast_cpu_reference(prob, p64)
+        del p64
+    del outputs
+    if not args.no_configs:
+        from paper_2010_14132_amd import workloads as wl2
+        configs = {}
+        print("bench: 32x32x16 plain", file=sys.stderr, flush=True)
+        configs["uniform_32x32x16"] = {
+            "workload": "32x32x16, dz = 40 m, rho = 1, white RHS (seed 0)",
+            "forms": config_forms(wl2.uniform_white(seed=0), ["fp64", "fp32_r2"],
+                                  max(200, args.steps), args.warmup)}
+        print("bench: 256x256x64 plain", file=sys.stderr, flush=True)
+        configs["plain_256x256x64"] = {
+            "workload": "256x256x64 stretched grid, rho(z), smooth RHS (seed 1)",
+            "forms": config_forms(wl2.plain_256(), ["fp64", "fp32", "fp32_r2", "fp32_r1"],
+                                  max(100, args.steps), args.warmup)}
+        print("bench: 512x512x128 differentiation", file=sys.stderr, flush=True)
+        configs["differentiation_512x512x128"] = config_differentiation(args.steps, args.warmup)
+        print("bench: 48-problem uneven batch", file=sys.stderr, flush=True)
+        configs["batch_48"] = config_batch(args.steps, args.warmup)
+        line["configs"] = configs
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(g, g.nz)
+        if not args.no_fast_cpu:
+            line["oracle_small_workloads"] = oracle_small_configs()
     print(json.dumps(line), flush=True)
 
 
