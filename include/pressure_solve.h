@@ -159,6 +159,8 @@ typedef struct ps_plan_info {
     int column_variant;   /* column-solve kernel chosen by planning / autotuning */
     int chunks;           /* kx ranges the y / column / y passes are split into */
     int fft_variant_xi;   /* ... and backward x */
+    int special_variant;  /* FP64-column kernel: 0 one lane per task through an HBM
+                             workspace, 1 staged in LDS */
 } ps_plan_info;
 
 int ps_plan_query(const ps_plan *plan, ps_plan_info *info);
@@ -171,11 +173,12 @@ int ps_plan_query(const ps_plan *plan, ps_plan_info *info);
  * nz, precision) for the life of the process -- a later autotune of an equal
  * plan just applies them -- and can be saved to / loaded from a text file
  * (one line per entry: arch nx ny nz precision x_variant y_variant
- * column_variant [fp64_beside [chunks [xi_variant]]]: fp64_beside 1 when the
- * FP64 columns run on a second stream beside the main column kernel, chunks
- * the number of kx ranges the y / column / y passes are taken in, both
- * defaulting to 1; xi_variant the backward x pass's, defaulting to
- * x_variant).
+ * column_variant [fp64_beside [chunks [xi_variant [special_variant]]]]:
+ * fp64_beside 1 when the FP64 columns run on a second stream beside the
+ * main column kernel, chunks the number of kx ranges the y / column / y
+ * passes are taken in, both defaulting to 1; xi_variant the backward x
+ * pass's, defaulting to x_variant; special_variant the FP64-column kernel's
+ * (0 or 1), defaulting to 1).
  * Synchronises. */
 int ps_plan_autotune(ps_plan *plan, int reps);
 int ps_tune_cache_save(const char *path);

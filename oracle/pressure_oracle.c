@@ -35,7 +35,9 @@
  *   2. forward DFT of every level, x then y ("one dimension for all data,
  *      then the next"), by direct summation with exactly reduced angles,
  *   3. one tridiagonal solve per wavenumber column (kx,ky) != (0,0), and the
- *      singular (0,0) column by two prefix sums plus the zero-mean gauge,
+ *      singular (0,0) column by two prefix sums plus the zero-mean gauge
+ *      (formed from the level sums in extended precision, see
+ *      mean_column_ext),
  *   4. backward DFT with 1/(nx*ny), Hermitian completion, real part.
  * Adjoint and density-gradient routines follow the same definitions.
  */
@@ -332,6 +334,66 @@ static void mean_column(int nz, const double *f, const double *D,
     }
 }
 
+/* The (0,0) column from the level sums of the input, in extended precision
+ * (long double), written over spec[k][0][0].  The (0,0) coefficient of
+ * level k of the projected right-hand side is S_k - N m, N = nx ny, with
+ * S_k the level sum and m the projection's mean (forward: the D-weighted
+ * mean of b; adjoint: the plain mean of w).  Forward: V x = that column by
+ * the flux prefix sums of mean_column, zero plain mean over levels.
+ * Adjoint: V z = D^{-1} (that column), sum_k D_k z_k = 0, output D_k z_k.
+ * The prefix sums are divided by f_{k+1/2}, which is small near the top of
+ * a tall stretched grid, so rounding in them is amplified there; carried in
+ * extended precision, the oracle's own error stays far below the parity
+ * bars.  Same steps as the FP64 path for the other columns. */
+static int mean_column_ext(int nx, int ny, int nz, const double *f, const double *D,
+                           const double *in, int adjoint, double *spec)
+{
+    const int hx = nx / 2 + 1;
+    const size_t nxy = (size_t)nx * ny;
+    long double *S = (long double *)malloc(sizeof(long double) * 2 * (size_t)nz);
+    if (!S)
+        return OR_ENOMEM;
+    long double *x = S + nz;
+    long double num = 0.0L, den = 0.0L, tot = 0.0L;
+    for (int k = 0; k < nz; ++k) {
+        long double acc = 0.0L;
+        const double *lv = in + (size_t)k * nxy;
+        for (size_t q = 0; q < nxy; ++q)
+            acc += (long double)lv[q];
+        S[k] = acc;
+        num += (long double)D[k] * acc;
+        den += (long double)D[k];
+        tot += acc;
+    }
+    const long double N = (long double)nxy;
+    const long double m = adjoint ? tot / (N * (long double)nz) : num / (N * den);
+    long double F = 0.0L;
+    x[0] = 0.0L;
+    for (int k = 0; k + 1 < nz; ++k) {
+        long double c = S[k] - N * m;
+        if (adjoint)
+            c /= (long double)D[k];
+        F += (long double)D[k] * c;
+        x[k + 1] = x[k] + F / (long double)f[k + 1];
+    }
+    long double g = 0.0L, w = 0.0L;
+    for (int k = 0; k < nz; ++k) {
+        long double wk = adjoint ? (long double)D[k] : 1.0L;
+        g += wk * x[k];
+        w += wk;
+    }
+    for (int k = 0; k < nz; ++k) {
+        long double v = x[k] - g / w;
+        if (adjoint)
+            v *= (long double)D[k];
+        double *e = spec + 2 * (((size_t)k * ny) * hx);
+        e[0] = (double)v;
+        e[1] = 0.0;
+    }
+    free(S);
+    return OR_OK;
+}
+
 /* Shared driver for forward and adjoint spectral solves over the half
  * spectrum spec[nz][ny][hx][2], in place.  Forward (adjoint == 0):
  * x = T^{-1} b-hat per column, mean column by prefix sums, gauge: zero plain
@@ -445,6 +507,8 @@ int oracle_solve(int nx, int ny, int nz, double dx, double dy,
     if (!err)
         err = spectral_solve(nx, ny, nz, dx, dy, f, D, spec, 0);
     if (!err)
+        err = mean_column_ext(nx, ny, nz, f, D, b, 0, spec);
+    if (!err)
         err = oracle_dft2_inverse(nx, ny, nz, spec, p);
     free(f); free(bp); free(spec);
     return err;
@@ -481,6 +545,8 @@ int oracle_solve_adjoint(int nx, int ny, int nz, double dx, double dy,
     err = oracle_dft2_forward(nx, ny, nz, wp, spec);
     if (!err)
         err = spectral_solve(nx, ny, nz, dx, dy, f, D, spec, 1);
+    if (!err)
+        err = mean_column_ext(nx, ny, nz, f, D, w, 1, spec);
     if (!err)
         err = oracle_dft2_inverse(nx, ny, nz, spec, lam);
     free(f); free(wp); free(spec);

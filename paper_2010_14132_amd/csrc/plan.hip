@@ -489,6 +489,7 @@ extern "C" int ps_plan_query(const ps_plan *p, ps_plan_info *info)
     info->spectrum_elems = p->spec_elems();
     info->column_variant = p->geom.columns;
     info->chunks = p->geom.special_side ? p->geom.chunks : 1;
+    info->special_variant = p->geom.special_variant;
     return PS_OK;
 }
 
@@ -642,7 +643,7 @@ static hipError_t special_columns(ps_plan *p, cx_t<T> *spec, int adjoint, hipStr
         p, K_SPECIAL,
         [&] {
             return launch_special<T>(spec, p->nx, p->ny, p->nz, adjoint, p->d_mlist, p->nmask,
-                                     p->d_S, p->d_ws, p->t64, st, 0);
+                                     p->d_S, p->d_ws, p->t64, st, p->geom.special_variant);
         },
         st);
 }
@@ -879,6 +880,7 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
             p->geom.columns = it->second.columns;
             p->geom.special_side = it->second.special_side;
             p->geom.chunks = it->second.chunks;
+            p->geom.special_variant = it->second.special_variant;
             return PS_OK;
         }
     }
@@ -924,6 +926,7 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
         pick(&FftGeom::columns, {0, 1, 2, 3, 4, 5, 6, 7, 8});
     else
         pick(&FftGeom::columns, {0, 3, 5, 6, 7, 8});
+    pick(&FftGeom::special_variant, {0, 1});
     pick(&FftGeom::special_side, {0, 1});
     if (p->geom.special_side) pick(&FftGeom::chunks, {1, 2, 4, 8});
     p->prof.on = prof;
@@ -937,8 +940,9 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
 }
 
 // Text format, one line per entry: arch nx ny nz precision variant_x
-// variant_y columns special_side chunks variant_xi (the last three optional on
-// reading; variant_xi defaults to variant_x)
+// variant_y columns special_side chunks variant_xi special_variant (the last
+// four optional on reading; variant_xi defaults to variant_x,
+// special_variant to 1)
 extern "C" int ps_tune_cache_save(const char *path)
 {
     if (!path) return fail(PS_EINVAL, "path is NULL");
@@ -948,7 +952,7 @@ extern "C" int ps_tune_cache_save(const char *path)
     for (auto &kv : g_tune)
         f << kv.first << ' ' << kv.second.variant_x << ' ' << kv.second.variant_y << ' '
           << kv.second.columns << ' ' << kv.second.special_side << ' ' << kv.second.chunks << ' '
-          << kv.second.variant_xi << '\n';
+          << kv.second.variant_xi << ' ' << kv.second.special_variant << '\n';
     return f.good() ? PS_OK : fail(PS_EINVAL, "write failed");
 }
 
@@ -962,13 +966,14 @@ extern "C" int ps_tune_cache_load(const char *path)
     while (std::getline(f, line)) {
         std::istringstream is(line);
         std::string arch;
-        int nx, ny, nz, prec, vx, vy, col, side = 1, chunks = 1, vxi = -1;
+        int nx, ny, nz, prec, vx, vy, col, side = 1, chunks = 1, vxi = -1, spv = 1;
         if (!(is >> arch >> nx >> ny >> nz >> prec >> vx >> vy >> col)) continue;
         if (!(is >> side)) side = 1;
         if (!(is >> chunks)) chunks = 1;
         if (!(is >> vxi)) vxi = vx;
+        if (!(is >> spv)) spv = 1;
         if (vx < 0 || vx > 4 || vy < 0 || vy > 2 || col < 0 || col > 8 || side < 0 || side > 1 ||
-            chunks < 1 || chunks > 64 || vxi < 0 || vxi > 4)
+            chunks < 1 || chunks > 64 || vxi < 0 || vxi > 4 || spv < 0 || spv > 1)
             continue;
         std::ostringstream k;
         k << arch << ' ' << nx << ' ' << ny << ' ' << nz << ' ' << prec;
@@ -979,6 +984,7 @@ extern "C" int ps_tune_cache_load(const char *path)
         g.columns = col;
         g.special_side = side;
         g.chunks = chunks;
+        g.special_variant = spv;
         got[k.str()] = g;
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -52,6 +52,8 @@ struct FftGeom {
     int special_side = 1; // 1: FP64 columns on the side stream beside the main kernel
     int columns = 2;     // column-solve kernel variant (see launch_columns_impl)
     int chunks = 1;      // y forward / columns / y backward run in this many kx chunks
+    int special_variant = 1; // FP64 columns: 0 one lane per task via the HBM workspace,
+                             // 1 staged in LDS (k_special_lds)
 };
 
 struct Launch {

@@ -709,6 +709,62 @@ __device__ void columns3s_tile(cx_t<T> *__restrict__ spec, int L, int ny, const 
     }
 }
 
+// ----------------------------------------------------------- the mean column
+// The singular (0,0) column (FP64) from the level sums sS (unnormalised
+// level sums of the input), written as final values to xr[k * stride]
+// (xi[k * stride], used as scratch, ends zero).  The projection removes the
+// mean M of the level sums (forward: D-weighted, adjoint: plain), so the
+// column's right-hand side is c_k = (S_k - M)/(nx ny).  The face fluxes
+// F_{k+1/2} = sum_{j<=k} t_j (t_j = D_j c_j forward, c_j adjoint) are zero at
+// both ends (the projection makes the terms sum to zero), so each face's
+// flux is taken from whichever end carries less weight: the bottom-up sum,
+// or minus the top-down sum of the levels above.  Equal in exact
+// arithmetic; in FP64 it keeps the rounding of the long sums out of the
+// faces near the top, where the level differences F / f_{k+1/2} amplify it
+// (f is small there on stretched grids with decaying density).  Then
+// x_{k+1} = x_k + F_{k+1/2} / f_{k+1/2}, x_0 = 0, and the gauge (forward:
+// zero plain mean over levels; adjoint: sum_k D_k x_k = 0).
+__device__ inline void mean_column_fp64(int nz, int nx, int ny, int adjoint,
+                                        const double *f, const double *D, const double *sS,
+                                        double *xr, double *xi, int stride)
+{
+    const double on = 1.0 / ((double)nx * (double)ny);
+    double num = 0.0, den = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        const double w = adjoint ? 1.0 : D[k];
+        num += w * sS[k];
+        den += w;
+    }
+    const double M = num / den;
+    double a = 0.0;
+    for (int k = nz - 1; k >= 0; --k) {
+        xi[(size_t)k * stride] = a; // sum of the terms above level k
+        const double c = (sS[k] - M) * on;
+        a += adjoint ? c : D[k] * c;
+    }
+    double P = 0.0, wlo = 0.0, x = 0.0;
+    xr[0] = 0.0;
+    for (int k = 0; k + 1 < nz; ++k) {
+        const double c = (sS[k] - M) * on;
+        P += adjoint ? c : D[k] * c;
+        wlo += adjoint ? 1.0 : D[k];
+        const double F = wlo <= den - wlo ? P : -xi[(size_t)k * stride];
+        x += F / f[k + 1];
+        xr[(size_t)(k + 1) * stride] = x;
+    }
+    double acc = 0.0, wsum = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        const double wk = adjoint ? D[k] : 1.0;
+        acc += wk * xr[(size_t)k * stride];
+        wsum += wk;
+    }
+    const double shift = acc / wsum;
+    for (int k = 0; k < nz; ++k) {
+        xr[(size_t)k * stride] -= shift;
+        xi[(size_t)k * stride] = 0.0;
+    }
+}
+
 // ----------------------------------------------------------- FP64 columns, compact
 // One lane per task, FP64, with short code: the level loop is unrolled by U
 // only, the next U levels' loads are issued before the current U levels are
@@ -818,37 +874,8 @@ __device__ void special_seq_tile(cx_t<T> *__restrict__ spec, int nx, int ny, int
         }
     }
 
-    // ---- the mean column: level means minus mu (forward: D-weighted mean;
-    // adjoint: plain mean), V x = c by flux prefix sums, then the gauge
-    // (forward: zero plain mean; adjoint: sum_k D_k x_k = 0).  Stored into the
-    // A workspace as final values.
-    if (mean) {
-        const double on = 1.0 / ((double)nx * (double)ny);
-        double num = 0.0, den = 0.0, tot = 0.0;
-        for (int k = 0; k < nz; ++k) {
-            num += D[k] * sS[k];
-            den += D[k];
-            tot += sS[k];
-        }
-        const double mu = adjoint ? tot * on / (double)nz : num * on / den;
-        double F = 0.0, x = 0.0, acc = 0.0, wsum = 0.0;
-        for (int k = 0; k < nz; ++k) {
-            if (k > 0) {
-                const double c = sS[k - 1] * on - mu;
-                F += adjoint ? c : D[k - 1] * c;
-                x += F / f[k];
-            }
-            yar[k * st] = x;
-            const double wk = adjoint ? D[k] : 1.0;
-            acc += wk * x;
-            wsum += wk;
-        }
-        const double shift = acc / wsum;
-        for (int k = 0; k < nz; ++k) {
-            yar[k * st] -= shift;
-            yai[k * st] = 0.0;
-        }
-    }
+    // ---- the mean column, stored into the A workspace as final values
+    if (mean) mean_column_fp64(nz, nx, ny, adjoint, f, D, sS, yar, yai, (int)st);
 
     // ---- backward substitution (loads of the next U levels prefetched)
     double xra = 0.0, xia = 0.0, xrb = 0.0, xib = 0.0;

@@ -451,6 +451,171 @@ __global__ __launch_bounds__(64) void k_special_seq(
                            blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// LDS-staged form of the FP64 column tasks.  A block takes G consecutive
+// tasks: it loads every level of their columns into LDS in one batch, runs
+// the eliminations of special_seq_tile from LDS -- the A and B systems of a
+// packed-row pair on two lanes, a near-singular column on one -- with the
+// eliminated values and reciprocal pivots kept in LDS instead of the HBM
+// workspace, and stores every level in one batch.  Per system the
+// arithmetic and its order are those of special_seq_tile.  The few lanes of
+// the sweeps wait on LDS rather than on HBM round trips, which matters
+// because the kernel runs beside the main column kernel while that one
+// saturates memory.
+// LDS: [f (nz+1) | D | rs | os | sS (nz each) | pad] doubles, then
+// y [nz][2][G] double2, pivots [nz][2][G] double, input [nz][2][G] complex T,
+// columns [2][G] int (index 0: Z_ky / the column, 1: Z_-ky / the column).
+template <typename T>
+__global__ __launch_bounds__(256) void k_special_lds(
+    cx_t<T> *__restrict__ spec, int nx, int ny, int nz, int adjoint, const int *__restrict__ mlist,
+    int nmask, const double *__restrict__ S, const double *__restrict__ ax,
+    const double *__restrict__ ay, const double *__restrict__ fg, const double *__restrict__ Dg,
+    const double *__restrict__ rsg, const double *__restrict__ osg, int G)
+{
+    using C = cx_t<T>;
+    __builtin_amdgcn_s_setprio(3);
+    extern __shared__ __align__(16) double sm[];
+    const int L = nx / 2, npair = ny / 2 + 1, ntask = npair + nmask;
+    const size_t lvl = (size_t)L * ny;
+    const int ntab = 5 * nz + 1 + ((5 * nz + 1) & 1);
+    double *f = sm, *D = f + nz + 1, *rs = D + nz, *os = rs + nz, *sS = os + nz;
+    double2 *ys = reinterpret_cast<double2 *>(sm + ntab);
+    double *gs = reinterpret_cast<double *>(ys + (size_t)nz * 2 * G);
+    C *zin = reinterpret_cast<C *>(gs + (size_t)nz * 2 * G);
+    int *scol = reinterpret_cast<int *>(zin + (size_t)nz * 2 * G);
+    const int t0 = blockIdx.x * G;
+
+    for (int i = threadIdx.x; i <= nz; i += blockDim.x) {
+        f[i] = fg[i];
+        if (i < nz) {
+            D[i] = Dg[i];
+            rs[i] = rsg[i];
+            os[i] = osg ? osg[i] : 1.0;
+            sS[i] = S[i];
+        }
+    }
+    if (threadIdx.x < 2 * G) {
+        const int g = threadIdx.x % G, which = threadIdx.x / G;
+        const int t = min(t0 + g, ntask - 1);
+        scol[threadIdx.x] = t < npair ? (which ? (ny - t) % ny : t) : mlist[t - npair];
+    }
+    __syncthreads();
+
+    // one batch of loads: UNR per thread in flight before the first is used;
+    // indices past the end are clamped (their values are never used)
+    constexpr int UNR = 8;
+    const int nload = nz * 2 * G;
+    for (int base = 0; base < nload; base += UNR * (int)blockDim.x) {
+        C v[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int i = min(base + u * (int)blockDim.x + (int)threadIdx.x, nload - 1);
+            const int g = i % G, r = i / G;
+            v[u] = spec[(size_t)(r >> 1) * lvl + scol[(r & 1) * G + g]];
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int i = base + u * (int)blockDim.x + (int)threadIdx.x;
+            if (i < nload) zin[i] = v[u];
+        }
+    }
+    __syncthreads();
+
+    // the sweeps: lanes [0, 2G), two per task (pair: A and B; a
+    // near-singular column: one); the mean column (task 0's A) runs on the
+    // block's last thread, in another wave, so the wave of the sweeps does
+    // not execute its serial loops as well
+    if ((int)threadIdx.x < 2 * G) {
+        const int g = threadIdx.x >> 1, sys = threadIdx.x & 1, t = t0 + g;
+        const bool pair = t < npair;
+        if (t < ntask && (sys == 0 || pair) && !(pair && t == 0 && sys == 0)) {
+            double s;
+            if (pair) {
+                s = sys ? ax[L] + ay[t] : ay[t];
+            } else {
+                const int c = scol[g], kx = c / ny, ky = c - kx * ny;
+                s = ax[kx] + ay[ky];
+            }
+            // forward elimination (dominance-excess pivots)
+            double q = 0.0, gp = 0.0, yr = 0.0, yi = 0.0;
+#pragma unroll 4
+            for (int k = 0; k < nz; ++k) {
+                const C z0 = zin[(k * 2) * G + g], z1 = zin[(k * 2 + 1) * G + g];
+                double ar, ai;
+                if (pair) { // A = (Z + conj Zm)/2, B = (Z - conj Zm)/(2i)
+                    const double zr = z0.x, zi = z0.y, mr = z1.x, mi = -(double)z1.y;
+                    if (sys == 0) {
+                        ar = 0.5 * (zr + mr);
+                        ai = 0.5 * (zi + mi);
+                    } else {
+                        ar = 0.5 * (zi - mi);
+                        ai = -0.5 * (zr - mr);
+                    }
+                } else {
+                    ar = z0.x;
+                    ai = z0.y;
+                }
+                const double fp = f[k], fn = f[k + 1], r = rs[k];
+                const double e = s * D[k] + fp * q;
+                const double gi = 1.0 / (e + fn);
+                const double c = fp * gp;
+                yr = r * ar + c * yr;
+                yi = r * ai + c * yi;
+                ys[(k * 2 + sys) * G + g] = double2{yr, yi};
+                gs[(k * 2 + sys) * G + g] = gi;
+                q = e * gi;
+                gp = gi;
+            }
+            // backward substitution, in place
+            double xr = 0.0, xi = 0.0;
+#pragma unroll 4
+            for (int k = nz - 1; k >= 0; --k) {
+                const double2 y = ys[(k * 2 + sys) * G + g];
+                const double gi = gs[(k * 2 + sys) * G + g], fn = f[k + 1];
+                xr = gi * (y.x + fn * xr);
+                xi = gi * (y.y + fn * xi);
+                ys[(k * 2 + sys) * G + g] = double2{xr, xi};
+            }
+        }
+    }
+    if (t0 == 0 && threadIdx.x == blockDim.x - 1) {
+        double *base = reinterpret_cast<double *>(ys);
+        mean_column_fp64(nz, nx, ny, adjoint, f, D, sS, base, base + 1, 4 * G);
+    }
+    __syncthreads();
+
+    // one batch of stores: repack a pair, Z'_ky = A' + i B',
+    // Z'_-ky = conj A' + i conj B'; a near-singular column as it is
+    const int nst = nz * G;
+    for (int i = threadIdx.x; i < nst; i += blockDim.x) {
+        const int g = i % G, k = i / G, t = t0 + g;
+        if (t >= ntask) continue;
+        const double o = os[k];
+        const double2 A = ys[(k * 2) * G + g];
+        const size_t base = (size_t)k * lvl;
+        if (t < npair) {
+            const double2 B = ys[(k * 2 + 1) * G + g];
+            const double Ar = o * A.x, Ai = o * A.y, Br = o * B.x, Bi = o * B.y;
+            const int i0 = scol[g], i1 = scol[G + g];
+            spec[base + i0] = C{(T)(Ar - Bi), (T)(Ai + Br)};
+            if (i1 != i0) spec[base + i1] = C{(T)(Ar + Bi), (T)(Br - Ai)};
+        } else {
+            spec[base + scol[g]] = C{(T)(o * A.x), (T)(o * A.y)};
+        }
+    }
+}
+
+// Tasks per block of k_special_lds: as many as fit in 64 KiB of LDS (at most
+// 64), and the block's LDS bytes for them.
+template <typename T> static int special_lds_tasks(int nz, size_t *bytes)
+{
+    const size_t tab = 8 * (size_t)(5 * nz + 2);
+    const size_t per = 2 * (size_t)nz * (16 + 8 + sizeof(cx_t<T>)) + 2 * sizeof(int);
+    int G = (int)((65536 - tab) / per);
+    G = std::max(1, std::min(64, G));
+    *bytes = tab + (size_t)G * per;
+    return G;
+}
+
 // ----------------------------------------------------------- level sums
 __global__ __launch_bounds__(256) void k_level_sums(const double *__restrict__ rowsum,
                                                     double *__restrict__ S, int ny)
@@ -698,18 +863,27 @@ template hipError_t launch_columns_impl<double>(cx_t<double> *, int, int, int, i
                                                 int);
 
 // FP64 columns: the packed kx = 0 row, the mean column and the near-singular
-// columns, one lane per task (k_special_seq).
+// columns; parallel = 0: one lane per task through the HBM workspace
+// (k_special_seq), else staged in LDS (k_special_lds).
 template <typename T>
 hipError_t launch_special(cx_t<T> *spec, int nx, int ny, int nz, int adjoint, const int *mlist,
                           int nmask, const double *S, double *ws, const Tables<double> &tb64,
                           hipStream_t st, int parallel)
 {
-    (void)parallel;
     const int ntask = ny / 2 + 1 + nmask;
+    const double *rs = adjoint ? tb64.rs_adj : tb64.rs_fwd;
+    const double *os = adjoint ? tb64.os_adj : nullptr;
+    if (parallel) {
+        size_t bytes = 0;
+        const int G = special_lds_tasks<T>(nz, &bytes);
+        hipLaunchKernelGGL(k_special_lds<T>, dim3((ntask + G - 1) / G), dim3(256), bytes, st,
+                           spec, nx, ny, nz, adjoint, mlist, nmask, S, tb64.ax, tb64.ay, tb64.f,
+                           tb64.D, rs, os, G);
+        return hipGetLastError();
+    }
     const int grid = (ntask + 63) / 64;
     hipLaunchKernelGGL((k_special_seq<T, 16>), dim3(grid), dim3(64), 0, st, spec, nx, ny, nz,
-                       adjoint, mlist, nmask, S, ws, tb64.ax, tb64.ay, tb64.f, tb64.D,
-                       adjoint ? tb64.rs_adj : tb64.rs_fwd, adjoint ? tb64.os_adj : nullptr);
+                       adjoint, mlist, nmask, S, ws, tb64.ax, tb64.ay, tb64.f, tb64.D, rs, os);
     return hipGetLastError();
 }
 

@@ -497,3 +497,45 @@ def test_autotune_and_cache_file(tmp_path):
     path = tmp_path / "cache.txt"
     tune_cache_save(str(path))
     assert " %d %d %d 1 " % (nx, ny, nz) in path.read_text()
+
+
+SPECIAL_SHAPES = [(128, 64, 96), (20, 64, 128), (5, 12, 18), (1, 8, 8), (256, 8, 8),
+                  (33, 1, 16), (16, 96, 64)]
+
+
+@pytest.mark.parametrize("shape", SPECIAL_SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_r2"])
+def test_fp64_column_kernels_agree(tmp_path, precision, shape):
+    """The two FP64-column kernels (one lane per task through the HBM
+    workspace; staged in LDS, several tasks per block), forced through the
+    tune cache: the same per-system arithmetic, so the same solution up to
+    FP64 rounding, and each against the oracle (forward and adjoint)."""
+    from paper_2010_14132_amd.binding import PRECISIONS, tune_cache_load
+    nz, ny, nx = shape
+    announce("FP64-column kernels %s %s" % (precision, shape))
+    g = stretched(nx, ny, nz, seed=41 + nz)
+    b = np.random.default_rng(43).standard_normal(shape) + 0.3
+    if precision != "fp64":
+        b = b.astype(np.float32).astype(np.float64)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    tol = TOL64 if precision == "fp64" else TOL32
+    ref = oracle.solve(b, g.dx, g.dy, g.dz, g.rho)
+    lref = oracle.solve_adjoint(b, g.dx, g.dy, g.dz, g.rho)
+    sols = []
+    for spv in (0, 1):
+        f = tmp_path / ("tune%d.txt" % spv)
+        f.write_text("%s %d %d %d %d 1 1 3 1 1 1 %d\n"
+                     % (_arch(), nx, ny, nz, PRECISIONS[precision], spv))
+        tune_cache_load(str(f))
+        plan = make_plan(g, precision)
+        plan.autotune()
+        assert plan.info()["special_variant"] == spv
+        p = plan.solve(torch.from_numpy(b).to("cuda", dt)).double().cpu().numpy()
+        lam = plan.solve_adjoint(torch.from_numpy(b).to("cuda", dt)).double().cpu().numpy()
+        plan.close()
+        assert relmax(p, ref) < tol
+        assert relmax(lam, lref) < tol
+        sols.append((p, lam))
+    print("bit-equal: %s" % (np.array_equal(sols[0][0], sols[1][0])
+                             and np.array_equal(sols[0][1], sols[1][1])))
+    assert relmax(sols[1][0], sols[0][0]) < (1e-14 if precision == "fp64" else 1e-6)

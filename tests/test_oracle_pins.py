@@ -348,3 +348,56 @@ def test_p12_euler_identity_and_fd():
         Lm = np.vdot(w, oracle.solve(b, 50.0, 50.0, dz, rm))
         fd = (Lp - Lm) / (2 * h * rho[k])
         assert abs(fd - g[k]) < 1e-6 * np.abs(g).max()
+
+
+# ---------------------------------------------------------------- mean column, exact arithmetic
+def _exact_level_means(b, dz, rho, nx, ny, adjoint):
+    """Level means of S b (or S^T w) in exact rational arithmetic, from the
+    definition of the (0,0) mode: projected level sums, fluxes as prefix
+    sums over levels (zero at the bottom), level differences flux / f, and
+    the gauge (plain zero mean; adjoint: D-weighted, output times D)."""
+    from fractions import Fraction as Fr
+    nz = b.shape[0]
+    N = nx * ny
+    S = [sum(Fr(float(v)) for v in b[k].ravel()) for k in range(nz)]
+    dzf = [Fr(float(v)) for v in dz]
+    rf = [Fr(float(v)) for v in rho]
+    D = [rf[k] * dzf[k] for k in range(nz)]
+    f = [Fr(0)] * (nz + 1)
+    for k in range(nz - 1):
+        f[k + 1] = (rf[k] + rf[k + 1]) / 2 / ((dzf[k] + dzf[k + 1]) / 2)
+    m = sum(S) / (N * nz) if adjoint else sum(D[k] * S[k] for k in range(nz)) / (N * sum(D))
+    c = [S[k] - N * m for k in range(nz)]
+    if adjoint:
+        c = [c[k] / D[k] for k in range(nz)]
+    x, F = [Fr(0)], Fr(0)
+    for k in range(nz - 1):
+        F += D[k] * c[k]
+        x.append(x[-1] + F / f[k + 1])
+    w = D if adjoint else [Fr(1)] * nz
+    g = sum(w[k] * x[k] for k in range(nz)) / sum(w)
+    out = [(x[k] - g) * (D[k] if adjoint else 1) / N for k in range(nz)]
+    return np.array([float(v) for v in out])
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+@pytest.mark.parametrize("nz,stretch,seed", [(128, 1.03, 1), (96, 1.05, 2), (40, 1.1, 3)])
+def test_mean_column_exact_arithmetic(nz, stretch, seed, adjoint):
+    """Tall stretched grids with jittered thicknesses and densities, where
+    the flux prefix sums are divided by very small f near the top: the
+    oracle's level means against the exact rational solution of the (0,0)
+    mode, relative to max |p|.  An incompatible right-hand side (offset)
+    makes the projection matter."""
+    nx, ny = 16, 12
+    r = np.random.default_rng(seed)
+    g = wl.stretched_grid(nx, ny, nz, stretch=stretch)
+    dz = g.dz * r.uniform(0.7, 1.3, nz)
+    rho = g.rho * r.uniform(0.8, 1.2, nz)
+    b = r.standard_normal((nz, ny, nx)) + 0.3
+    if adjoint:
+        p = oracle.solve_adjoint(b, g.dx, 37.0, dz, rho)
+    else:
+        p = oracle.solve(b, g.dx, 37.0, dz, rho)
+    want = _exact_level_means(b, dz, rho, nx, ny, adjoint)
+    got = p.mean(axis=(1, 2))
+    assert np.abs(got - want).max() < 1e-14 * np.abs(p).max()
