@@ -324,6 +324,43 @@ def config_forms(prob, forms, steps, warmup, oracle_ref=True):
     return res
 
 
+def config_cg(prob):
+    """The paper's Table 1 on this hardware: matrix-free CG (Jacobi and no
+    preconditioner, FP64) terminated at relative residuals 1e-2 ... 1e-8,
+    iterations, time per solve (host clock around the call, which reads the
+    convergence flag every 16 iterations) and the mean difference from the
+    FP64 direct solve, relative to the direct solution's mean magnitude;
+    the direct solve's time beside it."""
+    import torch
+    from paper_2010_14132_amd import CGSolver, Plan
+    g = prob.grid
+    b = torch.from_numpy(prob.rhs).cuda()
+    plan = Plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.rho, precision="fp64")
+    plan.autotune(reps=5)
+    direct = plan.solve(b)
+    d_ms = time_calls(lambda: plan.solve(b, out=direct), 50, 5)
+    dmean = direct.abs().mean().item()
+    res = {"direct_fp64_ms": d_ms, "ladder": []}
+    for precond in ("jacobi", "none"):
+        s = CGSolver(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.rho, precond=precond)
+        s.solve(b, rtol=1e-2)  # warm-up
+        for rtol in (1e-2, 1e-4, 1e-6, 1e-8):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, it, rel = s.solve(b, rtol=rtol, max_iter=100000)
+            ms = (time.perf_counter() - t0) * 1e3
+            res["ladder"].append({
+                "precond": precond, "rtol": rtol, "iterations": it, "ms": ms,
+                "ms_per_iteration": ms / max(it, 1),
+                "mean_diff_vs_direct": (x - direct).abs().mean().item() / dmean,
+                "max_diff_vs_direct": (x - direct).abs().max().item() / direct.abs().max().item(),
+                "iteration_bytes": 88 * g.points,
+                "iteration_gbs": 88 * g.points * max(it, 1) / (ms * 1e-3) / 1e9})
+        s.close()
+    plan.close()
+    return res
+
+
 def config_differentiation(steps, warmup):
     """512^2 x 128 differentiation workload: forward solve, adjoint solve and
     density gradient (one differentiation step = all three), FP32 form with
@@ -627,6 +664,8 @@ def main():
             "workload": "256x256x64 stretched grid, rho(z), smooth RHS (seed 1)",
             "forms": config_forms(wl2.plain_256(), ["fp64", "fp32", "fp32_r2", "fp32_r1"],
                                   max(100, args.steps), args.warmup)}
+        print("bench: 256x256x64 matrix-free CG ladder", file=sys.stderr, flush=True)
+        configs["plain_256x256x64"]["cg_table1"] = config_cg(wl2.plain_256())
         print("bench: 512x512x128 differentiation", file=sys.stderr, flush=True)
         configs["differentiation_512x512x128"] = config_differentiation(args.steps, args.warmup)
         print("bench: 48-problem uneven batch", file=sys.stderr, flush=True)

@@ -271,6 +271,37 @@ int ps_batch_query(const ps_batch *batch, int *count, int *tiles, int *grid, int
 int ps_batch_status(ps_batch *batch);
 int ps_batch_destroy(ps_batch *batch);
 
+/* ---- matrix-free conjugate gradients -----------------------------------
+ * The paper's iterative alternative to the direct solve (Section 2.2: a
+ * bespoke matrix-free Krylov solver with a hard-coded operator, several
+ * inner products reduced together, terminated on the relative residual;
+ * Table 1 compares its accuracy and cost with the FFT solve), on the same
+ * discrete operator A and the same bordered-system result as ps_solve.
+ * CG runs on M = -D A (D_k = rho_k dz_k), which is symmetric positive
+ * semi-definite, with the right-hand side -D (b - mu), mu the D-weighted
+ * mean of b; the result is shifted to zero mean.  FP64 throughout. */
+typedef struct ps_cg ps_cg;
+enum { PS_CG_NONE = 0, PS_CG_JACOBI = 1 }; /* preconditioner: none, diagonal of M */
+/* nx, ny, nz >= 1 (fewer than 2^31 points), dx, dy > 0, dz and rho host
+ * arrays of nz values > 0 (copied).  Allocates three FP64 fields of
+ * workspace (synchronises).  Errors: PS_EINVAL, PS_EUNSUPPORTED, PS_ENOMEM,
+ * PS_EHIP. */
+int ps_cg_create(ps_cg **out, int nx, int ny, int nz, double dx, double dy, const double *dz,
+                 const double *rho, int precond, void *stream);
+/* Solve from the initial guess in x (device, [nz][ny][nx] doubles, read
+ * and overwritten; the previous timestep's pressure is a warm start) for
+ * rhs (device, not aliasing x) until |r| <= rtol |-D (b - mu)| (2-norms of
+ * the residual of the symmetrised system, as updated by the recurrence) or
+ * max_iter iterations.  iters and rel_res (host, may be NULL) receive the
+ * iterations done and the final relative residual.  Synchronises: the host
+ * reads the device-side convergence flag every 16 iterations, so this call
+ * cannot be captured into a graph. */
+int ps_cg_solve(ps_cg *cg, const double *rhs, double *x, double rtol, int max_iter, int *iters,
+                double *rel_res);
+int ps_cg_set_stream(ps_cg *cg, void *stream);
+size_t ps_cg_workspace_bytes(const ps_cg *cg);
+int ps_cg_destroy(ps_cg *cg);
+
 const char *ps_status_string(int status);
 const char *ps_last_error(void);
 

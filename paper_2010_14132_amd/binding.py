@@ -72,6 +72,13 @@ SIGNATURES = {
     "ps_plan_profile_report": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                               ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_int)]),
+    "ps_cg_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_double, ctypes.c_double, _D, _D, ctypes.c_int, _vp]),
+    "ps_cg_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _I,
+                                   ctypes.POINTER(ctypes.c_double)]),
+    "ps_cg_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "ps_cg_workspace_bytes": (ctypes.c_size_t, [_vp]),
+    "ps_cg_destroy": (ctypes.c_int, [_vp]),
     "ps_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ps_last_error": (ctypes.c_char_p, []),
 }
@@ -334,6 +341,61 @@ def poisson_solve(b, rho, plan: Plan):
     if _poisson is None:
         _poisson = _solve_fn()
     return _poisson.apply(b, rho, plan)
+
+
+class CGSolver:
+    """Matrix-free conjugate gradients on the same operator as Plan (the C
+    ABI's ps_cg), FP64: preconditioner "none" or "jacobi".  solve() starts
+    from x (or zeros) and returns (x, iterations, relative residual)."""
+
+    PRECOND = {"none": 0, "jacobi": 1}
+
+    def __init__(self, nx, ny, nz, dx, dy, dz, rho, precond="jacobi"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the pressure-solve library needs a GPU (no CPU fallback)")
+        lib = load()
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        dz = np.ascontiguousarray(dz, dtype=np.float64)
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        h = _vp()
+        check(lib.ps_cg_create(ctypes.byref(h), self.nx, self.ny, self.nz, float(dx), float(dy),
+                               _dptr(dz), _dptr(rho), self.PRECOND[precond], _stream_handle()),
+              "ps_cg_create")
+        self._h = h
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    def solve(self, rhs, x=None, rtol=1e-8, max_iter=10000):
+        import torch
+        for t, nm in ((rhs, "rhs"),) + (((x, "x"),) if x is not None else ()):
+            if t.dtype != torch.float64 or tuple(t.shape) != self.shape or not t.is_contiguous() \
+                    or t.device != self.device:
+                raise ValueError("%s must be a contiguous float64 tensor of shape %s on %s"
+                                 % (nm, self.shape, self.device))
+        if x is None:
+            x = torch.zeros_like(rhs)
+        it = ctypes.c_int()
+        rr = ctypes.c_double()
+        lib = load()
+        check(lib.ps_cg_set_stream(self._h, _stream_handle()), "ps_cg_set_stream")
+        check(lib.ps_cg_solve(self._h, _vp(rhs.data_ptr()), _vp(x.data_ptr()), float(rtol),
+                              int(max_iter), ctypes.byref(it), ctypes.byref(rr)), "ps_cg_solve")
+        return x, it.value, rr.value
+
+    def close(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h is not None and h.value and _lib is not None:
+            _lib.ps_cg_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def tune_cache_save(path: str):
