@@ -324,6 +324,50 @@ def config_forms(prob, forms, steps, warmup, oracle_ref=True):
     return res
 
 
+def config_monc_layout(prob, steps, warmup):
+    """The headline workload with its fields in MONC's z-fastest layout
+    ([nx][ny][nz]): ps_solve_zyx (transposes inside the x passes) against the
+    level-major solve preceded and followed by explicit layout copies (what
+    a caller would otherwise run), FP32 with the in-register refinement,
+    autotuned; per-kernel event times of the z-fastest x passes."""
+    import torch
+    from paper_2010_14132_amd import Plan
+    g = prob.grid
+    plan = Plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.rho, precision="fp32_r2")
+    plan.autotune(reps=5)
+    b = torch.from_numpy(prob.rhs_as("f32")).cuda()
+    bz = b.permute(2, 1, 0).contiguous()
+    pz = torch.empty_like(bz)
+    p = torch.empty_like(b)
+    zyx = time_calls(lambda: plan.solve_zyx(bz, out=pz), steps, warmup)
+
+    def unfused():
+        bb = bz.permute(2, 1, 0).contiguous()
+        plan.solve(bb, out=p)
+        pz.copy_(p.permute(2, 1, 0))
+
+    unf = time_calls(unfused, steps, warmup)
+    lm = time_calls(lambda: plan.solve(b, out=p), steps, warmup)
+    plan.profile(True)
+    for _ in range(steps):
+        plan.solve_zyx(bz, out=pz)
+    kern = plan.profile_report()
+    plan.profile(False)
+    N = g.points
+    xk = {}
+    for name in ("fwd_x", "inv_x"):
+        if name in kern:
+            tot, n = kern[name]
+            ms = tot / steps
+            xk[name] = {"ms_per_solve": ms, "gbs": 8.0 * N / (ms * 1e-3) / 1e9}
+    res = {"zyx_ms_per_solve": zyx, "solves_per_s": 1e3 / zyx, "mpts_per_s": N / zyx / 1e3,
+           "level_major_ms": lm, "level_major_with_two_transposes_ms": unf,
+           "speedup_vs_transposes": unf / zyx, "zyx_kc": plan.info()["zyx_kc"],
+           "x_passes": xk}
+    plan.close()
+    return res
+
+
 def config_cg(prob):
     """The paper's Table 1 on this hardware: matrix-free CG (Jacobi and no
     preconditioner, FP64) terminated at relative residuals 1e-2 ... 1e-8,
@@ -641,6 +685,9 @@ def main():
         line["device_copy_gbs"] = copy_gbs
     if "fp64" in results and args.precision != "fp64":
         line["speedup_vs_fp64"] = results["fp64"]["ms_per_solve"] / results[args.precision]["ms_per_solve"]
+    if not args.no_configs:
+        print("bench: MONC layout", file=sys.stderr, flush=True)
+        line["monc_layout"] = config_monc_layout(prob, args.steps, args.warmup)
     line["whole_solve_hbm"] = results[args.precision]["whole_solve"]
     line["timing"] = {k: results[args.precision][k] for k in ("median_ms", "min_ms", "mean_ms",
                                                                "reps")}

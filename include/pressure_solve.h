@@ -123,6 +123,14 @@ int ps_plan_set_coeffs(ps_plan *plan, const double *rho);
  * stream and replay it with the same pointers. */
 int ps_solve(ps_plan *plan, const void *rhs, void *p);
 
+/* ps_solve (adjoint = 0) or ps_solve_adjoint (adjoint != 0) for fields in
+ * MONC's own layout p%data(z,y,x) (Section 2.2's Fortran field, z fastest):
+ * element (i, j, k) at (i ny + j) nz + k, element type as for ps_solve.  The
+ * transposes between the columns and the transform rows are done in LDS
+ * inside the two x passes (no extra pass over HBM); the rest is ps_solve's.
+ * rhs and p may alias.  PS_FP32_R1 plans give PS_EUNSUPPORTED. */
+int ps_solve_zyx(ps_plan *plan, const void *rhs, void *p, int adjoint);
+
 /* Adjoint solve: grhs = S^T gp, the lambda-block of
  * [[A^T,1],[1^T,0]] [lambda; nu] = [gp; 0] -- the gradient of <gp, p> with
  * respect to rhs.  Same layout and aliasing rules as ps_solve (refinement
@@ -161,6 +169,8 @@ typedef struct ps_plan_info {
     int fft_variant_xi;   /* ... and backward x */
     int special_variant;  /* FP64-column kernel: 0 one lane per task through an HBM
                              workspace, 1 staged in LDS */
+    int zyx_kc;           /* z-fastest-layout x passes: levels per tile (capped by the
+                             tile's rows) */
 } ps_plan_info;
 
 int ps_plan_query(const ps_plan *plan, ps_plan_info *info);
@@ -178,7 +188,9 @@ int ps_plan_query(const ps_plan *plan, ps_plan_info *info);
  * main column kernel, chunks the number of kx ranges the y / column / y
  * passes are taken in, both defaulting to 1; xi_variant the backward x
  * pass's, defaulting to x_variant; special_variant the FP64-column kernel's
- * (0 or 1), defaulting to 1).
+ * (0 or 1), defaulting to 1; zyx_kc the levels per tile of the z-fastest
+ * layout's x passes (1..256), defaulting to 64; it is timed with
+ * ps_solve_zyx).
  * Synchronises. */
 int ps_plan_autotune(ps_plan *plan, int reps);
 int ps_tune_cache_save(const char *path);

@@ -35,7 +35,8 @@ class PlanInfo(ctypes.Structure):
                 ("tau", ctypes.c_double), ("fft_variant_x", ctypes.c_int),
                 ("fft_variant_y", ctypes.c_int), ("spectrum_elems", ctypes.c_size_t),
                 ("column_variant", ctypes.c_int), ("chunks", ctypes.c_int),
-                ("fft_variant_xi", ctypes.c_int), ("special_variant", ctypes.c_int)]
+                ("fft_variant_xi", ctypes.c_int), ("special_variant", ctypes.c_int),
+                ("zyx_kc", ctypes.c_int)]
 
 
 # name -> (restype, argtypes); mirrors include/pressure_solve.h
@@ -48,6 +49,7 @@ SIGNATURES = {
     "ps_plan_set_coeffs": (ctypes.c_int, [_vp, _D]),
     "ps_solve": (ctypes.c_int, [_vp, _vp, _vp]),
     "ps_solve_adjoint": (ctypes.c_int, [_vp, _vp, _vp]),
+    "ps_solve_zyx": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
     "ps_grad_coeffs": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "ps_grad_coeffs_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "ps_workspace_bytes": (ctypes.c_size_t, [_vp]),
@@ -190,6 +192,27 @@ class Plan:
         self._sync_stream()
         check(load().ps_solve_adjoint(self._h, _vp(gp.data_ptr()), _vp(out.data_ptr())),
               "ps_solve_adjoint")
+        return out
+
+    @property
+    def shape_zyx(self):
+        """MONC's p%data(z,y,x) as a C array: [nx][ny][nz], z fastest."""
+        return (self.nx, self.ny, self.nz)
+
+    def solve_zyx(self, rhs, out=None, adjoint=False):
+        """ps_solve / ps_solve_adjoint for fields in MONC's z-fastest layout
+        (tensors of shape [nx][ny][nz])."""
+        import torch
+        for t, nm in ((rhs, "rhs"),) + (((out, "out"),) if out is not None else ()):
+            if t.device != self.device or t.dtype != self.dtype \
+                    or tuple(t.shape) != self.shape_zyx or not t.is_contiguous():
+                raise ValueError("%s must be a contiguous %s tensor of shape %s on %s"
+                                 % (nm, self.dtype, self.shape_zyx, self.device))
+        if out is None:
+            out = torch.empty(self.shape_zyx, dtype=self.dtype, device=self.device)
+        self._sync_stream()
+        check(load().ps_solve_zyx(self._h, _vp(rhs.data_ptr()), _vp(out.data_ptr()),
+                                  int(bool(adjoint))), "ps_solve_zyx")
         return out
 
     def grad_coeffs(self, lam, p):

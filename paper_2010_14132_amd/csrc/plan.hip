@@ -490,6 +490,7 @@ extern "C" int ps_plan_query(const ps_plan *p, ps_plan_info *info)
     info->column_variant = p->geom.columns;
     info->chunks = p->geom.special_side ? p->geom.chunks : 1;
     info->special_variant = p->geom.special_variant;
+    info->zyx_kc = p->geom.zyx_kc;
     return PS_OK;
 }
 
@@ -768,6 +769,38 @@ template <typename T> static int run(ps_plan *p, const T *in, T *out, int adjoin
     return PS_OK;
 }
 
+// The solve for fields in the z-fastest (MONC) layout: its own x passes
+// around the shared y / column / y passes.
+template <typename T> static int run_zyx(ps_plan *p, const T *in, T *out, int adjoint)
+{
+    auto *spec = reinterpret_cast<cx_t<T> *>(p->d_spec);
+    const Tables<T> &tb = tables<T>(p);
+    PS_HIP(timed(p, K_FWD_X, [&] {
+        return launch_fwd_x_zyx<T>(in, spec, p->d_rowsum, p->nx, p->ny, p->nz, p->geom.rows_x,
+                                   p->geom.zyx_kc, p->spx, tb, p->stream);
+    }));
+    PS_TRY(middle<T>(p, spec, adjoint, p->precision == PS_FP32_R2));
+    PS_HIP(timed(p, K_INV_X, [&] {
+        return launch_inv_x_zyx<T>(spec, out, p->nx, p->ny, p->nz, p->geom.rows_x,
+                                   p->geom.zyx_kc, p->spx, tb, p->stream);
+    }));
+    return PS_OK;
+}
+
+static int solve_zyx_common(ps_plan *p, const void *in, void *out, int adjoint)
+{
+    if (!p || !in || !out) return fail(PS_EINVAL, "plan, input and output must not be NULL");
+    if (p->precision == PS_FP32_R1)
+        return fail(PS_EUNSUPPORTED, "the z-fastest layout supports PS_FP64, PS_FP32 and PS_FP32_R2");
+    if (p->fp64()) return run_zyx<double>(p, (const double *)in, (double *)out, adjoint != 0);
+    return run_zyx<float>(p, (const float *)in, (float *)out, adjoint != 0);
+}
+
+extern "C" int ps_solve_zyx(ps_plan *p, const void *rhs, void *out, int adjoint)
+{
+    return solve_zyx_common(p, rhs, out, adjoint);
+}
+
 static int solve_common(ps_plan *p, const void *in, void *out, int adjoint)
 {
     if (!p || !in || !out) return fail(PS_EINVAL, "plan, input and output must not be NULL");
@@ -846,14 +879,15 @@ static std::string tune_key(const ps_plan *p)
     return k.str();
 }
 
-static int time_solves(ps_plan *p, const void *in, void *out, int reps, float *ms)
+static int time_solves(ps_plan *p, const void *in, void *out, int reps, float *ms,
+                       int (*solve)(ps_plan *, const void *, void *, int) = solve_common)
 {
     hipEvent_t a, b;
     PS_HIP(hipEventCreate(&a));
     PS_HIP(hipEventCreate(&b));
-    int rc = solve_common(p, in, out, 0); // warm-up
+    int rc = solve(p, in, out, 0); // warm-up
     if (rc == PS_OK && hipEventRecord(a, p->stream) != hipSuccess) rc = PS_EHIP;
-    for (int i = 0; i < reps && rc == PS_OK; ++i) rc = solve_common(p, in, out, 0);
+    for (int i = 0; i < reps && rc == PS_OK; ++i) rc = solve(p, in, out, 0);
     if (rc == PS_OK && hipEventRecord(b, p->stream) != hipSuccess) rc = PS_EHIP;
     if (rc == PS_OK && hipEventSynchronize(b) != hipSuccess) rc = PS_EHIP;
     if (rc == PS_OK && hipEventElapsedTime(ms, a, b) != hipSuccess) rc = PS_EHIP;
@@ -881,6 +915,7 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
             p->geom.special_side = it->second.special_side;
             p->geom.chunks = it->second.chunks;
             p->geom.special_variant = it->second.special_variant;
+            p->geom.zyx_kc = it->second.zyx_kc;
             return PS_OK;
         }
     }
@@ -898,14 +933,15 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
     // Each option is timed in two interleaved rounds (A B C, A B C) and keeps
     // its faster time, so that a slow drift of the clock or a one-off stall
     // does not decide between options a few per cent apart.
-    auto pick = [&](int FftGeom::*knob, const std::vector<int> &opts) {
+    auto pick = [&](int FftGeom::*knob, const std::vector<int> &opts,
+                    int (*solve)(ps_plan *, const void *, void *, int) = solve_common) {
         if (rc != PS_OK || opts.size() < 2) return;
         std::vector<float> best_of(opts.size(), 1e30f);
         for (int round = 0; round < 2; ++round) {
             for (size_t i = 0; i < opts.size(); ++i) {
                 p->geom.*knob = opts[i];
                 float ms = 0.f;
-                rc = time_solves(p, in, out, reps, &ms);
+                rc = time_solves(p, in, out, reps, &ms, solve);
                 if (rc != PS_OK) return;
                 best_of[i] = std::min(best_of[i], ms);
             }
@@ -929,6 +965,7 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
     pick(&FftGeom::special_variant, {0, 1});
     pick(&FftGeom::special_side, {0, 1});
     if (p->geom.special_side) pick(&FftGeom::chunks, {1, 2, 4, 8});
+    if (p->precision != PS_FP32_R1) pick(&FftGeom::zyx_kc, {1, 2, 4, 8, 64}, solve_zyx_common);
     p->prof.on = prof;
     (void)hipStreamSynchronize(p->stream);
     (void)hipFree(in);
@@ -940,9 +977,9 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
 }
 
 // Text format, one line per entry: arch nx ny nz precision variant_x
-// variant_y columns special_side chunks variant_xi special_variant (the last
-// four optional on reading; variant_xi defaults to variant_x,
-// special_variant to 1)
+// variant_y columns special_side chunks variant_xi special_variant zyx_kc
+// (the last five optional on reading; variant_xi defaults to variant_x,
+// special_variant to 1, zyx_kc to 64)
 extern "C" int ps_tune_cache_save(const char *path)
 {
     if (!path) return fail(PS_EINVAL, "path is NULL");
@@ -952,7 +989,8 @@ extern "C" int ps_tune_cache_save(const char *path)
     for (auto &kv : g_tune)
         f << kv.first << ' ' << kv.second.variant_x << ' ' << kv.second.variant_y << ' '
           << kv.second.columns << ' ' << kv.second.special_side << ' ' << kv.second.chunks << ' '
-          << kv.second.variant_xi << ' ' << kv.second.special_variant << '\n';
+          << kv.second.variant_xi << ' ' << kv.second.special_variant << ' '
+          << kv.second.zyx_kc << '\n';
     return f.good() ? PS_OK : fail(PS_EINVAL, "write failed");
 }
 
@@ -966,14 +1004,16 @@ extern "C" int ps_tune_cache_load(const char *path)
     while (std::getline(f, line)) {
         std::istringstream is(line);
         std::string arch;
-        int nx, ny, nz, prec, vx, vy, col, side = 1, chunks = 1, vxi = -1, spv = 1;
+        int nx, ny, nz, prec, vx, vy, col, side = 1, chunks = 1, vxi = -1, spv = 1, zkc = 64;
         if (!(is >> arch >> nx >> ny >> nz >> prec >> vx >> vy >> col)) continue;
         if (!(is >> side)) side = 1;
         if (!(is >> chunks)) chunks = 1;
         if (!(is >> vxi)) vxi = vx;
         if (!(is >> spv)) spv = 1;
+        if (!(is >> zkc)) zkc = 64;
         if (vx < 0 || vx > 4 || vy < 0 || vy > 2 || col < 0 || col > 8 || side < 0 || side > 1 ||
-            chunks < 1 || chunks > 64 || vxi < 0 || vxi > 4 || spv < 0 || spv > 1)
+            chunks < 1 || chunks > 64 || vxi < 0 || vxi > 4 || spv < 0 || spv > 1 || zkc < 1 ||
+            zkc > 256)
             continue;
         std::ostringstream k;
         k << arch << ' ' << nx << ' ' << ny << ' ' << nz << ' ' << prec;
@@ -985,6 +1025,7 @@ extern "C" int ps_tune_cache_load(const char *path)
         g.special_side = side;
         g.chunks = chunks;
         g.special_variant = spv;
+        g.zyx_kc = zkc;
         got[k.str()] = g;
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);

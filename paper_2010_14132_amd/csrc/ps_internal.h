@@ -54,6 +54,7 @@ struct FftGeom {
     int chunks = 1;      // y forward / columns / y backward run in this many kx chunks
     int special_variant = 1; // FP64 columns: 0 one lane per task via the HBM workspace,
                              // 1 staged in LDS (k_special_lds)
+    int zyx_kc = 64;     // z-fastest (MONC) x passes: levels per tile (capped by the tile rows)
 };
 
 struct Launch {
@@ -102,6 +103,17 @@ hipError_t launch_c2r_fast(const cx_t<T> *spec, T *out, int nx, int ny, int nz, 
                            const cx_t<T> *tw4, const cx_t<T> *tws, hipStream_t st, int variant);
 
 hipError_t launch_level_sums(const double *rowsum, double *S, int ny, int nz, hipStream_t st);
+
+// x passes for fields in the z-fastest layout (i ny + j) nz + k (monc.hip):
+// tiles of `rows` rows, kc_pref levels each (capped by rows and nz).
+template <typename T>
+hipError_t launch_fwd_x_zyx(const T *in, cx_t<T> *spec, double *rowsum, int nx, int ny, int nz,
+                            int rows, int kc_pref, const StagePlan &spx, const Tables<T> &tb,
+                            hipStream_t st);
+template <typename T>
+hipError_t launch_inv_x_zyx(const cx_t<T> *spec, T *out, int nx, int ny, int nz, int rows,
+                            int kc_pref, const StagePlan &spx, const Tables<T> &tb,
+                            hipStream_t st);
 
 // Column solves of the rows kx in [kxlo, kxhi) (kx = 0 excluded: the FP64
 // kernel's row).
