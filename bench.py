@@ -368,6 +368,49 @@ def config_monc_layout(prob, steps, warmup):
     return res
 
 
+def config_projection(prob, steps, warmup):
+    """One projection step of the dynamical core on the headline grid
+    (ps_project: divergence inside the forward x pass, solve, gradient
+    correction), FP32 + in-register refinement and FP32 + physical-residual
+    refinement, autotuned; velocities drawn N(0,1) by a seeded GPU generator.
+    Beside it the plain solve on the same plan; per-kernel rates of the
+    fused forward pass (reads u, v, w and writes the spectrum: 4 e bytes per
+    point) and of the correction (reads p, u, v, w, writes u, v, w: 7 e)."""
+    import torch
+    from paper_2010_14132_amd import Plan
+    g = prob.grid
+    N = g.points
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    res = {}
+    for form in ("fp32_r2", "fp32_r1"):
+        plan = Plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.rho, precision=form)
+        plan.autotune(reps=5)
+        u, v, w = (torch.randn((g.nz, g.ny, g.nx), generator=gen, device="cuda")
+                   for _ in range(3))
+        p = torch.empty_like(u)
+        b = torch.from_numpy(prob.rhs_as("f32")).cuda()
+        # repeated projections of the same (already corrected) flow: the
+        # work per step does not depend on the values
+        proj = time_calls(lambda: plan.project(u, v, w, 10.0, out=p, correct=True), steps, warmup)
+        solve = time_calls(lambda: plan.solve(b, out=p), steps, warmup)
+        plan.profile(True)
+        for _ in range(steps):
+            plan.project(u, v, w, 10.0, out=p, correct=True)
+        kern = plan.profile_report()
+        plan.profile(False)
+        kt = {}
+        for name, bpp in (("fwd_x_divergence", 16.0), ("grad_correct", 28.0)):
+            if name in kern:
+                ms = kern[name][0] / steps
+                kt[name] = {"ms_per_step": ms, "alg_bytes_per_point": bpp,
+                            "gbs": bpp * N / (ms * 1e-3) / 1e9}
+        res[form] = {"projection_ms": proj, "steps_per_s": 1e3 / proj,
+                     "mpts_per_s": N / proj / 1e3, "plain_solve_ms": solve, "kernels": kt}
+        plan.close()
+        del u, v, w, p, b
+    return res
+
+
 def config_cg(prob):
     """The paper's Table 1 on this hardware: matrix-free CG (Jacobi and no
     preconditioner, FP64) terminated at relative residuals 1e-2 ... 1e-8,
@@ -688,6 +731,8 @@ def main():
     if not args.no_configs:
         print("bench: MONC layout", file=sys.stderr, flush=True)
         line["monc_layout"] = config_monc_layout(prob, args.steps, args.warmup)
+        print("bench: projection step", file=sys.stderr, flush=True)
+        line["projection_step"] = config_projection(prob, args.steps, args.warmup)
     line["whole_solve_hbm"] = results[args.precision]["whole_solve"]
     line["timing"] = {k: results[args.precision][k] for k in ("median_ms", "min_ms", "mean_ms",
                                                                "reps")}

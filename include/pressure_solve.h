@@ -131,6 +131,27 @@ int ps_solve(ps_plan *plan, const void *rhs, void *p);
  * rhs and p may alias.  PS_FP32_R1 plans give PS_EUNSUPPORTED. */
 int ps_solve_zyx(ps_plan *plan, const void *rhs, void *p, int adjoint);
 
+/* One pressure-projection step of the dynamical core around the solve
+ * (Section 1: the source terms feed the solve, its pressure corrects the
+ * flow).  u, v, w: device [nz][ny][nx] fields of the plan's element type,
+ * the provisional velocity on the staggered grid -- u[k][j][i] on the
+ * x-face between cells i-1 and i, v on the y-face between rows j-1 and j,
+ * w on the face between levels k-1 and k (level 0's w is the bottom
+ * boundary, no flux: neither read nor written); no flux through the top.
+ * Solves A p = div(u, v, w)/dt (p written to the device field p), with
+ *   div = (u_{i+1}-u_i)/dx + (v_{j+1}-v_j)/dy
+ *       + (rho_{k+1/2} w_{k+1} - rho_{k-1/2} w_k)/(rho_k dz_k),
+ * the divergence formed inside the forward x pass (no right-hand-side
+ * field); then, if correct != 0, subtracts dt times the pressure gradient
+ * (p_i-p_{i-1})/dx, (p_j-p_{j-1})/dy, (p_k-p_{k-1})/h_{k-1/2} from u, v and w
+ * in one further pass, after which div(u, v, w) = 0 up to rounding (div of
+ * the gradient is A).  In the PS_FP32_R1 form the refinement's residual
+ * div/dt - A p is formed again from u, v, w and p (FP64 accumulation) inside
+ * the second solve's forward x pass, so it refers to the FP64 divergence.
+ * dt finite and > 0; u, v, w, p distinct.  Asynchronous on the plan's
+ * stream. */
+int ps_project(ps_plan *plan, void *u, void *v, void *w, double dt, void *p, int correct);
+
 /* Adjoint solve: grhs = S^T gp, the lambda-block of
  * [[A^T,1],[1^T,0]] [lambda; nu] = [gp; 0] -- the gradient of <gp, p> with
  * respect to rhs.  Same layout and aliasing rules as ps_solve (refinement

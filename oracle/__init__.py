@@ -54,10 +54,12 @@ def _load():
         lib.oracle_column_solve.argtypes = [i, _D, _D, d, _D, _D, _D, _D]
         lib.oracle_vertical_coefficients.argtypes = [i, _D, _D, _D, _D]
         lib.oracle_num_threads.argtypes = []
+        lib.oracle_divergence.argtypes = grid + [_D, _D, _D, _D]
+        lib.oracle_gradient.argtypes = grid + [_D, _D, _D, _D]
         for fn in (lib.oracle_solve, lib.oracle_solve_adjoint, lib.oracle_apply,
                    lib.oracle_grad_rho, lib.oracle_dft2_forward, lib.oracle_dft2_inverse,
                    lib.oracle_column_solve, lib.oracle_vertical_coefficients,
-                   lib.oracle_num_threads):
+                   lib.oracle_num_threads, lib.oracle_divergence, lib.oracle_gradient):
             fn.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -171,6 +173,28 @@ def vertical_coefficients(dz, rho):
     _check(_load().oracle_vertical_coefficients(nz, _ptr(dz), _ptr(rho), _ptr(f), _ptr(D)),
            "vertical_coefficients")
     return f, D
+
+
+def divergence(u, v, w, dx, dy, dz, rho) -> np.ndarray:
+    """Anelastic divergence of C-grid velocities (see pressure_oracle.c)."""
+    u, v, w = _f64(u), _f64(v), _f64(w)
+    nz, ny, nx = u.shape
+    dz, rho = _grid_args(dx, dy, dz, rho)
+    out = np.empty_like(u)
+    _check(_load().oracle_divergence(nx, ny, nz, float(dx), float(dy), _ptr(dz), _ptr(rho),
+                                     _ptr(u), _ptr(v), _ptr(w), _ptr(out)), "divergence")
+    return out
+
+
+def gradient(p, dx, dy, dz, rho):
+    """(gu, gv, gw): the pressure gradient on the u, v and w faces."""
+    p = _f64(p)
+    nz, ny, nx = p.shape
+    dz, rho = _grid_args(dx, dy, dz, rho)
+    gu, gv, gw = np.empty_like(p), np.empty_like(p), np.empty_like(p)
+    _check(_load().oracle_gradient(nx, ny, nz, float(dx), float(dy), _ptr(dz), _ptr(rho),
+                                   _ptr(p), _ptr(gu), _ptr(gv), _ptr(gw)), "gradient")
+    return gu, gv, gw
 
 
 def num_threads() -> int:

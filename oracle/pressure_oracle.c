@@ -553,6 +553,68 @@ int oracle_solve_adjoint(int nx, int ny, int nz, double dx, double dy,
     return err;
 }
 
+/* The two dynamical-core steps either side of the solve (Section 1: the
+ * source terms feed the pressure solve, whose result corrects the flow).
+ * Velocities on the staggered (C) grid, arrays [nz][ny][nx]: u[k][j][i] at
+ * the x-face between cells i-1 and i, v[k][j][i] at the y-face between rows
+ * j-1 and j, w[k][j][i] at the face between levels k-1 and k (w of level 0
+ * is the bottom boundary face, zero flux, never used).
+ * Divergence (anelastic form, whose composition with the gradient below is
+ * the operator A of the solve):
+ *   div_ijk = (u_{i+1} - u_i)/dx + (v_{j+1} - v_j)/dy
+ *           + (rho_{k+1/2} w_{k+1} - rho_{k-1/2} w_k) / (rho_k dz_k),
+ * periodic in x and y, with no flux through the bottom and top faces.
+ * Gradient: (p_i - p_{i-1})/dx on u faces, (p_j - p_{j-1})/dy on v faces,
+ * (p_k - p_{k-1})/h_{k-1/2} on the w faces of levels k >= 1 (0 at k = 0). */
+int oracle_divergence(int nx, int ny, int nz, double dx, double dy,
+                      const double *dz, const double *rho, const double *u,
+                      const double *v, const double *w, double *div)
+{
+    int err = check_grid(nx, ny, nz, dx, dy, dz, rho);
+    if (err || !u || !v || !w || !div)
+        return OR_EINVAL;
+    for (int k = 0; k < nz; ++k) {
+        const double Dk = rho[k] * dz[k];
+        const double rup = k + 1 < nz ? 0.5 * (rho[k] + rho[k + 1]) : 0.0;
+        const double rdn = k > 0 ? 0.5 * (rho[k - 1] + rho[k]) : 0.0;
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const size_t c = ((size_t)k * ny + j) * nx + i;
+                const size_t ie = ((size_t)k * ny + j) * nx + (i + 1) % nx;
+                const size_t jn = ((size_t)k * ny + (j + 1) % ny) * nx + i;
+                double d = (u[ie] - u[c]) / dx + (v[jn] - v[c]) / dy;
+                double flux = 0.0;
+                if (k + 1 < nz)
+                    flux += rup * w[c + (size_t)nx * ny];
+                if (k > 0)
+                    flux -= rdn * w[c];
+                div[c] = d + flux / Dk;
+            }
+    }
+    return OR_OK;
+}
+
+int oracle_gradient(int nx, int ny, int nz, double dx, double dy,
+                    const double *dz, const double *rho, const double *p,
+                    double *gu, double *gv, double *gw)
+{
+    int err = check_grid(nx, ny, nz, dx, dy, dz, rho);
+    if (err || !p || !gu || !gv || !gw)
+        return OR_EINVAL;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const size_t c = ((size_t)k * ny + j) * nx + i;
+                const size_t iw = ((size_t)k * ny + j) * nx + (i + nx - 1) % nx;
+                const size_t js = ((size_t)k * ny + (j + ny - 1) % ny) * nx + i;
+                gu[c] = (p[c] - p[iw]) / dx;
+                gv[c] = (p[c] - p[js]) / dy;
+                gw[c] = k > 0 ? (p[c] - p[c - (size_t)nx * ny]) / (0.5 * (dz[k - 1] + dz[k]))
+                              : 0.0;
+            }
+    return OR_OK;
+}
+
 /* Explicit 7-point operator, A p, by direct stencil application. */
 int oracle_apply(int nx, int ny, int nz, double dx, double dy,
                  const double *dz, const double *rho, const double *p,

@@ -50,6 +50,7 @@ SIGNATURES = {
     "ps_solve": (ctypes.c_int, [_vp, _vp, _vp]),
     "ps_solve_adjoint": (ctypes.c_int, [_vp, _vp, _vp]),
     "ps_solve_zyx": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
+    "ps_project": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, ctypes.c_int]),
     "ps_grad_coeffs": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "ps_grad_coeffs_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "ps_workspace_bytes": (ctypes.c_size_t, [_vp]),
@@ -213,6 +214,19 @@ class Plan:
         self._sync_stream()
         check(load().ps_solve_zyx(self._h, _vp(rhs.data_ptr()), _vp(out.data_ptr()),
                                   int(bool(adjoint))), "ps_solve_zyx")
+        return out
+
+    def project(self, u, v, w, dt, out=None, correct=True):
+        """One projection step: p = S(div(u, v, w)/dt) with the divergence
+        formed in the forward pass; with correct, (u, v, w) -= dt G p in
+        place.  Returns p."""
+        for t, nm in ((u, "u"), (v, "v"), (w, "w")):
+            self._check_field(t, nm)
+        out = self._out(out)
+        self._sync_stream()
+        check(load().ps_project(self._h, _vp(u.data_ptr()), _vp(v.data_ptr()),
+                                _vp(w.data_ptr()), float(dt), _vp(out.data_ptr()),
+                                int(bool(correct))), "ps_project")
         return out
 
     def grad_coeffs(self, lam, p):

@@ -94,6 +94,13 @@ __global__ __launch_bounds__(NT) void k_fft_y_fast(cx_t<T> *__restrict__ spec, i
 // f_{k-1/2}/D_{k-1}, (f_{k+1/2}+f_{k-1/2})/D_k); zero at the ends.  The x
 // neighbours x_{2n-1} and x_{2n+2} of the pair z_n = (x_{2n}, x_{2n+1}) come
 // from the neighbouring lanes of the row.
+// DIV: the transformed row is scale times the divergence of C-grid
+// velocities (in = u on the x-faces i-1/2, pres = v on the y-faces j-1/2,
+// wz = w on the faces k-1/2), formed in FP64 and rounded once to T:
+// idx2 (u_{i+1} - u_i) + idy2 (v_{j+1} - v_i) + a_up w_{k+1} - a_dn w_k, with
+// idx2 = 1/dx, idy2 = 1/dy and per-level rc[3k] = rho_{k+1/2}/D_k,
+// rc[3k+1] = rho_{k-1/2}/D_k (zero at the top and bottom faces).  u_{2n+2}
+// comes from the neighbouring lane as in RES.
 // PAIR (R1 = 2 R2): the row transform is four_step_pair, whose output slot
 // kk of lane t = 2m + h is X[m + R2 kk + R2^2 h].
 template <int R1, int R2, bool PAIR> __device__ __forceinline__ int out_index(int t, int i)
@@ -111,7 +118,7 @@ template <int R1, int R2, typename T, bool PAIR> constexpr int row_stride()
         return four_step_stride<R1, R2, T>();
 }
 
-template <typename T, int R1, int R2, int ROWS, bool RES, bool PAIR = false>
+template <typename T, int R1, int R2, int ROWS, bool RES, bool PAIR = false, bool DIV = false>
 __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
                                                       cx_t<T> *__restrict__ spec,
                                                       double *__restrict__ rowsum, int ny,
@@ -120,7 +127,8 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
                                                       const T *__restrict__ pres, int nz,
                                                       double idx2, double idy2,
                                                       const double *__restrict__ rc, int swz,
-                                                      int korder)
+                                                      int korder, const T *__restrict__ wz,
+                                                      double scale)
 {
     using C = cx_t<T>;
     constexpr int L = R1 * R2, NT = ROWS * R1, S = row_stride<R1, R2, T, PAIR>();
@@ -134,7 +142,41 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
     const C *src = reinterpret_cast<const C *>(in) + (ok ? g : 0) * (long)L;
     C v[R2], w[PAIR ? 1 : R2];
     double s = 0.0;
-    if constexpr (RES) {
+    if constexpr (DIV) {
+        const long gg = ok ? g : 0;
+        const int lev = (int)((unsigned)gg / (unsigned)ny), j = (int)(gg - (long)lev * ny);
+        const double au = rc[3 * lev], ad = rc[3 * lev + 1];
+        const C *V = reinterpret_cast<const C *>(pres);
+        const C *W = reinterpret_cast<const C *>(wz);
+        const C *vc_row = V + gg * L;
+        const C *vn_row = V + ((long)lev * ny + (j + 1 == ny ? 0 : j + 1)) * L;
+        const C *wc_row = W + gg * L;
+        // the top level's upper face carries no flux: its row pointer is this
+        // row and au is exactly zero (no branch around the load)
+        const C *wu_row = wc_row + (lev + 1 < nz ? (long)ny * L : 0);
+        C uc[R2];
+#pragma unroll
+        for (int q = 0; q < R2; ++q) uc[q] = nt_load<T>(&src[t + R1 * q]);
+        const int lane = threadIdx.x & 63, base = lane - t;
+        const int right = base + (t == R1 - 1 ? 0 : t + 1);
+#pragma unroll
+        for (int q = 0; q < R2; ++q) {
+            const int n = t + R1 * q;
+            // u_{2n+2}: lane t+1 slot q, or for t = R1-1 lane 0 slot q+1 (mod R2)
+            const T er_a = __shfl(uc[q].x, right, 64);
+            const T er_b = __shfl(uc[(q + 1) % R2].x, right, 64);
+            const T ue = t == R1 - 1 ? er_b : er_a;
+            const C vc = vc_row[n], vn = vn_row[n], wc = wc_row[n], wu = wu_row[n];
+            const double d0 = ((double)uc[q].y - (double)uc[q].x) * idx2 +
+                              ((double)vn.x - (double)vc.x) * idy2 + au * (double)wu.x -
+                              ad * (double)wc.x;
+            const double d1 = ((double)ue - (double)uc[q].y) * idx2 +
+                              ((double)vn.y - (double)vc.y) * idy2 + au * (double)wu.y -
+                              ad * (double)wc.y;
+            v[q] = C{(T)(scale * d0), (T)(scale * d1)};
+            s += ok ? (double)v[q].x + (double)v[q].y : 0.0;
+        }
+    } else if constexpr (RES) {
         const long gg = ok ? g : 0;
         const int lev = (int)((unsigned)gg / (unsigned)ny), j = (int)(gg - (long)lev * ny);
         const double au = rc[3 * lev], ad = rc[3 * lev + 1], ac = rc[3 * lev + 2];
@@ -449,21 +491,26 @@ template <typename T, int R1, int R2, bool WIDE>
 static hipError_t r2c_fast_rows(const T *in, cx_t<T> *spec, double *rowsum, int ny, int nz,
                                 const cx_t<T> *tw4, const cx_t<T> *tws, const T *pres,
                                 double idx2, double idy2, const double *rc, int swz,
-                                hipStream_t st)
+                                hipStream_t st, const T *wz, double scale)
 {
     constexpr int ROWS = x_rows<T, R1, R2, WIDE>();
     const int nrows = ny * nz;
     const int grid = (nrows + ROWS - 1) / ROWS;
-    // the residual's level-fastest tile order, where tiles do not straddle levels
+    // the level-fastest tile order of the residual and divergence forms,
+    // where tiles do not straddle levels
     const int korder = pres && swz && ny % ROWS == 0;
-    if (pres)
+    if (wz)
+        hipLaunchKernelGGL((k_r2c_fast<T, R1, R2, ROWS, false, false, true>), dim3(grid),
+                           dim3(ROWS * R1), 0, st, in, spec, rowsum, ny, nrows, tw4, tws, pres, nz,
+                           idx2, idy2, rc, swz, korder, wz, scale);
+    else if (pres)
         hipLaunchKernelGGL((k_r2c_fast<T, R1, R2, ROWS, true>), dim3(grid), dim3(ROWS * R1), 0, st,
                            in, spec, rowsum, ny, nrows, tw4, tws, pres, nz, idx2, idy2, rc, swz,
-                           korder);
+                           korder, (const T *)nullptr, 1.0);
     else
         hipLaunchKernelGGL((k_r2c_fast<T, R1, R2, ROWS, false>), dim3(grid), dim3(ROWS * R1), 0,
                            st, in, spec, rowsum, ny, nrows, tw4, tws, pres, nz, idx2, idy2, rc,
-                           swz, 0);
+                           swz, 0, (const T *)nullptr, 1.0);
     return hipGetLastError();
 }
 
@@ -472,20 +519,25 @@ static hipError_t r2c_fast_rows(const T *in, cx_t<T> *spec, double *rowsum, int 
 template <typename T, int R1, int R2>
 static hipError_t r2c_pair(const T *in, cx_t<T> *spec, double *rowsum, int ny, int nz,
                            const cx_t<T> *tw4, const cx_t<T> *tws, const T *pres, double idx2,
-                           double idy2, const double *rc, hipStream_t st)
+                           double idy2, const double *rc, hipStream_t st, const T *wz,
+                           double scale)
 {
     constexpr int ROWS = x_rows<T, R2, R1, false, true>();
     const int nrows = ny * nz;
     const int grid = (nrows + ROWS - 1) / ROWS;
     const int korder = pres && ny % ROWS == 0;
-    if (pres)
+    if (wz)
+        hipLaunchKernelGGL((k_r2c_fast<T, R2, R1, ROWS, false, true, true>), dim3(grid),
+                           dim3(ROWS * R2), 0, st, in, spec, rowsum, ny, nrows, tw4, tws, pres, nz,
+                           idx2, idy2, rc, 1, korder, wz, scale);
+    else if (pres)
         hipLaunchKernelGGL((k_r2c_fast<T, R2, R1, ROWS, true, true>), dim3(grid), dim3(ROWS * R2), 0,
                            st, in, spec, rowsum, ny, nrows, tw4, tws, pres, nz, idx2, idy2, rc, 1,
-                           korder);
+                           korder, (const T *)nullptr, 1.0);
     else
         hipLaunchKernelGGL((k_r2c_fast<T, R2, R1, ROWS, false, true>), dim3(grid), dim3(ROWS * R2),
                            0, st, in, spec, rowsum, ny, nrows, tw4, tws, pres, nz, idx2, idy2, rc,
-                           1, 0);
+                           1, 0, (const T *)nullptr, 1.0);
     return hipGetLastError();
 }
 
@@ -495,26 +547,29 @@ static hipError_t r2c_pair(const T *in, cx_t<T> *spec, double *rowsum, int ny, i
 template <typename T, int R1, int R2>
 static hipError_t r2c_fast(const T *in, cx_t<T> *spec, double *rowsum, int ny, int nz,
                            const cx_t<T> *tw4, const cx_t<T> *tws, const T *pres, double idx2,
-                           double idy2, const double *rc, int variant, hipStream_t st)
+                           double idy2, const double *rc, int variant, hipStream_t st,
+                           const T *wz, double scale)
 {
     if constexpr (R2 == 2 * R1)
         if (variant == 4)
             return r2c_pair<T, R1, R2>(in, spec, rowsum, ny, nz, tw4, tws, pres, idx2, idy2, rc,
-                                       st);
+                                       st, wz, scale);
     if (variant == 3)
         return r2c_fast_rows<T, R1, R2, true>(in, spec, rowsum, ny, nz, tw4, tws, pres, idx2,
-                                              idy2, rc, 1, st);
+                                              idy2, rc, 1, st, wz, scale);
     return r2c_fast_rows<T, R1, R2, false>(in, spec, rowsum, ny, nz, tw4, tws, pres, idx2, idy2,
-                                           rc, variant >= 2, st);
+                                           rc, variant >= 2, st, wz, scale);
 }
 
 template <typename T>
 hipError_t launch_r2c_fast(const T *in, cx_t<T> *spec, double *rowsum, int nx, int ny, int nz,
                            const cx_t<T> *tw4, const cx_t<T> *tws, hipStream_t st,
-                           const T *pres, double idx2, double idy2, const double *rc, int variant)
+                           const T *pres, double idx2, double idy2, const double *rc, int variant,
+                           const T *wz, double scale)
 {
 #define PS_X(a, b)                                                                                 \
-    r2c_fast<T, a, b>(in, spec, rowsum, ny, nz, tw4, tws, pres, idx2, idy2, rc, variant, st)
+    r2c_fast<T, a, b>(in, spec, rowsum, ny, nz, tw4, tws, pres, idx2, idy2, rc, variant, st, wz,   \
+                      scale)
     PS_FAST_SWITCH(nx / 2, PS_X)
 #undef PS_X
 }
@@ -564,7 +619,8 @@ hipError_t launch_c2r_fast(const cx_t<T> *spec, T *out, int nx, int ny, int nz, 
                                              const cx_t<T> *, hipStream_t, int);                  \
     template hipError_t launch_r2c_fast<T>(const T *, cx_t<T> *, double *, int, int, int,        \
                                            const cx_t<T> *, const cx_t<T> *, hipStream_t,         \
-                                           const T *, double, double, const double *, int);       \
+                                           const T *, double, double, const double *, int,        \
+                                           const T *, double);                                    \
     template hipError_t launch_c2r_fast<T>(const cx_t<T> *, T *, int, int, int, int,             \
                                            const cx_t<T> *, const cx_t<T> *, hipStream_t, int);
 PS_INST(float)

@@ -287,6 +287,22 @@ static int upload_residual_table(ps_plan *p)
     return upload(p->d_rc, rc);
 }
 
+// Divergence and gradient coefficients per level k: rho_{k+1/2}/D_k (0 at
+// the top), rho_{k-1/2}/D_k (0 at the bottom), 1/h_{k-1/2} (0 at k = 0).
+static int upload_div_table(ps_plan *p)
+{
+    const int nz = p->nz;
+    std::vector<double> dc(3 * (size_t)nz, 0.0);
+    for (int k = 0; k < nz; ++k) {
+        if (k + 1 < nz) dc[3 * k] = 0.5 * (p->rho[k] + p->rho[k + 1]) / p->D[k];
+        if (k > 0) {
+            dc[3 * k + 1] = 0.5 * (p->rho[k - 1] + p->rho[k]) / p->D[k];
+            dc[3 * k + 2] = 2.0 / (p->dz[k - 1] + p->dz[k]);
+        }
+    }
+    return upload(p->d_dc, dc);
+}
+
 static int upload_grad_table(ps_plan *p)
 {
     const int nz = p->nz;
@@ -421,6 +437,7 @@ extern "C" int ps_plan_create(ps_plan **out, int nx, int ny, int nz, double dx, 
     step(dev_alloc(p, &p->d_gk, 6 * (size_t)nz + 2));
     step(dev_alloc(p, &p->d_partial, (size_t)nz * p->nblk));
     step(dev_alloc(p, &p->d_rc, 6 * (size_t)nz));
+    step(dev_alloc(p, &p->d_dc, 3 * (size_t)nz));
     step(dev_alloc(p, &p->d_maskcnt, (size_t)p->L));
     step(dev_alloc(p, &p->d_mlist, list.size()));
     if (rc == PS_OK) step(upload_tables(p, p->t64));
@@ -429,6 +446,7 @@ extern "C" int ps_plan_create(ps_plan **out, int nx, int ny, int nz, double dx, 
     if (rc == PS_OK && !list.empty()) step(upload(p->d_mlist, list));
     if (rc == PS_OK) step(upload_grad_table(p));
     if (rc == PS_OK) step(upload_residual_table(p));
+    if (rc == PS_OK) step(upload_div_table(p));
     if (rc != PS_OK) {
         free_plan(p);
         return rc;
@@ -469,6 +487,7 @@ extern "C" int ps_plan_set_coeffs(ps_plan *p, const double *rho)
     if (!p->fp64()) PS_TRY(upload_coeff_tables(p, p->t32));
     PS_TRY(upload_grad_table(p));
     PS_TRY(upload_residual_table(p));
+    PS_TRY(upload_div_table(p));
     return PS_OK;
 }
 
@@ -799,6 +818,55 @@ static int solve_zyx_common(ps_plan *p, const void *in, void *out, int adjoint)
 extern "C" int ps_solve_zyx(ps_plan *p, const void *rhs, void *out, int adjoint)
 {
     return solve_zyx_common(p, rhs, out, adjoint);
+}
+
+// One projection step: p = S(div(u, v, w) / dt) with the divergence formed
+// inside the forward x pass, then optionally (u, v, w) -= dt G p.
+template <typename T>
+static int run_project(ps_plan *p, T *u, T *v, T *w, double dt, T *out, int correct)
+{
+    auto *spec = reinterpret_cast<cx_t<T> *>(p->d_spec);
+    const Tables<T> &tb = tables<T>(p);
+    PS_HIP(timed(p, K_FWD_X_DIV, [&] {
+        if (p->geom.variant_x >= 1)
+            return launch_r2c_fast<T>(u, spec, p->d_rowsum, p->nx, p->ny, p->nz, tb.tw4_x,
+                                      tb.tw_s, p->stream, v, 1.0 / p->dx, 1.0 / p->dy, p->d_dc,
+                                      p->geom.variant_x, w, 1.0 / dt);
+        return launch_fwd_x_div<T>(u, v, w, 1.0 / dt, spec, p->d_rowsum, p->nx, p->ny, p->nz,
+                                   p->dx, p->dy, p->d_dc, p->geom, p->spx, tb, p->stream);
+    }));
+    PS_TRY(middle<T>(p, spec, 0, p->precision == PS_FP32_R2));
+    PS_TRY(inv_x<T>(p, spec, out, 0));
+    if (p->precision == PS_FP32_R1) {
+        // one refinement step: the residual of the divergence, formed again
+        // inside the forward pass with FP64 accumulation, solved and added
+        PS_HIP(timed(p, K_FWD_X_RES, [&] {
+            return launch_fwd_x_div<T>(u, v, w, 1.0 / dt, spec, p->d_rowsum, p->nx, p->ny,
+                                       p->nz, p->dx, p->dy, p->d_dc, p->geom, p->spx, tb,
+                                       p->stream, out, p->d_rc);
+        }));
+        PS_TRY(middle<T>(p, spec, 0, 0));
+        PS_TRY(inv_x<T>(p, spec, out, 1));
+    }
+    if (correct)
+        PS_HIP(timed(p, K_CORRECT, [&] {
+            return launch_grad_correct<T>(u, v, w, out, dt, p->nx, p->ny, p->nz, p->dx, p->dy,
+                                          p->d_dc, p->stream);
+        }));
+    return PS_OK;
+}
+
+extern "C" int ps_project(ps_plan *p, void *u, void *v, void *w, double dt, void *out,
+                          int correct)
+{
+    if (!p || !u || !v || !w || !out) return fail(PS_EINVAL, "arguments must not be NULL");
+    if (!std::isfinite(dt) || dt <= 0.0) return fail(PS_EINVAL, "dt must be finite and > 0");
+    if (out == u || out == v || out == w || u == v || u == w || v == w)
+        return fail(PS_EINVAL, "u, v, w and p must be distinct fields");
+    if (p->fp64())
+        return run_project<double>(p, (double *)u, (double *)v, (double *)w, dt, (double *)out,
+                                   correct);
+    return run_project<float>(p, (float *)u, (float *)v, (float *)w, dt, (float *)out, correct);
 }
 
 static int solve_common(ps_plan *p, const void *in, void *out, int adjoint)

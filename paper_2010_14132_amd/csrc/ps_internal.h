@@ -92,12 +92,29 @@ template <typename T>
 hipError_t launch_fft_y_fast(cx_t<T> *spec, int nz, int L, int kxlo, int kxcnt, int ny, int dir,
                              const cx_t<T> *tw4, hipStream_t st, int variant);
 // pres != nullptr: transform the residual in - A pres (or in - A^T pres),
-// with the per-level vertical coefficients rc (see k_r2c_fast).
+// with the per-level vertical coefficients rc (see k_r2c_fast).  wz !=
+// nullptr: transform scale times the divergence of (in, pres, wz) = (u, v, w)
+// with idx2 = 1/dx, idy2 = 1/dy and the divergence coefficients rc.
 template <typename T>
 hipError_t launch_r2c_fast(const T *in, cx_t<T> *spec, double *rowsum, int nx, int ny, int nz,
                            const cx_t<T> *tw4, const cx_t<T> *tws, hipStream_t st,
                            const T *pres, double idx2, double idy2, const double *rc,
-                           int variant);
+                           int variant, const T *wz = nullptr, double scale = 1.0);
+// Generic (any length) forward x pass of scale times the divergence, and the
+// pressure-gradient correction u -= dt Gx p, v -= dt Gy p, w -= dt Gz p
+// (dyncore.hip).  dc: per level k, rho_{k+1/2}/D_k, rho_{k-1/2}/D_k and
+// 1/h_{k-1/2} (three values each, zero where a face is a boundary).
+// pres != nullptr: the residual scale * div - A pres instead (forward
+// vertical coefficients rc, the plan's residual table).
+template <typename T>
+hipError_t launch_fwd_x_div(const T *u, const T *v, const T *w, double scale, cx_t<T> *spec,
+                            double *rowsum, int nx, int ny, int nz, double dx, double dy,
+                            const double *dc, const FftGeom &g, const StagePlan &spx,
+                            const Tables<T> &tb, hipStream_t st, const T *pres = nullptr,
+                            const double *rc = nullptr);
+template <typename T>
+hipError_t launch_grad_correct(T *u, T *v, T *w, const T *p, double dt, int nx, int ny, int nz,
+                               double dx, double dy, const double *dc, hipStream_t st);
 template <typename T>
 hipError_t launch_c2r_fast(const cx_t<T> *spec, T *out, int nx, int ny, int nz, int accumulate,
                            const cx_t<T> *tw4, const cx_t<T> *tws, hipStream_t st, int variant);

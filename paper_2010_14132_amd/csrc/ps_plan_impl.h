@@ -12,10 +12,10 @@ using ps::Tables;
 
 // Per-kernel event timing (see ps_plan_profile).
 enum KernelId { K_FWD_X, K_FWD_X_RES, K_LEVEL_SUMS, K_FFT_Y_FWD, K_COLUMNS, K_SPECIAL, K_FFT_Y_INV,
-                K_INV_X, K_GRAD, K_COUNT };
+                K_INV_X, K_GRAD, K_FWD_X_DIV, K_CORRECT, K_COUNT };
 static const char *const kKernelNames[K_COUNT] = {
     "fwd_x", "fwd_x_residual", "level_sums", "fft_y_fwd", "columns", "special_fp64",
-    "fft_y_inv", "inv_x", "grad_rho"};
+    "fft_y_inv", "inv_x", "grad_rho", "fwd_x_divergence", "grad_correct"};
 
 struct Profiler {
     bool on = false;
@@ -73,6 +73,7 @@ struct ps_plan {
     double *d_gk = nullptr;
     double *d_partial = nullptr;
     double *d_rc = nullptr; // residual vertical coefficients [fwd: 3 nz][adj: 3 nz]
+    double *d_dc = nullptr; // divergence / gradient coefficients, 3 per level
     int nblk = 0;
     size_t bytes = 0;
     std::vector<void *> allocs;

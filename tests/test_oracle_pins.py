@@ -401,3 +401,38 @@ def test_mean_column_exact_arithmetic(nz, stretch, seed, adjoint):
     want = _exact_level_means(b, dz, rho, nx, ny, adjoint)
     got = p.mean(axis=(1, 2))
     assert np.abs(got - want).max() < 1e-14 * np.abs(p).max()
+
+
+# ---------------------------------------------------------------- divergence and gradient
+@pytest.mark.parametrize("shape,seed", [((6, 8, 10), 1), ((1, 4, 6), 2), ((9, 5, 3), 3)])
+def test_divergence_of_gradient_is_the_operator(shape, seed):
+    """Div(G p) = A p, the composition that makes the corrected flow
+    divergence-free: against the oracle's independent 7-point stencil."""
+    nz, ny, nx = shape
+    r = np.random.default_rng(seed)
+    g = wl.stretched_grid(nx, ny, nz, stretch=1.05)
+    dz = g.dz * r.uniform(0.8, 1.2, nz)
+    rho = g.rho * r.uniform(0.8, 1.2, nz)
+    p = r.standard_normal(shape)
+    gu, gv, gw = oracle.gradient(p, g.dx, 37.0, dz, rho)
+    d = oracle.divergence(gu, gv, gw, g.dx, 37.0, dz, rho)
+    a = oracle.apply(p, g.dx, 37.0, dz, rho)
+    assert np.abs(d - a).max() < 1e-12 * np.abs(a).max()
+
+
+def test_divergence_is_compatible_and_gradient_of_constant_vanishes():
+    """The D-weighted sum of any divergence is zero (periodic sides, no flux
+    through bottom and top): its projection mean is zero, so the solve needs
+    no compatibility correction; the gradient of a constant is zero, and
+    the bottom boundary face carries no gradient."""
+    r = np.random.default_rng(4)
+    nz, ny, nx = 7, 6, 8
+    g = wl.stretched_grid(nx, ny, nz, stretch=1.04)
+    u, v, w = (r.standard_normal((nz, ny, nx)) for _ in range(3))
+    d = oracle.divergence(u, v, w, g.dx, g.dy, g.dz, g.rho)
+    D = g.rho * g.dz
+    assert abs((D[:, None, None] * d).sum()) < 1e-12 * (D[:, None, None] * np.abs(d)).sum()
+    gu, gv, gw = oracle.gradient(np.full((nz, ny, nx), 3.5), g.dx, g.dy, g.dz, g.rho)
+    assert not gu.any() and not gv.any() and not gw.any()
+    gu, gv, gw = oracle.gradient(r.standard_normal((nz, ny, nx)), g.dx, g.dy, g.dz, g.rho)
+    assert not gw[0].any()
