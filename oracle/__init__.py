@@ -27,22 +27,32 @@ _lib = None
 _D = ctypes.POINTER(ctypes.c_double)
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
+_LIB_ASAN = os.path.join(_HERE, "libpressure_oracle_asan.so")
+
+
+def build(force: bool = False, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math); with
+    sanitize, a variant instrumented with AddressSanitizer and
+    UndefinedBehaviorSanitizer (loaded when PS_ORACLE_SANITIZE is set, with
+    gcc's ASan runtime preloaded)."""
+    lib = _LIB_ASAN if sanitize else _LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        tmp = lib + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-fopenmp", "-fno-fast-math", "-ffp-contract=off",
                "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
+        if sanitize:
+            cmd[1:1] = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                        "-fno-omit-frame-pointer", "-g"]
         subprocess.check_call(cmd)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, lib)
+    return lib
 
 
 def _load():
     global _lib
     if _lib is None:
-        build()
-        lib = ctypes.CDLL(_LIB)
+        sanitize = bool(os.environ.get("PS_ORACLE_SANITIZE"))
+        lib = ctypes.CDLL(build(sanitize=sanitize))
         i, d = ctypes.c_int, ctypes.c_double
         grid = [i, i, i, d, d, _D, _D]
         lib.oracle_solve.argtypes = grid + [_D, _D]

@@ -15,7 +15,9 @@ import threading
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpressure_solve.so")
+# PS_LIBRARY selects another build of the same library (the host-sanitizer
+# build of the CPU tests); by default the in-tree build.
+LIB_PATH = os.environ.get("PS_LIBRARY") or os.path.join(_HERE, "libpressure_solve.so")
 
 PS_FP64, PS_FP32, PS_FP32_R2, PS_FP32_R1 = 0, 1, 2, 3
 PRECISIONS = {"fp64": PS_FP64, "fp32": PS_FP32, "fp32_r2": PS_FP32_R2, "fp32_r1": PS_FP32_R1}

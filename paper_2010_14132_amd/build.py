@@ -3,6 +3,11 @@
 Every source under csrc/ is compiled (in parallel) to an object under
 _build/ and linked into paper_2010_14132_amd/libpressure_solve.so.  The build
 always recompiles; it runs on a machine without a GPU (hipcc cross-compiles).
+
+build(sanitize=True) builds a CPU-checking variant instead,
+_build_asan/libpressure_solve_asan.so: the host code instrumented with
+AddressSanitizer and UndefinedBehaviorSanitizer (device code unchanged), for
+running the host-side tests with the clang ASan runtime preloaded.
 """
 from __future__ import annotations
 
@@ -31,9 +36,17 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+BUILD_ASAN = os.path.join(HERE, "_build_asan")
+LIB_ASAN = os.path.join(BUILD_ASAN, "libpressure_solve_asan.so")
+# host-side sanitizers only: each -fsanitize applies to the host compilation
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all",
+             "-g"]
+
+
+def _compile(src: str, sanitize: bool = False) -> str:
+    obj = os.path.join(BUILD_ASAN if sanitize else BUILD, os.path.basename(src) + ".o")
+    cmd = [HIPCC] + FLAGS + (SAN_FLAGS if sanitize else []) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr))
@@ -43,19 +56,24 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = True) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = True, sanitize: bool = False) -> str:
+    out_dir = BUILD_ASAN if sanitize else BUILD
+    lib = LIB_ASAN if sanitize else LIB
+    os.makedirs(out_dir, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", "8")), 8)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp%d" % os.getpid()
+        objs = list(ex.map(lambda src: _compile(src, sanitize), srcs))
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+    if sanitize:
+        cmd += ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                "-shared-libsan"]
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -116,3 +116,48 @@ def test_tune_cache_round_trip_and_rejects_bad_lines(lib, tmp_path):
     assert ("gfx950", "128", "128", "16", "1") not in lines
     assert not any(k[1:4] == ("64", "64", "8") for k in lines)
     assert lib.ps_tune_cache_load(os.fsencode(str(tmp_path / "missing.txt"))) == 1
+
+
+def test_new_entry_points_reject_bad_arguments_before_any_hip_call(lib):
+    """Batched, conjugate-gradient, z-fastest, projection and no-allocation
+    entry points validate on the host (no GPU needed)."""
+    from paper_2010_14132_amd import binding
+    vp = ctypes.c_void_p
+    one = (ctypes.c_int * 1)(8)
+    d1 = (ctypes.c_double * 1)(50.0)
+    dz = np.full(8, 40.0)
+    arr = (binding._D * 1)(binding._dptr(dz))
+    h = vp(1234)
+    assert lib.ps_batch_create(None, 1, one, one, one, d1, d1, arr, arr, 1, None) == 1
+    assert lib.ps_batch_create(ctypes.byref(h), 0, one, one, one, d1, d1, arr, arr, 1, None) == 1
+    assert h.value is None
+    assert lib.ps_batch_create(ctypes.byref(h), 1, None, one, one, d1, d1, arr, arr, 1, None) == 1
+    assert lib.ps_batch_create(ctypes.byref(h), 1, one, one, one, d1, d1, arr, arr, 9, None) == 2
+    nul = (binding._D * 1)()
+    assert lib.ps_batch_create(ctypes.byref(h), 1, one, one, one, d1, d1, nul, arr, 1, None) == 1
+    assert lib.ps_batch_solve(None, None, None) == 1
+    assert lib.ps_batch_set_lanes(None, 2) == 1
+    assert lib.ps_batch_set_mode(None, 3) == 1
+    assert lib.ps_batch_autotune(None, None, None, 1) == 1
+    assert lib.ps_batch_query(None, None, None, None, None) == 1
+    assert lib.ps_batch_status(None) == 1
+    assert lib.ps_batch_destroy(None) == 0
+    rho = np.ones(8)
+    for args, code in (((8, 8, 8, 50.0, 50.0, binding._dptr(dz), binding._dptr(rho), 7), 1),
+                       ((0, 8, 8, 50.0, 50.0, binding._dptr(dz), binding._dptr(rho), 1), 2),
+                       ((8, 8, 8, -1.0, 50.0, binding._dptr(dz), binding._dptr(rho), 1), 1),
+                       ((8, 8, 8, 50.0, 50.0, None, binding._dptr(rho), 1), 1),
+                       ((1 << 12, 1 << 12, 1 << 8, 50.0, 50.0, binding._dptr(dz),
+                         binding._dptr(rho), 1), 2)):
+        assert lib.ps_cg_create(ctypes.byref(h), *args, None) == code, args
+        assert h.value is None
+    bad = np.full(8, 40.0)
+    bad[3] = -1.0
+    assert lib.ps_cg_create(ctypes.byref(h), 8, 8, 8, 50.0, 50.0, binding._dptr(bad),
+                            binding._dptr(rho), 1, None) == 1
+    assert lib.ps_cg_solve(None, None, None, 1e-6, 10, None, None) == 1
+    assert lib.ps_cg_destroy(None) == 0
+    assert lib.ps_cg_workspace_bytes(None) == 0
+    assert lib.ps_solve_zyx(None, None, None, 0) == 1
+    assert lib.ps_project(None, None, None, None, 1.0, None, 1) == 1
+    assert lib.ps_grad_coeffs_noalloc(None, None, None, None) == 1
