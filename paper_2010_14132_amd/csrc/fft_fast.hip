@@ -44,7 +44,7 @@ template <typename T> __device__ __forceinline__ void nt_store(cx_t<T> v, cx_t<T
 template <typename T, int R1, int R2, int DIR, int NT>
 __global__ __launch_bounds__(NT) void k_fft_y_fast(cx_t<T> *__restrict__ spec, int nrows,
                                                    const cx_t<T> *__restrict__ tw4, int nkx,
-                                                   int kxlo, int kxcnt, int swz)
+                                                   int kxlo, int kxcnt, int swz, int keep)
 {
     using C = cx_t<T>;
     constexpr int L = R1 * R2, RB = NT / R1, S = four_step_stride<R1, R2, T>();
@@ -63,16 +63,21 @@ __global__ __launch_bounds__(NT) void k_fft_y_fast(cx_t<T> *__restrict__ spec, i
         // the forward pass stores non-temporally: its rows are read next by
         // the column kernel, which then does not pay for writing back this
         // pass's dirty lines (measured; the backward pass measured better
-        // with plain stores)
+        // with plain stores).  keep (the kx ranges of a chunked pipeline,
+        // small enough to stay in the last-level cache until the column
+        // kernel reads them): plain stores.
+        if (DIR < 0 && !keep) {
 #pragma unroll
-        for (int j = 0; j < R2 / R1; ++j)
+            for (int j = 0; j < R2 / R1; ++j)
 #pragma unroll
-            for (int k1 = 0; k1 < R1; ++k1) {
-                if constexpr (DIR < 0)
+                for (int k1 = 0; k1 < R1; ++k1)
                     nt_store<T>(w[j * R1 + k1], &base[(t + R1 * j) + R2 * k1]);
-                else
-                    base[(t + R1 * j) + R2 * k1] = w[j * R1 + k1];
-            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < R2 / R1; ++j)
+#pragma unroll
+                for (int k1 = 0; k1 < R1; ++k1) base[(t + R1 * j) + R2 * k1] = w[j * R1 + k1];
+        }
     }
 }
 
@@ -444,7 +449,7 @@ template <typename T, int R1, int R2, bool WIDE, bool PAIR = false> constexpr in
 // Returns hipErrorNotSupported when L has no register-resident kernel.
 template <typename T, int R1, int R2>
 static hipError_t y_fast(cx_t<T> *spec, int nrows, int dir, const cx_t<T> *tw4, int nkx, int kxlo,
-                         int kxcnt, int swz, hipStream_t st)
+                         int kxcnt, int swz, hipStream_t st, int keep)
 {
     constexpr int NT = sizeof(T) == 8 && R1 * R2 >= 512 ? 128 : 256;
     constexpr int RB = NT / R1;
@@ -452,10 +457,10 @@ static hipError_t y_fast(cx_t<T> *spec, int nrows, int dir, const cx_t<T> *tw4, 
     const int grid = (nrows + RB - 1) / RB;
     if (dir < 0)
         hipLaunchKernelGGL((k_fft_y_fast<T, R1, R2, -1, NT>), dim3(grid), dim3(NT), 0, st, spec,
-                           nrows, tw4, nkx, kxlo, kxcnt, swz);
+                           nrows, tw4, nkx, kxlo, kxcnt, swz, keep);
     else
         hipLaunchKernelGGL((k_fft_y_fast<T, R1, R2, 1, NT>), dim3(grid), dim3(NT), 0, st, spec,
-                           nrows, tw4, nkx, kxlo, kxcnt, swz);
+                           nrows, tw4, nkx, kxlo, kxcnt, swz, keep);
     return hipGetLastError();
 }
 
@@ -478,11 +483,11 @@ bool pair_length(int L) { return L == 32 || L == 128 || L == 512; }
 // variant: 1 = plain block order, 2 = XCD-contiguous tiles.
 template <typename T>
 hipError_t launch_fft_y_fast(cx_t<T> *spec, int nz, int nkx, int kxlo, int kxcnt, int ny, int dir,
-                             const cx_t<T> *tw4, hipStream_t st, int variant)
+                             const cx_t<T> *tw4, hipStream_t st, int variant, int keep)
 {
     const int nrows = nz * kxcnt;
     const int swz = variant >= 2;
-#define PS_Y(a, b) y_fast<T, a, b>(spec, nrows, dir, tw4, nkx, kxlo, kxcnt, swz, st)
+#define PS_Y(a, b) y_fast<T, a, b>(spec, nrows, dir, tw4, nkx, kxlo, kxcnt, swz, st, keep)
     PS_FAST_SWITCH(ny, PS_Y)
 #undef PS_Y
 }
@@ -616,7 +621,7 @@ hipError_t launch_c2r_fast(const cx_t<T> *spec, T *out, int nx, int ny, int nz, 
 
 #define PS_INST(T)                                                                                 \
     template hipError_t launch_fft_y_fast<T>(cx_t<T> *, int, int, int, int, int, int,            \
-                                             const cx_t<T> *, hipStream_t, int);                  \
+                                             const cx_t<T> *, hipStream_t, int, int);             \
     template hipError_t launch_r2c_fast<T>(const T *, cx_t<T> *, double *, int, int, int,        \
                                            const cx_t<T> *, const cx_t<T> *, hipStream_t,         \
                                            const T *, double, double, const double *, int,        \

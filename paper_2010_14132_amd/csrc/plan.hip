@@ -577,7 +577,7 @@ template <> Tables<double> &tables<double>(ps_plan *p) { return p->t64; }
 
 template <typename T>
 static hipError_t y_pass(ps_plan *p, cx_t<T> *spec, int dir, int kxlo = 0, int kxcnt = -1,
-                         hipStream_t st = nullptr)
+                         hipStream_t st = nullptr, int keep = 0)
 {
     const Tables<T> &tb = tables<T>(p);
     if (kxcnt < 0) kxcnt = p->L - kxlo;
@@ -588,7 +588,7 @@ static hipError_t y_pass(ps_plan *p, cx_t<T> *spec, int dir, int kxlo = 0, int k
         [&] {
             if (p->geom.variant_y >= 1)
                 return launch_fft_y_fast<T>(spec, p->nz, p->L, kxlo, kxcnt, p->ny, dir, tb.tw4_y,
-                                            st, p->geom.variant_y);
+                                            st, p->geom.variant_y, keep);
             return launch_fft_y<T>(spec, p->nz, p->L, kxlo, kxcnt, p->ny, dir, p->geom, p->spy,
                                    tb, st);
         },
@@ -743,7 +743,7 @@ template <typename T> static int middle(ps_plan *p, cx_t<T> *spec, int adjoint, 
     for (int c = 0; c < nch; ++c) {
         const int a = km + (int)(rest * c / nch), b = km + (int)(rest * (c + 1) / nch);
         if (b <= a) continue;
-        PS_HIP(y_pass<T>(p, spec, -1, a, b - a));
+        PS_HIP(y_pass<T>(p, spec, -1, a, b - a, nullptr, 1));
         PS_HIP(main_columns<T>(p, spec, adjoint, refine, a, b));
         PS_HIP(y_pass<T>(p, spec, 1, a, b - a));
     }

@@ -88,9 +88,11 @@ int fast_r1(int L); // lanes per row of the register-resident kernels
 // 2 = XCD-contiguous tiles, 3 (x passes only) = as 2 with twice the rows per
 // block, 4 (x passes only) = as 2 with the paired row transform when
 // nx/2 = 2 s^2 (else as 2).
+// keep: the forward pass stores with the normal cache policy (its rows are
+// read again soon, in a chunked pipeline) instead of non-temporally.
 template <typename T>
 hipError_t launch_fft_y_fast(cx_t<T> *spec, int nz, int L, int kxlo, int kxcnt, int ny, int dir,
-                             const cx_t<T> *tw4, hipStream_t st, int variant);
+                             const cx_t<T> *tw4, hipStream_t st, int variant, int keep = 0);
 // pres != nullptr: transform the residual in - A pres (or in - A^T pres),
 // with the per-level vertical coefficients rc (see k_r2c_fast).  wz !=
 // nullptr: transform scale times the divergence of (in, pres, wz) = (u, v, w)

@@ -765,6 +765,119 @@ __device__ inline void mean_column_fp64(int nz, int nx, int ny, int adjoint,
     }
 }
 
+// The same mean column computed by one whole wave (64 lanes; nz <= 256, so
+// lane l takes levels 4l .. 4l+3): the sums are lane partials combined in a
+// fixed butterfly, the bottom-up and top-down flux sums and the level
+// differences are prefix / suffix sums (lane-local runs plus a scan of the
+// lane totals).  The same definitions as mean_column_fp64 (including each
+// face's choice between the two flux sums), summed in another order.
+__device__ inline double wave_incl_scan(double v, int lane)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+__device__ inline double wave_incl_scan_rev(double v, int lane)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double u = __shfl_down(v, o, 64);
+        if (lane + o < 64) v += u;
+    }
+    return v;
+}
+__device__ inline void mean_column_wave(int nz, int nx, int ny, int adjoint, const double *f,
+                                        const double *D, const double *sS, double *xr,
+                                        double *xi, int stride)
+{
+    constexpr int P = 4;
+    const int lane = threadIdx.x & 63;
+    const int k0 = lane * P;
+    const double on = 1.0 / ((double)nx * (double)ny);
+    double w[P], t[P];
+    double num = 0.0, den = 0.0;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int k = k0 + q;
+        w[q] = k < nz ? (adjoint ? 1.0 : D[k]) : 0.0;
+        num += k < nz ? w[q] * sS[k] : 0.0;
+        den += w[q];
+    }
+    num = wave_sum(num);
+    den = wave_sum(den);
+    const double M = num / den;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int k = k0 + q;
+        t[q] = k < nz ? w[q] * ((sS[k] - M) * on) : 0.0;
+    }
+    // bottom-up sums P_k and weights W_k (inclusive), top-down sums of the
+    // levels above k (exclusive)
+    double lt = 0.0, lw = 0.0;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        lt += t[q];
+        lw += w[q];
+    }
+    const double pt = wave_incl_scan(lt, lane) - lt, pw = wave_incl_scan(lw, lane) - lw;
+    const double st = wave_incl_scan_rev(lt, lane) - lt;
+    double up[P], wl[P], dn[P];
+    double a = pt, b = pw;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        a += t[q];
+        b += w[q];
+        up[q] = a;
+        wl[q] = b;
+    }
+    double c = st;
+#pragma unroll
+    for (int q = P - 1; q >= 0; --q) {
+        dn[q] = c;
+        c += t[q];
+    }
+    // level differences d_k = F_{k+1/2} / f_{k+1/2} (k < nz - 1), then
+    // x_{k+1} = sum_{j <= k} d_j, x_0 = 0
+    double d[P], ld = 0.0;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int k = k0 + q;
+        const double F = wl[q] <= den - wl[q] ? up[q] : -dn[q];
+        d[q] = k + 1 < nz ? F / f[k + 1] : 0.0;
+        ld += d[q];
+    }
+    const double pd = wave_incl_scan(ld, lane) - ld;
+    double x[P];
+    double e = pd;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        x[q] = e; // x_k = sum_{j < k} d_j
+        e += d[q];
+    }
+    double acc = 0.0, wsum = 0.0;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int k = k0 + q;
+        const double wk = k < nz ? (adjoint ? D[k] : 1.0) : 0.0;
+        acc += wk * x[q];
+        wsum += wk;
+    }
+    acc = wave_sum(acc);
+    wsum = wave_sum(wsum);
+    const double shift = acc / wsum;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int k = k0 + q;
+        if (k < nz) {
+            xr[(size_t)k * stride] = x[q] - shift;
+            xi[(size_t)k * stride] = 0.0;
+        }
+    }
+}
+
 // ----------------------------------------------------------- FP64 columns, compact
 // One lane per task, FP64, with short code: the level loop is unrolled by U
 // only, the next U levels' loads are issued before the current U levels are

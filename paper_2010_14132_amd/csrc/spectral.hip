@@ -521,9 +521,9 @@ __global__ __launch_bounds__(256) void k_special_lds(
     __syncthreads();
 
     // the sweeps: lanes [0, 2G), two per task (pair: A and B; a
-    // near-singular column: one); the mean column (task 0's A) runs on the
-    // block's last thread, in another wave, so the wave of the sweeps does
-    // not execute its serial loops as well
+    // near-singular column: one); the mean column (task 0's A) is computed by
+    // the block's last wave with scans (2G <= 128, so that wave does no
+    // sweep)
     if ((int)threadIdx.x < 2 * G) {
         const int g = threadIdx.x >> 1, sys = threadIdx.x & 1, t = t0 + g;
         const bool pair = t < npair;
@@ -577,9 +577,9 @@ __global__ __launch_bounds__(256) void k_special_lds(
             }
         }
     }
-    if (t0 == 0 && threadIdx.x == blockDim.x - 1) {
+    if (t0 == 0 && threadIdx.x >= blockDim.x - 64) {
         double *base = reinterpret_cast<double *>(ys);
-        mean_column_fp64(nz, nx, ny, adjoint, f, D, sS, base, base + 1, 4 * G);
+        mean_column_wave(nz, nx, ny, adjoint, f, D, sS, base, base + 1, 4 * G);
     }
     __syncthreads();
 

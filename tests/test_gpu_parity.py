@@ -507,9 +507,12 @@ SPECIAL_SHAPES = [(128, 64, 96), (20, 64, 128), (5, 12, 18), (1, 8, 8), (256, 8,
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_r2"])
 def test_fp64_column_kernels_agree(tmp_path, precision, shape):
     """The two FP64-column kernels (one lane per task through the HBM
-    workspace; staged in LDS, several tasks per block), forced through the
-    tune cache: the same per-system arithmetic, so the same solution up to
-    FP64 rounding, and each against the oracle (forward and adjoint)."""
+    workspace; staged in LDS, several tasks per block, the mean column by
+    wave scans), forced through the tune cache: each against the oracle
+    (forward and adjoint), and against each other within the sum of their
+    bars (the eliminations are the same arithmetic, the mean column's sums
+    are taken in another order, whose rounding the top of a tall stretched
+    grid amplifies)."""
     from paper_2010_14132_amd.binding import PRECISIONS, tune_cache_load
     nz, ny, nx = shape
     announce("FP64-column kernels %s %s" % (precision, shape))
@@ -538,4 +541,4 @@ def test_fp64_column_kernels_agree(tmp_path, precision, shape):
         sols.append((p, lam))
     print("bit-equal: %s" % (np.array_equal(sols[0][0], sols[1][0])
                              and np.array_equal(sols[0][1], sols[1][1])))
-    assert relmax(sols[1][0], sols[0][0]) < (1e-14 if precision == "fp64" else 1e-6)
+    assert relmax(sols[1][0], sols[0][0]) < 2 * tol
