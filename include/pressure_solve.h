@@ -192,6 +192,8 @@ typedef struct ps_plan_info {
                              workspace, 1 staged in LDS */
     int zyx_kc;           /* z-fastest-layout x passes: levels per tile (capped by the
                              tile's rows) */
+    int fp64_beside;      /* where the FP64 columns (packed kx = 0 row, mean column,
+                             near-singular columns) run: the tune cache's fp64_beside */
 } ps_plan_info;
 
 int ps_plan_query(const ps_plan *plan, ps_plan_info *info);
@@ -204,10 +206,12 @@ int ps_plan_query(const ps_plan *plan, ps_plan_info *info);
  * nz, precision) for the life of the process -- a later autotune of an equal
  * plan just applies them -- and can be saved to / loaded from a text file
  * (one line per entry: arch nx ny nz precision x_variant y_variant
- * column_variant [fp64_beside [chunks [xi_variant [special_variant]]]]:
- * fp64_beside 1 when the FP64 columns run on a second stream beside the
- * main column kernel, chunks the number of kx ranges the y / column / y
- * passes are taken in, both defaulting to 1; xi_variant the backward x
+ * column_variant [fp64_beside [chunks [xi_variant [special_variant [zyx_kc]]]]]:
+ * fp64_beside where the FP64 columns run: 0 on the plan's stream before the
+ * main column kernel, 1 on a second stream beside it (that stream also
+ * transforms their rows in y), 2 on a second stream forked after the whole
+ * y pass; chunks the number of kx ranges the y / column / y passes are
+ * taken in (with fp64_beside 1 only); both defaulting to 1; xi_variant the backward x
  * pass's, defaulting to x_variant; special_variant the FP64-column kernel's
  * (0 or 1), defaulting to 1; zyx_kc the levels per tile of the z-fastest
  * layout's x passes (1..256), defaulting to 64; it is timed with

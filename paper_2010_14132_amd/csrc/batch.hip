@@ -141,9 +141,9 @@ extern "C" int ps_batch_create(ps_batch **out, int count, const int *nx, const i
     };
     for (int l = 0; l < kMaxLanes; ++l)
         if (hipStreamCreateWithFlags(&b->lanes[l], hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&b->ev_join[l], hipEventDisableTiming) != hipSuccess)
+            hipEventCreateWithFlags(&b->ev_join[l], ps::kStreamEventFlags) != hipSuccess)
             return bail(bfail(PS_EHIP, "stream or event creation failed"));
-    if (hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess)
+    if (hipEventCreateWithFlags(&b->ev_in, ps::kStreamEventFlags) != hipSuccess)
         return bail(bfail(PS_EHIP, "event creation failed"));
     b->plans.assign(count, nullptr);
     b->points.assign(count, 0);

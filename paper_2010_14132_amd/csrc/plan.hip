@@ -413,9 +413,9 @@ extern "C" int ps_plan_create(ps_plan **out, int nx, int ny, int nz, double dx, 
         return fail(PS_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
     }
     if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&p->join, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&p->ydone, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&p->fork, kStreamEventFlags) != hipSuccess ||
+        hipEventCreateWithFlags(&p->join, kStreamEventFlags) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ydone, kStreamEventFlags) != hipSuccess) {
         free_plan(p);
         return fail(PS_EHIP, "stream or event creation failed");
     }
@@ -507,9 +507,10 @@ extern "C" int ps_plan_query(const ps_plan *p, ps_plan_info *info)
     info->fft_variant_y = p->geom.variant_y;
     info->spectrum_elems = p->spec_elems();
     info->column_variant = p->geom.columns;
-    info->chunks = p->geom.special_side ? p->geom.chunks : 1;
+    info->chunks = p->geom.special_side == 1 ? p->geom.chunks : 1;
     info->special_variant = p->geom.special_variant;
     info->zyx_kc = p->geom.zyx_kc;
+    info->fp64_beside = p->geom.special_side;
     return PS_OK;
 }
 
@@ -712,6 +713,15 @@ template <typename T> static int middle(ps_plan *p, cx_t<T> *spec, int adjoint, 
         PS_HIP(y_pass<T>(p, spec, -1));
         PS_HIP(special_columns<T>(p, spec, adjoint, p->stream));
         PS_HIP(main_columns<T>(p, spec, adjoint, refine, 1, L));
+        PS_HIP(y_pass<T>(p, spec, 1));
+        return PS_OK;
+    }
+    if (p->geom.special_side == 2) {
+        // The whole y pass on the plan's stream, then the FP64 columns forked
+        // beside the main column kernel: one cross-stream wait (the join)
+        // on the plan's stream instead of two.
+        PS_HIP(y_pass<T>(p, spec, -1));
+        PS_TRY(columns<T>(p, spec, adjoint, refine));
         PS_HIP(y_pass<T>(p, spec, 1));
         return PS_OK;
     }
@@ -1031,8 +1041,8 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
     else
         pick(&FftGeom::columns, {0, 3, 5, 6, 7, 8});
     pick(&FftGeom::special_variant, {0, 1});
-    pick(&FftGeom::special_side, {0, 1});
-    if (p->geom.special_side) pick(&FftGeom::chunks, {1, 2, 4, 8});
+    pick(&FftGeom::special_side, {0, 1, 2});
+    if (p->geom.special_side == 1) pick(&FftGeom::chunks, {1, 2, 4, 8});
     if (p->precision != PS_FP32_R1) pick(&FftGeom::zyx_kc, {1, 2, 4, 8, 64}, solve_zyx_common);
     p->prof.on = prof;
     (void)hipStreamSynchronize(p->stream);
@@ -1079,7 +1089,7 @@ extern "C" int ps_tune_cache_load(const char *path)
         if (!(is >> vxi)) vxi = vx;
         if (!(is >> spv)) spv = 1;
         if (!(is >> zkc)) zkc = 64;
-        if (vx < 0 || vx > 4 || vy < 0 || vy > 2 || col < 0 || col > 8 || side < 0 || side > 1 ||
+        if (vx < 0 || vx > 4 || vy < 0 || vy > 2 || col < 0 || col > 8 || side < 0 || side > 2 ||
             chunks < 1 || chunks > 64 || vxi < 0 || vxi > 4 || spv < 0 || spv > 1 || zkc < 1 ||
             zkc > 256)
             continue;

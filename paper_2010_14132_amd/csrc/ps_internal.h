@@ -10,6 +10,14 @@
 
 namespace ps {
 
+// Flags of the events that order work between streams of one device (the
+// side stream of the FP64 columns, the lanes of a batch).  Their consumers
+// are kernels on the same device, so the default system-scope fence on
+// record and wait (cache write-back and invalidation for the host and other
+// devices) is left out; the device-scope release and acquire that order
+// kernels remain.
+constexpr unsigned kStreamEventFlags = hipEventDisableTiming | hipEventDisableSystemFence;
+
 // One slot of the uniform-half column kernel's coefficient table (see
 // k_columns3): coupling to the previous and next row of the elimination,
 // D_k, right-hand-side and output factors, whether the slot is a real level
@@ -49,7 +57,10 @@ struct FftGeom {
     int variant_x = 0;   // forward x pass
     int variant_xi = 0;  // backward x pass
     int variant_y = 0;
-    int special_side = 1; // 1: FP64 columns on the side stream beside the main kernel
+    int special_side = 1; // FP64 columns: 0 on the plan's stream before the main kernel;
+                          // 1 on the side stream, which also transforms their rows
+                          // (kx < kmask) in y; 2 on the side stream after the whole
+                          // y pass
     int columns = 2;     // column-solve kernel variant (see launch_columns_impl)
     int chunks = 1;      // y forward / columns / y backward run in this many kx chunks
     int special_variant = 1; // FP64 columns: 0 one lane per task via the HBM workspace,

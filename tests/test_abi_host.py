@@ -100,6 +100,8 @@ def test_tune_cache_round_trip_and_rejects_bad_lines(lib, tmp_path):
         "gfx950 96 96 16 1 1 1 3 1 1 1 1 0",  # z-fastest tile levels out of range
         "gfx950 128 128 16 1 1 1 3 1 1 1 2", # FP64-column variant out of range
         "gfx950 256 256 32 0 1 1 3",         # short: fp64_beside 1, chunks 1, xi = x
+        "gfx950 256 256 32 2 1 1 7 2",       # FP64 columns forked after the y pass
+        "gfx950 512 512 32 2 1 1 7 3",       # fp64_beside out of range
         "gfx950 64 64 8 2 9 1 3",            # x variant out of range
         "gfx950 64 64 8 3 1 1 9",            # column variant out of range
         "gfx950 64 64 8 1 1 1 3 1 0",        # chunks out of range
@@ -112,6 +114,8 @@ def test_tune_cache_round_trip_and_rejects_bad_lines(lib, tmp_path):
     lines = {tuple(l.split()[:5]): l.split()[5:] for l in out.read_text().splitlines() if l}
     assert lines[("gfx950", "512", "256", "64", "1")] == ["2", "1", "5", "1", "4", "3", "0", "8"]
     assert lines[("gfx950", "256", "256", "32", "0")] == ["1", "1", "3", "1", "1", "1", "1", "64"]
+    assert lines[("gfx950", "256", "256", "32", "2")] == ["1", "1", "7", "2", "1", "1", "1", "64"]
+    assert ("gfx950", "512", "512", "32", "2") not in lines
     assert ("gfx950", "96", "96", "16", "1") not in lines
     assert ("gfx950", "128", "128", "16", "1") not in lines
     assert not any(k[1:4] == ("64", "64", "8") for k in lines)

@@ -450,6 +450,38 @@ def test_kernel_variants_via_tune_cache(tmp_path, precision, var):
     assert relmax(lam, lref) < (TOL64 if precision == "fp64" else TOL32)
 
 
+@pytest.mark.parametrize("side", [0, 1, 2])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_r1", "fp32_r2"])
+def test_fp64_column_placement_via_tune_cache(tmp_path, precision, side):
+    """Each placement of the FP64 columns (before the main column kernel on
+    the plan's stream; on the side stream with its own y pass of their rows;
+    on the side stream after the whole y pass), forced through the tune
+    cache, reproduces the oracle forward and adjoint, on a stretched grid
+    with near-singular columns in the FP32 forms."""
+    from paper_2010_14132_amd.binding import PRECISIONS, tune_cache_load
+    nz, ny, nx = 24, 96, 64
+    announce("fp64 columns placement %d %s" % (side, precision))
+    g = stretched(nx, ny, nz, seed=23)
+    f = tmp_path / "tune.txt"
+    f.write_text("%s %d %d %d %d 1 1 3 %d 1\n"
+                 % (_arch(), nx, ny, nz, PRECISIONS[precision], side))
+    tune_cache_load(str(f))
+    plan = make_plan(g, precision)
+    plan.autotune()
+    info = plan.info()
+    assert info["fp64_beside"] == side and info["column_variant"] == 3
+    b = np.random.default_rng(9).standard_normal((nz, ny, nx)) + 0.1
+    if precision != "fp64":
+        b = b.astype(np.float32).astype(np.float64)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    tol = TOL64 if precision == "fp64" else TOL32
+    p = plan.solve(torch.from_numpy(b).to("cuda", dt)).cpu().numpy()
+    assert relmax(p, oracle.solve(b, g.dx, g.dy, g.dz, g.rho)) < tol
+    lam = plan.solve_adjoint(torch.from_numpy(b).to("cuda", dt)).cpu().numpy()
+    assert relmax(lam, oracle.solve_adjoint(b, g.dx, g.dy, g.dz, g.rho)) < tol
+    plan.close()
+
+
 PAIR_SHAPES = [(6, 32, 64), (5, 24, 256), (3, 16, 1024)]  # nx/2 = 32, 128, 512 (= 2 s^2)
 
 
