@@ -412,12 +412,15 @@ def config_projection(prob, steps, warmup):
 
 
 def config_cg(prob):
-    """The paper's Table 1 on this hardware: matrix-free CG (Jacobi and no
-    preconditioner, FP64) terminated at relative residuals 1e-2 ... 1e-8,
-    iterations, time per solve (host clock around the call, which reads the
-    convergence flag every 16 iterations) and the mean difference from the
-    FP64 direct solve, relative to the direct solution's mean magnitude;
-    the direct solve's time beside it."""
+    """The paper's Tables 1 and 2 on this hardware: the matrix-free Krylov
+    solvers (CG on -D A, BiCGStab on A; Jacobi and no preconditioner, FP64)
+    terminated at relative residuals 1e-2 ... 1e-8, iterations, time per
+    solve (host clock around the call, which reads the convergence flag every
+    16 iterations) and the mean difference from the FP64 direct solve,
+    relative to the direct solution's mean magnitude; the direct solve's time
+    beside it.  Algorithmic bytes per iteration: CG 88 B/pt (operator 16,
+    update 48, direction 24), BiCGStab 168 B/pt (direction 32, two operator
+    applications 24 + 16, two updates 48 + 48)."""
     import torch
     from paper_2010_14132_amd import CGSolver, Plan
     g = prob.grid
@@ -428,22 +431,27 @@ def config_cg(prob):
     d_ms = time_calls(lambda: plan.solve(b, out=direct), 50, 5)
     dmean = direct.abs().mean().item()
     res = {"direct_fp64_ms": d_ms, "ladder": []}
-    for precond in ("jacobi", "none"):
-        s = CGSolver(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.rho, precond=precond)
-        s.solve(b, rtol=1e-2)  # warm-up
-        for rtol in (1e-2, 1e-4, 1e-6, 1e-8):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            x, it, rel = s.solve(b, rtol=rtol, max_iter=100000)
-            ms = (time.perf_counter() - t0) * 1e3
-            res["ladder"].append({
-                "precond": precond, "rtol": rtol, "iterations": it, "ms": ms,
-                "ms_per_iteration": ms / max(it, 1),
-                "mean_diff_vs_direct": (x - direct).abs().mean().item() / dmean,
-                "max_diff_vs_direct": (x - direct).abs().max().item() / direct.abs().max().item(),
-                "iteration_bytes": 88 * g.points,
-                "iteration_gbs": 88 * g.points * max(it, 1) / (ms * 1e-3) / 1e9})
-        s.close()
+    per_point = {"cg": 88, "bicgstab": 168}
+    for method in ("cg", "bicgstab"):
+        for precond in ("jacobi", "none"):
+            s = CGSolver(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.rho, precond=precond,
+                         method=method)
+            s.solve(b, rtol=1e-2)  # warm-up
+            for rtol in (1e-2, 1e-4, 1e-6, 1e-8):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, it, rel = s.solve(b, rtol=rtol, max_iter=100000)
+                ms = (time.perf_counter() - t0) * 1e3
+                nbytes = per_point[method] * g.points
+                res["ladder"].append({
+                    "method": method, "precond": precond, "rtol": rtol, "iterations": it,
+                    "ms": ms, "ms_per_iteration": ms / max(it, 1), "final_rel_res": rel,
+                    "mean_diff_vs_direct": (x - direct).abs().mean().item() / dmean,
+                    "max_diff_vs_direct":
+                        (x - direct).abs().max().item() / direct.abs().max().item(),
+                    "iteration_bytes": nbytes,
+                    "iteration_gbs": nbytes * max(it, 1) / (ms * 1e-3) / 1e9})
+            s.close()
     plan.close()
     return res
 

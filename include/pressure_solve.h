@@ -335,6 +335,22 @@ int ps_cg_create(ps_cg **out, int nx, int ny, int nz, double dx, double dy, cons
  * cannot be captured into a graph. */
 int ps_cg_solve(ps_cg *cg, const double *rhs, double *x, double rtol, int max_iter, int *iters,
                 double *rel_res);
+/* Krylov method of the object: PS_KRYLOV_CG (default) as above, or
+ * PS_KRYLOV_BICGSTAB, the paper's other bespoke solver (Section 2.2; its
+ * Table 2 compares the two): stabilised bi-conjugate gradients on A itself,
+ * which it does not need to be symmetric, with the projected right-hand side
+ * b' = b - mu, post-conditioned as the paper's is (right preconditioning by
+ * K, the diagonal of A for PS_CG_JACOBI or the identity: it solves
+ * A K^-1 y = b' and x = K^-1 y, so its residual is that of A x = b'); it
+ * stops when |b' - A x| <= rtol |b'| (the recurrence residual, tested after
+ * each half step) or after max_iter iterations of two operator applications
+ * each; the result is shifted to zero mean.  A breakdown (a zero inner
+ * product in a denominator) also stops it, with rel_res above rtol.
+ * Selecting BiCGStab the first time allocates its two further FP64 fields
+ * (synchronises).  Errors: PS_EINVAL (NULL, unknown method), PS_ENOMEM,
+ * PS_EHIP. */
+enum { PS_KRYLOV_CG = 0, PS_KRYLOV_BICGSTAB = 1 };
+int ps_cg_set_method(ps_cg *cg, int method);
 int ps_cg_set_stream(ps_cg *cg, void *stream);
 size_t ps_cg_workspace_bytes(const ps_cg *cg);
 int ps_cg_destroy(ps_cg *cg);

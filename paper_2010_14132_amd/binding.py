@@ -82,6 +82,7 @@ SIGNATURES = {
     "ps_cg_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _I,
                                    ctypes.POINTER(ctypes.c_double)]),
     "ps_cg_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "ps_cg_set_method": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ps_cg_workspace_bytes": (ctypes.c_size_t, [_vp]),
     "ps_cg_destroy": (ctypes.c_int, [_vp]),
     "ps_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -383,13 +384,15 @@ def poisson_solve(b, rho, plan: Plan):
 
 
 class CGSolver:
-    """Matrix-free conjugate gradients on the same operator as Plan (the C
-    ABI's ps_cg), FP64: preconditioner "none" or "jacobi".  solve() starts
-    from x (or zeros) and returns (x, iterations, relative residual)."""
+    """Matrix-free Krylov solver on the same operator as Plan (the C ABI's
+    ps_cg), FP64: method "cg" (on -D A) or "bicgstab" (on A, right
+    preconditioned), preconditioner "none" or "jacobi".  solve() starts from
+    x (or zeros) and returns (x, iterations, relative residual)."""
 
     PRECOND = {"none": 0, "jacobi": 1}
+    METHOD = {"cg": 0, "bicgstab": 1}
 
-    def __init__(self, nx, ny, nz, dx, dy, dz, rho, precond="jacobi"):
+    def __init__(self, nx, ny, nz, dx, dy, dz, rho, precond="jacobi", method="cg"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the pressure-solve library needs a GPU (no CPU fallback)")
@@ -403,6 +406,8 @@ class CGSolver:
                                _dptr(dz), _dptr(rho), self.PRECOND[precond], _stream_handle()),
               "ps_cg_create")
         self._h = h
+        check(lib.ps_cg_set_method(h, self.METHOD[method]), "ps_cg_set_method")
+        self.method = method
 
     @property
     def shape(self):

@@ -24,6 +24,20 @@
 // host reads the status only every few iterations.  All sums are per-block
 // partials in a fixed order, reduced in a fixed order: results do not depend
 // on scheduling.
+//
+// BiCGStab (van der Vorst's stabilised bi-conjugate gradients), the paper's
+// other bespoke Krylov solver, runs on A itself -- it needs no symmetric
+// operator -- with the projected right-hand side b' = b - mu, and is
+// post-conditioned as the paper's is (right preconditioning: it solves
+// A K^-1 y = b' and x = K^-1 y, K the diagonal of A or the identity, so the
+// residual it tracks is that of A x = b' itself).  An iteration is nine
+// launches: p = r + beta (p - omega v); v = A K^-1 p with the partials of
+// rh.v; alpha; x += alpha K^-1 p, s = r - alpha v with the partials of s.s;
+// the test on |s| (a half step can end the solve); t = A K^-1 s with the
+// partials of t.s and t.t; omega; x += omega K^-1 s, r = s - omega t with the
+// partials of rh.r and r.r; rho, beta and the test on |r|.  K^-1 multiplies
+// each value as it is loaded (a per-level factor), so neither K^-1 p nor
+// K^-1 s is stored.
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -48,7 +62,9 @@ struct CgState {
     double rhs2;    // |M-rhs|^2 = |D b'|^2
     double tol2;    // rtol^2 |M-rhs|^2
     double xmean;   // mean of x for the gauge
-    int done;       // 1 once converged (or max_iter reached)
+    double rho;     // BiCGStab: rh.r of the current residual
+    double omega;   // BiCGStab: the stabilising step
+    int done;       // 1 once converged (or max_iter reached, or a breakdown)
     int iters;      // completed iterations
     int max_iter;
     int pad;
@@ -98,6 +114,31 @@ __device__ __forceinline__ double diag_inv(const Geo &g, const double *__restric
 {
     if (!precond) return 1.0;
     return 1.0 / (D[k] * (2.0 * g.idx2 + 2.0 * g.idy2) + f[k] + f[k + 1]);
+}
+
+// (A y) at point c with y = K^-1 x (per-level factor kinv, 1 without a
+// preconditioner): the lateral second differences plus the vertical
+// operator, whose coefficients f_{k+1/2}/D_k and f_{k-1/2}/D_k are tabled
+// (au, ad; zero at the top and bottom faces).
+__device__ __forceinline__ double apply_ak(const double *__restrict__ x, const Geo &g,
+                                           const double *__restrict__ au,
+                                           const double *__restrict__ ad,
+                                           const double *__restrict__ kinv, unsigned c)
+{
+    const unsigned nxy = (unsigned)g.nx * (unsigned)g.ny;
+    const unsigned k = c / nxy, rem = c - k * nxy;
+    const unsigned j = rem / (unsigned)g.nx, i = rem - j * (unsigned)g.nx;
+    const double sk = kinv[k];
+    const unsigned row = c - i, lev = k * nxy;
+    const double xc = x[c] * sk;
+    const double xe = x[row + (i + 1 == (unsigned)g.nx ? 0u : i + 1)] * sk;
+    const double xw = x[row + (i == 0 ? (unsigned)g.nx - 1 : i - 1)] * sk;
+    const double xn = x[lev + (j + 1 == (unsigned)g.ny ? 0u : j + 1) * (unsigned)g.nx + i] * sk;
+    const double xs = x[lev + (j == 0 ? (unsigned)g.ny - 1 : j - 1) * (unsigned)g.nx + i] * sk;
+    const double xu = k + 1 < (unsigned)g.nz ? x[c + nxy] * kinv[k + 1] : xc;
+    const double xd = k > 0 ? x[c - nxy] * kinv[k - 1] : xc;
+    const double lat = ((xe - xc) + (xw - xc)) * g.idx2 + ((xn - xc) + (xs - xc)) * g.idy2;
+    return lat + au[k] * (xu - xc) + ad[k] * (xd - xc);
 }
 
 // Level sums of b, one block per level (fixed order).
@@ -314,16 +355,233 @@ __global__ __launch_bounds__(kThreads) void k_cg_shift(double *__restrict__ x, G
         x[c] -= m;
 }
 
+// ------------------------------------------------------------- BiCGStab
+// Tables of the BiCGStab kernels: au, ad and kinv, nz values each.
+struct BiTab {
+    const double *au, *ad, *kinv;
+};
+
+// r = rh = b' - A x0 (b' = b - mu), p = v = 0; partials of r.r and b'.b'.
+__global__ __launch_bounds__(kThreads) void k_bi_start(const double *__restrict__ b,
+                                                       const double *__restrict__ x, Geo g,
+                                                       BiTab tb, const double *__restrict__ one,
+                                                       double *__restrict__ r,
+                                                       double *__restrict__ rh,
+                                                       double *__restrict__ p,
+                                                       double *__restrict__ v,
+                                                       const CgState *__restrict__ st,
+                                                       double *__restrict__ part)
+{
+    __shared__ double red[4];
+    const double mu = st->mu;
+    double rr = 0.0, bb = 0.0;
+    for (unsigned c = blockIdx.x * blockDim.x + threadIdx.x; c < g.n;
+         c += gridDim.x * blockDim.x) {
+        const double rhs = b[c] - mu;
+        const double rc = rhs - apply_ak(x, g, tb.au, tb.ad, one, c);
+        r[c] = rc;
+        rh[c] = rc;
+        p[c] = 0.0;
+        v[c] = 0.0;
+        rr += rc * rc;
+        bb += rhs * rhs;
+    }
+    const double a = block_sum(rr, red), c2 = block_sum(bb, red);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = a;
+        part[gridDim.x + blockIdx.x] = c2;
+    }
+}
+
+// rho = rh.r = r.r, beta = 0 (so the first direction is r), alpha = omega = 1.
+__global__ __launch_bounds__(kThreads) void k_bi_start_scalars(const double *__restrict__ part,
+                                                               int nb, CgState *st, double rtol)
+{
+    __shared__ double v[2];
+    reduce_groups(part, nb, 2, v);
+    if (threadIdx.x == 0) {
+        st->rho = v[0];
+        st->rr = v[0];
+        st->rhs2 = v[1];
+        st->tol2 = rtol * rtol * v[1];
+        st->beta = 0.0;
+        st->alpha = 1.0;
+        st->omega = 1.0;
+        if (v[0] <= st->tol2 || st->max_iter <= 0) st->done = 1;
+    }
+}
+
+// p = r + beta (p - omega v).
+__global__ __launch_bounds__(kThreads) void k_bi_dir(double *__restrict__ p,
+                                                     const double *__restrict__ r,
+                                                     const double *__restrict__ v, Geo g,
+                                                     const CgState *__restrict__ st)
+{
+    if (st->done) return;
+    const double beta = st->beta, omega = st->omega;
+    for (unsigned c = blockIdx.x * blockDim.x + threadIdx.x; c < g.n;
+         c += gridDim.x * blockDim.x)
+        p[c] = r[c] + beta * (p[c] - omega * v[c]);
+}
+
+// out = A K^-1 in; partials of w1.out (and, with w2, of w2.out and out.out).
+__global__ __launch_bounds__(kThreads) void k_bi_apply(const double *__restrict__ in, Geo g,
+                                                       BiTab tb, double *__restrict__ out,
+                                                       const double *__restrict__ w1,
+                                                       int second,
+                                                       const CgState *__restrict__ st,
+                                                       double *__restrict__ part)
+{
+    if (st->done) return;
+    __shared__ double red[4];
+    double d1 = 0.0, d2 = 0.0;
+    for (unsigned c = blockIdx.x * blockDim.x + threadIdx.x; c < g.n;
+         c += gridDim.x * blockDim.x) {
+        const double o = apply_ak(in, g, tb.au, tb.ad, tb.kinv, c);
+        out[c] = o;
+        d1 += w1[c] * o;
+        d2 += o * o;
+    }
+    const double a = block_sum(d1, red);
+    const double b = second ? block_sum(d2, red) : 0.0;
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = a;
+        if (second) part[gridDim.x + blockIdx.x] = b;
+    }
+}
+
+// alpha = rho / rh.v (a zero rh.v is a breakdown: the solve stops).
+__global__ __launch_bounds__(kThreads) void k_bi_alpha(const double *__restrict__ part, int nb,
+                                                       CgState *st)
+{
+    if (st->done) return;
+    __shared__ double v[1];
+    reduce_groups(part, nb, 1, v);
+    if (threadIdx.x == 0) {
+        if (v[0] == 0.0 || !isfinite(v[0])) {
+            st->done = 1;
+            return;
+        }
+        st->alpha = st->rho / v[0];
+    }
+}
+
+// x += alpha K^-1 p, r := s = r - alpha v; partials of s.s.
+__global__ __launch_bounds__(kThreads) void k_bi_half(double *__restrict__ x,
+                                                      const double *__restrict__ p,
+                                                      double *__restrict__ r,
+                                                      const double *__restrict__ v, Geo g,
+                                                      BiTab tb, const CgState *__restrict__ st,
+                                                      double *__restrict__ part)
+{
+    if (st->done) return;
+    __shared__ double red[4];
+    const unsigned nxy = (unsigned)g.nx * (unsigned)g.ny;
+    const double alpha = st->alpha;
+    double ss = 0.0;
+    for (unsigned c = blockIdx.x * blockDim.x + threadIdx.x; c < g.n;
+         c += gridDim.x * blockDim.x) {
+        x[c] += alpha * (p[c] * tb.kinv[c / nxy]);
+        const double sc = r[c] - alpha * v[c];
+        r[c] = sc;
+        ss += sc * sc;
+    }
+    const double a = block_sum(ss, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = a;
+}
+
+// The half-step test: |s| small ends the solve with x as it stands.
+__global__ __launch_bounds__(kThreads) void k_bi_half_test(const double *__restrict__ part,
+                                                           int nb, CgState *st)
+{
+    if (st->done) return;
+    __shared__ double v[1];
+    reduce_groups(part, nb, 1, v);
+    if (threadIdx.x == 0 && v[0] <= st->tol2) {
+        st->rr = v[0];
+        st->iters += 1;
+        st->done = 1;
+    }
+}
+
+// omega = t.s / t.t (a zero t.t is a breakdown: the solve stops).
+__global__ __launch_bounds__(kThreads) void k_bi_omega(const double *__restrict__ part, int nb,
+                                                       CgState *st)
+{
+    if (st->done) return;
+    __shared__ double v[2];
+    reduce_groups(part, nb, 2, v);
+    if (threadIdx.x == 0) {
+        if (v[1] == 0.0 || !isfinite(v[1])) {
+            st->done = 1;
+            return;
+        }
+        st->omega = v[0] / v[1];
+    }
+}
+
+// x += omega K^-1 s, r = s - omega t; partials of rh.r and r.r.
+__global__ __launch_bounds__(kThreads) void k_bi_update(double *__restrict__ x,
+                                                        double *__restrict__ r,
+                                                        const double *__restrict__ t,
+                                                        const double *__restrict__ rh, Geo g,
+                                                        BiTab tb,
+                                                        const CgState *__restrict__ st,
+                                                        double *__restrict__ part)
+{
+    if (st->done) return;
+    __shared__ double red[4];
+    const unsigned nxy = (unsigned)g.nx * (unsigned)g.ny;
+    const double omega = st->omega;
+    double rhr = 0.0, rr = 0.0;
+    for (unsigned c = blockIdx.x * blockDim.x + threadIdx.x; c < g.n;
+         c += gridDim.x * blockDim.x) {
+        const double sc = r[c];
+        x[c] += omega * (sc * tb.kinv[c / nxy]);
+        const double rc = sc - omega * t[c];
+        r[c] = rc;
+        rhr += rh[c] * rc;
+        rr += rc * rc;
+    }
+    const double a = block_sum(rhr, red), b = block_sum(rr, red);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = a;
+        part[gridDim.x + blockIdx.x] = b;
+    }
+}
+
+// rho, beta = (rho_new / rho) (alpha / omega), the iteration count and the
+// test on |r| (a zero rho_new is a breakdown: the solve stops).
+__global__ __launch_bounds__(kThreads) void k_bi_rho(const double *__restrict__ part, int nb,
+                                                     CgState *st)
+{
+    if (st->done) return;
+    __shared__ double v[2];
+    reduce_groups(part, nb, 2, v);
+    if (threadIdx.x == 0) {
+        st->rr = v[1];
+        st->iters += 1;
+        if (v[1] <= st->tol2 || st->iters >= st->max_iter || v[0] == 0.0 || st->omega == 0.0) {
+            st->done = 1;
+            return;
+        }
+        st->beta = (v[0] / st->rho) * (st->alpha / st->omega);
+        st->rho = v[0];
+    }
+}
+
 } // namespace
 
 struct ps_cg {
     Geo g{};
     int precond = 0;
+    int method = PS_KRYLOV_CG;
     hipStream_t stream = nullptr;
     int nblk = 1;
-    double *f = nullptr; // [f (nz+1) | D (nz)]
+    double *f = nullptr; // [f (nz+1) | D (nz) | au (nz) | ad (nz) | kinv (nz) | ones (nz)]
     double *S = nullptr, *part = nullptr;
     double *r = nullptr, *p = nullptr, *q = nullptr;
+    double *rh = nullptr, *t = nullptr; // BiCGStab only (allocated when selected)
     CgState *st = nullptr;
     CgState *host = nullptr; // pinned copy of the state
     size_t bytes = 0;
@@ -331,10 +589,17 @@ struct ps_cg {
 
 static int cfail(int code, const std::string &msg) { return ps::set_error(code, msg); }
 
+#define PS_CHIP_EARLY(call)                                                                        \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return cfail(PS_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));              \
+    } while (0)
+
 static void free_cg(ps_cg *c)
 {
     for (void *q : {(void *)c->f, (void *)c->S, (void *)c->part, (void *)c->r, (void *)c->p,
-                    (void *)c->q, (void *)c->st})
+                    (void *)c->q, (void *)c->rh, (void *)c->t, (void *)c->st})
         if (q) (void)hipFree(q);
     if (c->host) (void)hipHostFree(c->host);
     delete c;
@@ -360,10 +625,20 @@ extern "C" int ps_cg_create(ps_cg **out, int nx, int ny, int nz, double dx, doub
     c->precond = precond;
     c->stream = reinterpret_cast<hipStream_t>(stream);
     c->nblk = (int)std::min<long long>(kMaxBlocks, ((long long)c->g.n + kThreads - 1) / kThreads);
-    std::vector<double> fd(2 * (size_t)nz + 1, 0.0); // [f (nz+1) | D (nz)]
+    // [f (nz+1) | D (nz) | au (nz) | ad (nz) | kinv (nz) | ones (nz)]
+    std::vector<double> fd(6 * (size_t)nz + 1, 0.0);
     for (int k = 0; k + 1 < nz; ++k)
         fd[k + 1] = 0.5 * (rho[k] + rho[k + 1]) / (0.5 * (dz[k] + dz[k + 1]));
-    for (int k = 0; k < nz; ++k) fd[nz + 1 + k] = rho[k] * dz[k];
+    for (int k = 0; k < nz; ++k) {
+        const double D = rho[k] * dz[k];
+        fd[nz + 1 + k] = D;
+        fd[2 * nz + 1 + k] = fd[k + 1] / D;
+        fd[3 * nz + 1 + k] = fd[k] / D;
+        // the diagonal of A: -(2/dx^2 + 2/dy^2) - (f_{k-1/2} + f_{k+1/2}) / D_k
+        const double diag = -(2.0 / (dx * dx) + 2.0 / (dy * dy)) - (fd[k] + fd[k + 1]) / D;
+        fd[4 * nz + 1 + k] = precond == PS_CG_JACOBI ? 1.0 / diag : 1.0;
+        fd[5 * nz + 1 + k] = 1.0;
+    }
     auto alloc = [&](double **ptr, size_t n) {
         void *q = nullptr;
         if (hipMalloc(&q, n * sizeof(double)) != hipSuccess) return false;
@@ -400,6 +675,27 @@ extern "C" int ps_cg_destroy(ps_cg *c)
     return PS_OK;
 }
 
+extern "C" int ps_cg_set_method(ps_cg *c, int method)
+{
+    if (!c) return cfail(PS_EINVAL, "cg is NULL");
+    if (method != PS_KRYLOV_CG && method != PS_KRYLOV_BICGSTAB)
+        return cfail(PS_EINVAL, "method must be PS_KRYLOV_CG or PS_KRYLOV_BICGSTAB");
+    if (method == PS_KRYLOV_BICGSTAB && !c->rh) {
+        PS_CHIP_EARLY(hipStreamSynchronize(c->stream));
+        void *a = nullptr, *b = nullptr;
+        const size_t n = (size_t)c->g.n * sizeof(double);
+        if (hipMalloc(&a, n) != hipSuccess || hipMalloc(&b, n) != hipSuccess) {
+            if (a) (void)hipFree(a);
+            return cfail(PS_ENOMEM, "hipMalloc of the BiCGStab vectors failed");
+        }
+        c->rh = reinterpret_cast<double *>(a);
+        c->t = reinterpret_cast<double *>(b);
+        c->bytes += 2 * n;
+    }
+    c->method = method;
+    return PS_OK;
+}
+
 extern "C" int ps_cg_set_stream(ps_cg *c, void *stream)
 {
     if (!c) return cfail(PS_EINVAL, "cg is NULL");
@@ -431,16 +727,42 @@ extern "C" int ps_cg_solve(ps_cg *c, const double *rhs, double *x, double rtol, 
     if (max_iter < 0) return cfail(PS_EINVAL, "max_iter must be >= 0");
     const Geo g = c->g;
     const double *f = c->f, *D = c->f + g.nz + 1;
+    const BiTab tb{c->f + 2 * g.nz + 1, c->f + 3 * g.nz + 1, c->f + 4 * g.nz + 1};
+    const double *ones = c->f + 5 * g.nz + 1;
     const int nb = c->nblk, pc = c->precond;
+    const bool bi = c->method == PS_KRYLOV_BICGSTAB;
     hipStream_t s = c->stream;
     PS_CLAUNCH(k_cg_levelsum, dim3(g.nz), dim3(kThreads), 0, s, rhs, g, c->S);
     PS_CLAUNCH(k_cg_setup, dim3(1), dim3(1), 0, s, c->S, D, g, c->st, max_iter);
-    PS_CLAUNCH(k_cg_start, dim3(nb), dim3(kThreads), 0, s, rhs, x, g, f, D, c->r, c->p, c->st,
-               c->part, pc);
-    PS_CLAUNCH(k_cg_start_scalars, dim3(1), dim3(kThreads), 0, s, c->part, nb, c->st, rtol);
+    if (bi) {
+        PS_CLAUNCH(k_bi_start, dim3(nb), dim3(kThreads), 0, s, rhs, x, g, tb, ones, c->r, c->rh,
+                   c->p, c->q, c->st, c->part);
+        PS_CLAUNCH(k_bi_start_scalars, dim3(1), dim3(kThreads), 0, s, c->part, nb, c->st, rtol);
+    } else {
+        PS_CLAUNCH(k_cg_start, dim3(nb), dim3(kThreads), 0, s, rhs, x, g, f, D, c->r, c->p,
+                   c->st, c->part, pc);
+        PS_CLAUNCH(k_cg_start_scalars, dim3(1), dim3(kThreads), 0, s, c->part, nb, c->st, rtol);
+    }
     for (int it = 0;;) {
         const int n = std::min(kChunk, std::max(1, max_iter - it));
         for (int i = 0; i < n; ++i) {
+            if (bi) {
+                // v = c->q; s overwrites r in place
+                PS_CLAUNCH(k_bi_dir, dim3(nb), dim3(kThreads), 0, s, c->p, c->r, c->q, g, c->st);
+                PS_CLAUNCH(k_bi_apply, dim3(nb), dim3(kThreads), 0, s, c->p, g, tb, c->q, c->rh,
+                           0, c->st, c->part);
+                PS_CLAUNCH(k_bi_alpha, dim3(1), dim3(kThreads), 0, s, c->part, nb, c->st);
+                PS_CLAUNCH(k_bi_half, dim3(nb), dim3(kThreads), 0, s, x, c->p, c->r, c->q, g, tb,
+                           c->st, c->part);
+                PS_CLAUNCH(k_bi_half_test, dim3(1), dim3(kThreads), 0, s, c->part, nb, c->st);
+                PS_CLAUNCH(k_bi_apply, dim3(nb), dim3(kThreads), 0, s, c->r, g, tb, c->t, c->r, 1,
+                           c->st, c->part);
+                PS_CLAUNCH(k_bi_omega, dim3(1), dim3(kThreads), 0, s, c->part, nb, c->st);
+                PS_CLAUNCH(k_bi_update, dim3(nb), dim3(kThreads), 0, s, x, c->r, c->t, c->rh, g,
+                           tb, c->st, c->part);
+                PS_CLAUNCH(k_bi_rho, dim3(1), dim3(kThreads), 0, s, c->part, nb, c->st);
+                continue;
+            }
             PS_CLAUNCH(k_cg_apply, dim3(nb), dim3(kThreads), 0, s, c->p, g, f, D, c->q, c->st,
                        c->part);
             PS_CLAUNCH(k_cg_alpha, dim3(1), dim3(kThreads), 0, s, c->part, nb, c->st);

@@ -160,6 +160,7 @@ def test_new_entry_points_reject_bad_arguments_before_any_hip_call(lib):
     assert lib.ps_cg_create(ctypes.byref(h), 8, 8, 8, 50.0, 50.0, binding._dptr(bad),
                             binding._dptr(rho), 1, None) == 1
     assert lib.ps_cg_solve(None, None, None, 1e-6, 10, None, None) == 1
+    assert lib.ps_cg_set_method(None, 1) == 1
     assert lib.ps_cg_destroy(None) == 0
     assert lib.ps_cg_workspace_bytes(None) == 0
     assert lib.ps_solve_zyx(None, None, None, 0) == 1

@@ -43,3 +43,38 @@ def test_jacobi_helps_and_warm_start_stops():
     exact = oracle.solve(b, g.dx, g.dy, g.dz, g.rho)
     _, it0, rel0, _ = cg.pcg(b, g.dx, g.dy, g.dz, g.rho, 1e-8, 5000, "jacobi", x0=exact)
     assert it0 == 0 and rel0 < 1e-8
+
+
+@pytest.mark.parametrize("shape,seed", [((6, 8, 10), 1), ((9, 12, 16), 2), ((1, 8, 8), 3),
+                                        ((12, 1, 6), 4)])
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_reference_bicgstab_converges_to_the_direct_solve(shape, seed, precond):
+    """The numpy BiCGStab reference on A itself (not symmetric on these
+    stretched grids) reaches the oracle's exact solution of the bordered
+    system, with its true residual within the tolerance."""
+    nz, ny, nx = shape
+    g = grid(nx, ny, nz, seed)
+    b = np.random.default_rng(seed + 10).standard_normal(shape) + 0.5
+    want = oracle.solve(b, g.dx, g.dy, g.dz, g.rho)
+    x, it, rel, hist = cg.bicgstab(b, g.dx, g.dy, g.dz, g.rho, 1e-12, 5000, precond)
+    assert rel <= 1e-12 and it < 5000
+    assert cg.true_relative_residual_a(x, b, g.dx, g.dy, g.dz, g.rho) < 1e-10
+    assert np.abs(x - want).max() < 1e-8 * np.abs(want).max()
+
+
+def test_bicgstab_warm_start_and_nonsymmetric_operator():
+    g = grid(16, 16, 24, 5)
+    b = np.random.default_rng(6).standard_normal((24, 16, 16))
+    exact = oracle.solve(b, g.dx, g.dy, g.dz, g.rho)
+    _, it0, rel0, _ = cg.bicgstab(b, g.dx, g.dy, g.dz, g.rho, 1e-8, 5000, "jacobi", x0=exact)
+    assert it0 == 0 and rel0 < 1e-8
+    # A is not symmetric on a stretched grid (so BiCGStab, not CG, applies
+    # to it directly) while -D A is
+    rng = np.random.default_rng(7)
+    u, w = rng.standard_normal((2, 24, 16, 16))
+    au = oracle.apply(u, g.dx, g.dy, g.dz, g.rho)
+    aw = oracle.apply(w, g.dx, g.dy, g.dz, g.rho)
+    assert abs((w * au).sum() - (u * aw).sum()) > 1e-6 * np.abs(w * au).sum()
+    mu = cg.m_apply(u, g.dx, g.dy, g.dz, g.rho)
+    mw = cg.m_apply(w, g.dx, g.dy, g.dz, g.rho)
+    assert abs((w * mu).sum() - (u * mw).sum()) < 1e-12 * np.abs(w * mu).sum()

@@ -1,8 +1,9 @@
-"""The HIP matrix-free CG (ps_cg, through the C ABI) against the numpy CG
-reference (the same algorithm in FP64: iteration counts and iterates) and
-against the oracle's direct solve (the exact solution it converges to), and
-the accuracy-versus-termination ladder of the paper's Table 1 on the
-256^2 x 64 workload, against the FP64 direct solve on the GPU."""
+"""The HIP matrix-free Krylov solvers (ps_cg, through the C ABI: CG on -D A
+and BiCGStab on A) against the numpy references (the same algorithms in
+FP64: iteration counts and iterates) and against the oracle's direct solve
+(the exact solution they converge to), and the accuracy-versus-termination
+ladder of the paper's Table 1 on the 256^2 x 64 workload, against the FP64
+direct solve on the GPU."""
 import time
 
 import numpy as np
@@ -28,9 +29,9 @@ def grid(nx, ny, nz, seed):
     return g
 
 
-def solver(g, precond):
+def solver(g, precond, method="cg"):
     from paper_2010_14132_amd import CGSolver
-    return CGSolver(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.rho, precond=precond)
+    return CGSolver(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.rho, precond=precond, method=method)
 
 
 SHAPES = [(6, 8, 10), (9, 12, 16), (1, 8, 8), (12, 1, 6), (16, 48, 64), (5, 7, 3), (33, 20, 24)]
@@ -62,6 +63,51 @@ def test_cg_matches_reference_and_oracle(shape, precond):
     s.close()
 
 
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_bicgstab_matches_reference_and_oracle(shape, precond):
+    """BiCGStab on the non-symmetric A against the numpy reference (the same
+    steps in FP64: iteration counts) and the oracle's direct solve."""
+    nz, ny, nx = shape
+    announce("bicgstab %s %s" % (precond, shape))
+    g = grid(nx, ny, nz, seed=nz + ny)
+    b = np.random.default_rng(7).standard_normal(shape) + 0.5  # incompatible
+    s = solver(g, precond, "bicgstab")
+    for rtol in (1e-6, 1e-12):
+        x, it, rel = s.solve(torch.from_numpy(b).cuda(), rtol=rtol, max_iter=20000)
+        x = x.cpu().numpy()
+        xr, itr, relr, _ = cgr.bicgstab(b, g.dx, g.dy, g.dz, g.rho, rtol, 20000, precond)
+        print("rtol %.0e: %d iterations (reference %d), recurrence residual %.2e"
+              % (rtol, it, itr, rel))
+        assert rel <= rtol and it < 20000
+        # same algorithm in FP64; only the rounding of the sums differs
+        assert abs(it - itr) <= max(3, itr // 7), (it, itr)
+        assert cgr.true_relative_residual_a(x, b, g.dx, g.dy, g.dz, g.rho) < 10 * rtol
+        assert abs(x.mean()) < 1e-12 * np.abs(x).max()
+    want = oracle.solve(b, g.dx, g.dy, g.dz, g.rho)
+    err = np.abs(x - want).max() / np.abs(want).max()
+    print("rtol 1e-12: rel_max against the direct solve %.2e" % err)
+    assert err < 1e-6
+    s.close()
+
+
+def test_bicgstab_warm_start_and_max_iter():
+    g = grid(32, 32, 16, seed=3)
+    b = np.random.default_rng(8).standard_normal((16, 32, 32))
+    exact = oracle.solve(b, g.dx, g.dy, g.dz, g.rho)
+    s = solver(g, "jacobi", "bicgstab")
+    bt = torch.from_numpy(b).cuda()
+    x, it, rel = s.solve(bt, x=torch.from_numpy(exact).cuda(), rtol=1e-8)
+    assert it == 0 and rel < 1e-8
+    x, it, rel = s.solve(bt, rtol=1e-14, max_iter=5)
+    assert it == 5 and rel > 1e-14
+    xr, itr, relr, _ = cgr.bicgstab(b, g.dx, g.dy, g.dz, g.rho, 1e-14, 5, "jacobi")
+    assert itr == 5
+    assert np.abs(x.cpu().numpy() - xr).max() < 1e-10 * np.abs(xr).max()
+    assert abs(rel - relr) < 1e-6 * relr
+    s.close()
+
+
 def test_cg_warm_start_and_max_iter():
     g = grid(32, 32, 16, seed=3)
     b = np.random.default_rng(8).standard_normal((16, 32, 32))
@@ -79,8 +125,9 @@ def test_cg_warm_start_and_max_iter():
 
 def test_table1_ladder_256():
     """Relative-residual terminations 1e-2 ... 1e-8 on the 256^2 x 64
-    stretched workload: iterations grow, the difference from the direct
-    solve (FP64 GPU) shrinks (the trend of the paper's Table 1)."""
+    stretched workload, CG and BiCGStab: iterations grow, the difference
+    from the direct solve (FP64 GPU) shrinks (the trend of the paper's
+    Table 1)."""
     from paper_2010_14132_amd import Plan
     prob = wl.plain_256()
     g = prob.grid
@@ -91,19 +138,22 @@ def test_table1_ladder_256():
     d = direct.abs().mean().item()
     announce("Table 1 ladder, 256^2x64")
     rows, last = [], None
-    for precond in ("jacobi", "none"):
-        s = solver(g, precond)
-        for rtol in (1e-2, 1e-4, 1e-6, 1e-8):
-            t = time.perf_counter()
-            x, it, rel = s.solve(b, rtol=rtol, max_iter=50000)
-            ms = (time.perf_counter() - t) * 1e3
-            mean_diff = (x - direct).abs().mean().item() / d
-            rows.append((precond, rtol, it, ms, mean_diff))
-            print("%-6s rtol %.0e: %5d iterations %8.2f ms, mean |x - direct| / mean |direct| %.3e"
-                  % (precond, rtol, it, ms, mean_diff))
-            if precond == "jacobi":
+    for method in ("cg", "bicgstab"):
+        for precond in ("jacobi", "none"):
+            s = solver(g, precond, method)
+            last = None
+            for rtol in (1e-2, 1e-4, 1e-6, 1e-8):
+                t = time.perf_counter()
+                x, it, rel = s.solve(b, rtol=rtol, max_iter=50000)
+                ms = (time.perf_counter() - t) * 1e3
+                mean_diff = (x - direct).abs().mean().item() / d
+                rows.append((method, precond, rtol, it, ms, mean_diff))
+                print("%-8s %-6s rtol %.0e: %5d iterations %8.2f ms, "
+                      "mean |x - direct| / mean |direct| %.3e"
+                      % (method, precond, rtol, it, ms, mean_diff))
+                assert rel <= rtol
                 if last is not None:
                     assert it > last[0] and mean_diff < last[1]
                 last = (it, mean_diff)
-        s.close()
-    assert last[1] < 1e-3
+            assert last[1] < 1e-3
+            s.close()
