@@ -326,10 +326,12 @@ def config_forms(prob, forms, steps, warmup, oracle_ref=True):
 
 def config_monc_layout(prob, steps, warmup):
     """The headline workload with its fields in MONC's z-fastest layout
-    ([nx][ny][nz]): ps_solve_zyx (transposes inside the x passes) against the
-    level-major solve preceded and followed by explicit layout copies (what
-    a caller would otherwise run), FP32 with the in-register refinement,
-    autotuned; per-kernel event times of the z-fastest x passes."""
+    ([nx][ny][nz]): ps_solve_zyx (x passes between the field and a
+    [kx][j][k] buffer, y passes between that buffer and the spectrum, so
+    40 B/pt as the level-major solve) against the level-major solve
+    preceded and followed by explicit layout copies (torch permute copies,
+    what a caller would otherwise run), FP32 with the in-register
+    refinement, autotuned; per-pass event times (8 B/pt each)."""
     import torch
     from paper_2010_14132_amd import Plan
     g = prob.grid
@@ -355,15 +357,16 @@ def config_monc_layout(prob, steps, warmup):
     plan.profile(False)
     N = g.points
     xk = {}
-    for name in ("fwd_x", "inv_x"):
+    for name in ("fwd_x", "fft_y_fwd", "fft_y_inv", "inv_x"):
         if name in kern:
             tot, n = kern[name]
             ms = tot / steps
             xk[name] = {"ms_per_solve": ms, "gbs": 8.0 * N / (ms * 1e-3) / 1e9}
     res = {"zyx_ms_per_solve": zyx, "solves_per_s": 1e3 / zyx, "mpts_per_s": N / zyx / 1e3,
+           "whole_solve_hbm_frac": 40.0 * N / (zyx * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "level_major_ms": lm, "level_major_with_two_transposes_ms": unf,
            "speedup_vs_transposes": unf / zyx, "zyx_kc": plan.info()["zyx_kc"],
-           "x_passes": xk}
+           "passes": xk}
     plan.close()
     return res
 

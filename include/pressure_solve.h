@@ -125,10 +125,16 @@ int ps_solve(ps_plan *plan, const void *rhs, void *p);
 
 /* ps_solve (adjoint = 0) or ps_solve_adjoint (adjoint != 0) for fields in
  * MONC's own layout p%data(z,y,x) (Section 2.2's Fortran field, z fastest):
- * element (i, j, k) at (i ny + j) nz + k, element type as for ps_solve.  The
- * transposes between the columns and the transform rows are done in LDS
- * inside the two x passes (no extra pass over HBM); the rest is ps_solve's.
- * rhs and p may alias.  PS_FP32_R1 plans give PS_EUNSUPPORTED. */
+ * element (i, j, k) at (i ny + j) nz + k, element type as for ps_solve.  No
+ * extra pass over HBM: with the register-resident transforms (the plan's x
+ * and y variants >= 1) the x passes move between the field and a plan-owned
+ * [kx][j][k] buffer (loads and stores along k, staged in LDS) and the y
+ * passes between that buffer and the spectrum; otherwise the x passes
+ * transpose between columns and rows in LDS around ps_solve's y and column
+ * passes.  The first call on a plan of the first kind allocates that buffer
+ * (the size of the spectrum; synchronises): call it once before capturing
+ * it into a graph.  rhs and p may alias.  PS_FP32_R1 plans give
+ * PS_EUNSUPPORTED. */
 int ps_solve_zyx(ps_plan *plan, const void *rhs, void *p, int adjoint);
 
 /* One pressure-projection step of the dynamical core around the solve

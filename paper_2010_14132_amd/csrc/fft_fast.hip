@@ -81,6 +81,73 @@ __global__ __launch_bounds__(NT) void k_fft_y_fast(cx_t<T> *__restrict__ spec, i
     }
 }
 
+// y passes of the z-fastest solve, between the [kx][j][k] layout (k
+// fastest; written and read by the z-fastest x passes) and the spectrum
+// spec[k][kx][ky].  A block takes RB = NT / R1 consecutive levels of one kx
+// (tiles level-chunk fastest, XCD-contiguous).  Forward: the rows are
+// gathered into an LDS staging by loads along k, transformed, and stored
+// into the spectrum along ky.  Backward: spectrum rows are loaded along ky,
+// transformed, staged in LDS and stored along k.  Levels past the last read
+// level nz - 1 and are never stored.  The row transform is k_fft_y_fast's.
+template <typename T, int R1, int R2, int DIR, int NT>
+__global__ __launch_bounds__(NT) void k_fft_y_zyx(const cx_t<T> *__restrict__ src,
+                                                  cx_t<T> *__restrict__ dst, int nz, int nkx,
+                                                  const cx_t<T> *__restrict__ tw4)
+{
+    using C = cx_t<T>;
+    constexpr int L = R1 * R2, RB = NT / R1, S = four_step_stride<R1, R2, T>();
+    constexpr int SW = L + 2; // complex values per staged row
+    constexpr int SA = RB * S, SB = 2 * RB * SW;
+    __shared__ T lds[SA > SB ? SA : SB];
+    C *stg = reinterpret_cast<C *>(lds);
+    const int r = threadIdx.x / R1, t = threadIdx.x - r * R1;
+    const int nkc = (nz + RB - 1) / RB;
+    const int tile = tile_of(blockIdx.x, gridDim.x, 1);
+    const int kx = tile / nkc, k0 = (tile % nkc) * RB, k = k0 + r;
+    C v[R2], w[R2];
+    if constexpr (DIR < 0) {
+        const C *base = src + (long)kx * L * nz + k0;
+#pragma unroll 8
+        for (int e = threadIdx.x; e < RB * L; e += NT) {
+            const int kk = e % RB, jj = e / RB;
+            const int kq = k0 + kk < nz ? kk : nz - 1 - k0;
+            stg[kk * SW + jj] = base[(long)jj * nz + kq];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < R2; ++q) v[q] = stg[r * SW + t + R1 * q];
+        __syncthreads(); // the staging is read before the transform reuses it
+    } else {
+        const C *row = src + ((long)(k < nz ? k : nz - 1) * nkx + kx) * L;
+#pragma unroll
+        for (int q = 0; q < R2; ++q) v[q] = row[t + R1 * q];
+    }
+    four_step<R1, R2, DIR>(v, w, t, lds + r * S, tw4);
+    if constexpr (DIR < 0) {
+        if (k < nz) {
+            C *row = dst + ((long)k * nkx + kx) * L;
+#pragma unroll
+            for (int j = 0; j < R2 / R1; ++j)
+#pragma unroll
+                for (int k1 = 0; k1 < R1; ++k1)
+                    nt_store<T>(w[j * R1 + k1], &row[(t + R1 * j) + R2 * k1]);
+        }
+    } else {
+        __syncthreads(); // the transform's last LDS reads are done
+#pragma unroll
+        for (int j = 0; j < R2 / R1; ++j)
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) stg[r * SW + (t + R1 * j) + R2 * k1] = w[j * R1 + k1];
+        __syncthreads();
+        C *base = dst + (long)kx * L * nz + k0;
+#pragma unroll 8
+        for (int e = threadIdx.x; e < RB * L; e += NT) {
+            const int kk = e % RB, jj = e / RB;
+            if (k0 + kk < nz) base[(long)jj * nz + kk] = stg[kk * SW + jj];
+        }
+    }
+}
+
 // ---------------------------------------------------------------- x forward
 // ROWS rows per block, R1 lanes per row.  Loads z_n = x_{2n} + i x_{2n+1},
 // records FP64 row sums, transforms, applies the even/odd split with one
@@ -108,6 +175,12 @@ __global__ __launch_bounds__(NT) void k_fft_y_fast(cx_t<T> *__restrict__ spec, i
 // comes from the neighbouring lane as in RES.
 // PAIR (R1 = 2 R2): the row transform is four_step_pair, whose output slot
 // kk of lane t = 2m + h is X[m + R2 kk + R2^2 h].
+// ZYX: the input is a field in the z-fastest layout ([nx][ny][nz]) and the
+// output the [kx][j][k] layout (k fastest) that the z-fastest y pass reads:
+// a block's rows are ROWS consecutive levels k of one row j (tiles level-
+// chunk fastest, so that neighbouring level chunks of a row meet in one L2),
+// its loads run along k into an LDS staging of the rows, and its stores run
+// along k (ROWS values per (kx, j)).  The row transform is unchanged.
 template <int R1, int R2, bool PAIR> __device__ __forceinline__ int out_index(int t, int i)
 {
     if constexpr (PAIR)
@@ -123,7 +196,15 @@ template <int R1, int R2, typename T, bool PAIR> constexpr int row_stride()
         return four_step_stride<R1, R2, T>();
 }
 
-template <typename T, int R1, int R2, int ROWS, bool RES, bool PAIR = false, bool DIV = false>
+template <int R1, int R2, int ROWS, typename T, bool PAIR, bool ZYX> constexpr int r2c_lds()
+{
+    constexpr int A = ROWS * row_stride<R1, R2, T, PAIR>(), B = R1 * R2 * ROWS;
+    constexpr int Z = ZYX ? ROWS * (2 * R1 * R2 + 2) : 0;
+    return A > B ? (A > Z ? A : Z) : (B > Z ? B : Z);
+}
+
+template <typename T, int R1, int R2, int ROWS, bool RES, bool PAIR = false, bool DIV = false,
+          bool ZYX = false>
 __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
                                                       cx_t<T> *__restrict__ spec,
                                                       double *__restrict__ rowsum, int ny,
@@ -136,18 +217,38 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
                                                       double scale)
 {
     using C = cx_t<T>;
+    static_assert(!ZYX || (!RES && !DIV), "the z-fastest pass has no fused residual");
     constexpr int L = R1 * R2, NT = ROWS * R1, S = row_stride<R1, R2, T, PAIR>();
-    constexpr int A = ROWS * S, B = L * ROWS;
-    __shared__ T lds[A > B ? A : B];
+    __shared__ T lds[r2c_lds<R1, R2, ROWS, T, PAIR, ZYX>()];
     const int r = threadIdx.x / R1, t = threadIdx.x - r * R1;
     const long tile = tile_of(blockIdx.x, gridDim.x, swz);
+    // ZYX: tile = (level chunk kc, row j), kc fastest
+    const int nkc = ZYX ? (nz + ROWS - 1) / ROWS : 1;
+    const int zj = ZYX ? (int)(tile / nkc) : 0, zk0 = ZYX ? (int)(tile % nkc) * ROWS : 0;
     const long g0 = korder ? (tile % nz) * (long)ny + (tile / nz) * ROWS : tile * ROWS;
-    const long g = g0 + r;
-    const bool ok = g < nrows;
-    const C *src = reinterpret_cast<const C *>(in) + (ok ? g : 0) * (long)L;
+    const long g = ZYX ? (long)(zk0 + r) * ny + zj : g0 + r;
+    const bool ok = ZYX ? zk0 + r < nz : g < nrows;
+    const C *src = reinterpret_cast<const C *>(in) + (ok && !ZYX ? g : 0) * (long)L;
     C v[R2], w[PAIR ? 1 : R2];
     double s = 0.0;
-    if constexpr (DIV) {
+    if constexpr (ZYX) {
+        // rows past the last level read level nz - 1: transformed, never stored
+        constexpr int SW = 2 * L + 2;
+#pragma unroll 8
+        for (int e = threadIdx.x; e < ROWS * 2 * L; e += NT) {
+            const int kk = e % ROWS, i = e / ROWS;
+            const int kq = zk0 + kk < nz ? zk0 + kk : nz - 1;
+            lds[kk * SW + i] = in[((long)i * ny + zj) * nz + kq];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < R2; ++q) {
+            const int n = t + R1 * q;
+            v[q] = C{lds[r * SW + 2 * n], lds[r * SW + 2 * n + 1]};
+            s += (double)v[q].x + (double)v[q].y;
+        }
+        __syncthreads(); // the staging is read before the transform reuses it
+    } else if constexpr (DIV) {
         const long gg = ok ? g : 0;
         const int lev = (int)((unsigned)gg / (unsigned)ny), j = (int)(gg - (long)lev * ny);
         const double au = rc[3 * lev], ad = rc[3 * lev + 1];
@@ -310,6 +411,19 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
     }
     // as in k_c2r_fast: this thread's row rr is the same for every i
     static_assert(NT % ROWS == 0, "rows per block must divide the block");
+    if constexpr (ZYX) {
+        const int kz = zk0 + threadIdx.x % ROWS;
+        if (kz < nz) {
+            C *dst = spec + (long)zj * nz + kz; // [kx][j][k]
+            const long kstride = (long)ny * nz;
+#pragma unroll
+            for (int i = 0; i < R2; ++i) {
+                const int kx = threadIdx.x / ROWS + (NT / ROWS) * i;
+                dst[(long)kx * kstride] = C{outr[i], outi[i]};
+            }
+        }
+        return;
+    }
     const long g2 = g0 + threadIdx.x % ROWS;
     if (g2 < nrows) {
         const long lev = (unsigned)g2 / (unsigned)ny, jj = g2 - lev * ny; // rows < 2^31
@@ -326,19 +440,24 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
 // Gathers ROWS rows of the transposed spectrum through LDS, undoes the
 // packing, Z_k = (X_k + conj X_{L-k}) + i W_nx^{-k} (X_k - conj X_{L-k}),
 // transforms backwards and stores real rows (optionally accumulated).
-template <typename T, int R1, int R2, int ROWS, bool PAIR = false>
+// ZYX (nz > 0): the rows are ROWS consecutive levels of one row j read from
+// the [kx][j][k] layout (along k), and the result is staged in LDS and
+// stored along k into a z-fastest field ([nx][ny][nz]); no accumulation.
+template <typename T, int R1, int R2, int ROWS, bool PAIR = false, bool ZYX = false>
 __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict__ spec,
                                                       T *__restrict__ out, int ny, int nrows,
                                                       int accumulate,
                                                       const cx_t<T> *__restrict__ tw4,
-                                                      const cx_t<T> *__restrict__ tws, int swz)
+                                                      const cx_t<T> *__restrict__ tws, int swz,
+                                                      int nz = 0)
 {
     using C = cx_t<T>;
     constexpr int L = R1 * R2, NT = ROWS * R1, S = row_stride<R1, R2, T, PAIR>();
-    constexpr int A = ROWS * S, B = L * ROWS;
-    __shared__ T lds[A > B ? A : B];
+    __shared__ T lds[r2c_lds<R1, R2, ROWS, T, PAIR, ZYX>()];
     const int r = threadIdx.x / R1, t = threadIdx.x - r * R1;
     const long tile = tile_of(blockIdx.x, gridDim.x, swz);
+    const int nkc = ZYX ? (nz + ROWS - 1) / ROWS : 1;
+    const int zj = ZYX ? (int)(tile / nkc) : 0, zk0 = ZYX ? (int)(tile % nkc) * ROWS : 0;
     const long g = tile * ROWS + r;
     const bool ok = g < nrows;
 
@@ -349,7 +468,19 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
     // never stored.
     static_assert(NT % ROWS == 0, "rows per block must divide the block");
     T inr[R2], ini[R2];
-    {
+    if constexpr (ZYX) {
+        // levels past the last read level nz - 1: transformed, never stored
+        const int kz = zk0 + threadIdx.x % ROWS;
+        const C *src = spec + (long)zj * nz + (kz < nz ? kz : nz - 1);
+        const long kstride = (long)ny * nz;
+#pragma unroll
+        for (int i = 0; i < R2; ++i) {
+            const int kx = threadIdx.x / ROWS + (NT / ROWS) * i;
+            const C x = nt_load<T>(&src[(long)kx * kstride]);
+            inr[i] = x.x;
+            ini[i] = x.y;
+        }
+    } else {
         const int rr = threadIdx.x % ROWS;
         const long g2 = tile * ROWS + rr < nrows ? tile * ROWS + rr : 0;
         const long lev = (unsigned)g2 / (unsigned)ny, jj = g2 - lev * ny; // rows < 2^31
@@ -408,6 +539,23 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
     else
         four_step<R1, R2, 1>(v, w, t, lds + r * S, tw4);
     C *Z = PAIR ? v : w;
+    if constexpr (ZYX) {
+        constexpr int SW = 2 * L + 2;
+        __syncthreads(); // the transform's last LDS reads are done
+#pragma unroll
+        for (int i = 0; i < R2; ++i) {
+            const int c = out_index<R1, R2, PAIR>(t, i);
+            lds[r * SW + 2 * c] = Z[i].x;
+            lds[r * SW + 2 * c + 1] = Z[i].y;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int e = threadIdx.x; e < ROWS * 2 * L; e += NT) {
+            const int kk = e % ROWS, i = e / ROWS;
+            if (zk0 + kk < nz) out[((long)i * ny + zj) * nz + zk0 + kk] = lds[kk * SW + i];
+        }
+        return;
+    }
     if (ok) {
         C *dst = reinterpret_cast<C *>(out) + g * (long)L;
         if (accumulate) {
@@ -619,7 +767,85 @@ hipError_t launch_c2r_fast(const cx_t<T> *spec, T *out, int nx, int ny, int nz, 
 #undef PS_X
 }
 
+// The z-fastest solve's passes (fast lengths only).
+template <typename T, int R1, int R2>
+static hipError_t y_zyx(const cx_t<T> *src, cx_t<T> *dst, int nz, int nkx, int dir,
+                        const cx_t<T> *tw4, hipStream_t st)
+{
+    constexpr int NT = sizeof(T) == 8 && R1 * R2 >= 512 ? 128 : 256;
+    constexpr int RB = NT / R1;
+    const int grid = nkx * ((nz + RB - 1) / RB);
+    if (dir < 0)
+        hipLaunchKernelGGL((k_fft_y_zyx<T, R1, R2, -1, NT>), dim3(grid), dim3(NT), 0, st, src, dst,
+                           nz, nkx, tw4);
+    else
+        hipLaunchKernelGGL((k_fft_y_zyx<T, R1, R2, 1, NT>), dim3(grid), dim3(NT), 0, st, src, dst,
+                           nz, nkx, tw4);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fft_y_zyx(const cx_t<T> *src, cx_t<T> *dst, int nz, int nkx, int ny, int dir,
+                            const cx_t<T> *tw4, hipStream_t st)
+{
+#define PS_Y(a, b) y_zyx<T, a, b>(src, dst, nz, nkx, dir, tw4, st)
+    PS_FAST_SWITCH(ny, PS_Y)
+#undef PS_Y
+}
+
+template <typename T, int R1, int R2>
+static hipError_t x_zyx(const T *in, cx_t<T> *tmp, double *rowsum, const cx_t<T> *tmp_in,
+                        T *out, int ny, int nz, const cx_t<T> *tw4, const cx_t<T> *tws,
+                        int pair, hipStream_t st)
+{
+    if constexpr (R2 == 2 * R1) {
+        if (pair) {
+            constexpr int ROWS = x_rows<T, R2, R1, false, true>();
+            const int grid = ny * ((nz + ROWS - 1) / ROWS);
+            if (in)
+                hipLaunchKernelGGL((k_r2c_fast<T, R2, R1, ROWS, false, true, false, true>),
+                                   dim3(grid), dim3(ROWS * R2), 0, st, in, tmp, rowsum, ny,
+                                   ny * nz, tw4, tws, (const T *)nullptr, nz, 0.0, 0.0,
+                                   (const double *)nullptr, 1, 0, (const T *)nullptr, 1.0);
+            else
+                hipLaunchKernelGGL((k_c2r_fast<T, R2, R1, ROWS, true, true>), dim3(grid),
+                                   dim3(ROWS * R2), 0, st, tmp_in, out, ny, ny * nz, 0, tw4, tws,
+                                   1, nz);
+            return hipGetLastError();
+        }
+    }
+    constexpr int ROWS = x_rows<T, R1, R2, false>();
+    const int grid = ny * ((nz + ROWS - 1) / ROWS);
+    if (in)
+        hipLaunchKernelGGL((k_r2c_fast<T, R1, R2, ROWS, false, false, false, true>), dim3(grid),
+                           dim3(ROWS * R1), 0, st, in, tmp, rowsum, ny, ny * nz, tw4, tws,
+                           (const T *)nullptr, nz, 0.0, 0.0, (const double *)nullptr, 1, 0,
+                           (const T *)nullptr, 1.0);
+    else
+        hipLaunchKernelGGL((k_c2r_fast<T, R1, R2, ROWS, false, true>), dim3(grid),
+                           dim3(ROWS * R1), 0, st, tmp_in, out, ny, ny * nz, 0, tw4, tws, 1, nz);
+    return hipGetLastError();
+}
+
+// Forward (in != NULL: z-fastest field -> [kx][j][k], row sums) or backward
+// (in == NULL: [kx][j][k] -> z-fastest field) x pass; pair selects the
+// paired row transform where nx/2 = 2 s^2.
+template <typename T>
+hipError_t launch_x_zyx_fast(const T *in, cx_t<T> *tmp, double *rowsum, const cx_t<T> *tmp_in,
+                             T *out, int nx, int ny, int nz, const cx_t<T> *tw4,
+                             const cx_t<T> *tws, int pair, hipStream_t st)
+{
+#define PS_X(a, b) x_zyx<T, a, b>(in, tmp, rowsum, tmp_in, out, ny, nz, tw4, tws, pair, st)
+    PS_FAST_SWITCH(nx / 2, PS_X)
+#undef PS_X
+}
+
 #define PS_INST(T)                                                                                 \
+    template hipError_t launch_fft_y_zyx<T>(const cx_t<T> *, cx_t<T> *, int, int, int, int,      \
+                                            const cx_t<T> *, hipStream_t);                        \
+    template hipError_t launch_x_zyx_fast<T>(const T *, cx_t<T> *, double *, const cx_t<T> *,    \
+                                             T *, int, int, int, const cx_t<T> *,                 \
+                                             const cx_t<T> *, int, hipStream_t);                  \
     template hipError_t launch_fft_y_fast<T>(cx_t<T> *, int, int, int, int, int, int,            \
                                              const cx_t<T> *, hipStream_t, int, int);             \
     template hipError_t launch_r2c_fast<T>(const T *, cx_t<T> *, double *, int, int, int,        \

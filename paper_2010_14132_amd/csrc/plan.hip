@@ -798,12 +798,47 @@ template <typename T> static int run(ps_plan *p, const T *in, T *out, int adjoin
     return PS_OK;
 }
 
-// The solve for fields in the z-fastest (MONC) layout: its own x passes
-// around the shared y / column / y passes.
+// Whether the z-fastest solve takes the register-resident passes through
+// the [kx][j][k] buffer (the plan's x and y passes are register-resident).
+static bool zyx_fast(const ps_plan *p) { return p->geom.variant_x >= 1 && p->geom.variant_y >= 1; }
+
+// The solve for fields in the z-fastest (MONC) layout.  Register-resident
+// lengths: forward x (field -> [kx][j][k], loads and stores along k), y
+// forward ([kx][j][k] -> spectrum), the column solves, y backward and
+// backward x, the same bytes per point as the level-major solve.  Other
+// lengths: x passes that transpose between columns and rows in LDS around
+// the level-major y / column / y passes.
 template <typename T> static int run_zyx(ps_plan *p, const T *in, T *out, int adjoint)
 {
     auto *spec = reinterpret_cast<cx_t<T> *>(p->d_spec);
     const Tables<T> &tb = tables<T>(p);
+    if (zyx_fast(p)) {
+        if (!p->d_zyx) {
+            cx_t<T> *buf = nullptr;
+            PS_TRY(dev_alloc(p, &buf, p->spec_elems()));
+            p->d_zyx = buf;
+        }
+        auto *tmp = reinterpret_cast<cx_t<T> *>(p->d_zyx);
+        const int refine = p->precision == PS_FP32_R2;
+        PS_HIP(timed(p, K_FWD_X, [&] {
+            return launch_x_zyx_fast<T>(in, tmp, p->d_rowsum, nullptr, nullptr, p->nx, p->ny,
+                                        p->nz, tb.tw4_x, tb.tw_s,
+                                        p->geom.variant_x == 4 && pair_length(p->L), p->stream);
+        }));
+        PS_HIP(timed(p, K_FFT_Y_FWD, [&] {
+            return launch_fft_y_zyx<T>(tmp, spec, p->nz, p->L, p->ny, -1, tb.tw4_y, p->stream);
+        }));
+        PS_TRY(columns<T>(p, spec, adjoint, refine));
+        PS_HIP(timed(p, K_FFT_Y_INV, [&] {
+            return launch_fft_y_zyx<T>(spec, tmp, p->nz, p->L, p->ny, 1, tb.tw4_y, p->stream);
+        }));
+        PS_HIP(timed(p, K_INV_X, [&] {
+            return launch_x_zyx_fast<T>(nullptr, nullptr, nullptr, tmp, out, p->nx, p->ny, p->nz,
+                                        tb.tw4_x, tb.tw_s,
+                                        p->geom.variant_xi == 4 && pair_length(p->L), p->stream);
+        }));
+        return PS_OK;
+    }
     PS_HIP(timed(p, K_FWD_X, [&] {
         return launch_fwd_x_zyx<T>(in, spec, p->d_rowsum, p->nx, p->ny, p->nz, p->geom.rows_x,
                                    p->geom.zyx_kc, p->spx, tb, p->stream);
@@ -1043,7 +1078,8 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
     pick(&FftGeom::special_variant, {0, 1});
     pick(&FftGeom::special_side, {0, 1, 2});
     if (p->geom.special_side == 1) pick(&FftGeom::chunks, {1, 2, 4, 8});
-    if (p->precision != PS_FP32_R1) pick(&FftGeom::zyx_kc, {1, 2, 4, 8, 64}, solve_zyx_common);
+    if (p->precision != PS_FP32_R1 && !zyx_fast(p))
+        pick(&FftGeom::zyx_kc, {1, 2, 4, 8, 64}, solve_zyx_common);
     p->prof.on = prof;
     (void)hipStreamSynchronize(p->stream);
     (void)hipFree(in);

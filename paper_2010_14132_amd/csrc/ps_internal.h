@@ -145,6 +145,19 @@ hipError_t launch_inv_x_zyx(const cx_t<T> *spec, T *out, int nx, int ny, int nz,
                             int kc_pref, const StagePlan &spx, const Tables<T> &tb,
                             hipStream_t st);
 
+// The z-fastest solve's passes for fast lengths (fft_fast.hip), through
+// the [kx][j][k] layout (k fastest, tmp): forward x (in != NULL: field ->
+// tmp, row sums) or backward x (in == NULL: tmp_in -> field out), pair: the
+// paired row transform (nx/2 = 2 s^2); y forward (dir < 0: tmp -> spectrum)
+// or backward (dir > 0: spectrum -> tmp).
+template <typename T>
+hipError_t launch_x_zyx_fast(const T *in, cx_t<T> *tmp, double *rowsum, const cx_t<T> *tmp_in,
+                             T *out, int nx, int ny, int nz, const cx_t<T> *tw4,
+                             const cx_t<T> *tws, int pair, hipStream_t st);
+template <typename T>
+hipError_t launch_fft_y_zyx(const cx_t<T> *src, cx_t<T> *dst, int nz, int nkx, int ny, int dir,
+                            const cx_t<T> *tw4, hipStream_t st);
+
 // Column solves of the rows kx in [kxlo, kxhi) (kx = 0 excluded: the FP64
 // kernel's row).
 template <typename T>

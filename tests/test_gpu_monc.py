@@ -1,8 +1,10 @@
 """Solves in MONC's own field layout p%data(z,y,x) (z fastest, a C array
-[nx][ny][nz]) through ps_solve_zyx: the x passes read and write that layout
-themselves (transposes in LDS), the rest is the level-major solve.  With the
-level-major plan on the generic x transform (the same Stockham passes over
-the same rows) the two give the same bits; both against the oracle."""
+[nx][ny][nz]) through ps_solve_zyx.  Register-resident lengths go through a
+[kx][j][k] buffer (x and y passes staging along k); other lengths through x
+passes that transpose in LDS around the level-major y and column passes.
+Either way the row transforms are the level-major solve's: with the
+generic x passes the two layouts give the same bits, with the register-
+resident ones they agree to rounding; both against the oracle."""
 import numpy as np
 import pytest
 
@@ -75,6 +77,62 @@ def test_zyx_solve_matches_level_major_and_oracle(tmp_path, precision, shape):
     lref = oracle.solve_adjoint(b, g.dx, g.dy, g.dz, g.rho)
     assert relmax(p_z.permute(2, 1, 0).double().cpu().numpy(), ref) < TOL[precision]
     assert relmax(l_z.permute(2, 1, 0).double().cpu().numpy(), lref) < TOL[precision]
+
+
+FAST_SHAPES = [(16, 32, 64), (1, 16, 32), (33, 64, 256), (9, 16, 1024), (70, 64, 32),
+               (5, 128, 512), (3, 1024, 32)]
+
+
+@pytest.mark.parametrize("shape", FAST_SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_r2"])
+def test_zyx_fast_passes_bit_equal_to_level_major(tmp_path, precision, shape):
+    """Register-resident lengths: the z-fastest solve through the [kx][j][k]
+    buffer (x passes staging along k, y passes between that buffer and the
+    spectrum) runs the same row transforms as the level-major solve with
+    the same variants (plain and paired x, both y tile orders); the compiler
+    fuses a few products differently in the separately built kernels, so
+    the two agree to rounding (not bit for bit), forward and adjoint, and
+    each is checked against the oracle; the in-place call gives the same
+    bits as the out-of-place one.  Partial level chunks (nz not a multiple
+    of a block's levels) and nz = 1 included."""
+    from paper_2010_14132_amd import Plan
+    from paper_2010_14132_amd.binding import PRECISIONS, tune_cache_load
+    nz, ny, nx = shape
+    announce("zyx fast passes %s %s" % (precision, shape))
+    g = grid(nx, ny, nz, seed=nz + 2 * ny + nx)
+    b = np.random.default_rng(6).standard_normal(shape) + 0.3
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    if precision != "fp64":
+        b = b.astype(np.float32).astype(np.float64)
+    ref = oracle.solve(b, g.dx, g.dy, g.dz, g.rho)
+    lref = oracle.solve_adjoint(b, g.dx, g.dy, g.dz, g.rho)
+    for vx, vy in ((1, 1), (4, 2)):
+        f = tmp_path / ("tune%d.txt" % vx)
+        f.write_text("%s %d %d %d %d %d %d 3 1 1 %d 1 64\n"
+                     % (arch(), nx, ny, nz, PRECISIONS[precision], vx, vy, vx))
+        tune_cache_load(str(f))
+        plan = Plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.rho, precision=precision)
+        plan.autotune()
+        info = plan.info()
+        assert (info["fft_variant_x"], info["fft_variant_y"], info["fft_variant_xi"]) == (vx, vy, vx)
+        bt = torch.from_numpy(b).to("cuda", dt)
+        bz = bt.permute(2, 1, 0).contiguous()          # [nx][ny][nz]
+        p_lm = plan.solve(bt)
+        p_z = plan.solve_zyx(bz)
+        l_lm = plan.solve_adjoint(bt)
+        l_z = plan.solve_zyx(bz, adjoint=True)
+        x = bz.clone()
+        plan.solve_zyx(x, out=x)
+        torch.cuda.synchronize()
+        agree = 1e-14 if precision == "fp64" else 2e-6
+        pz, lz = p_z.permute(2, 1, 0).double().cpu().numpy(), l_z.permute(2, 1, 0).double().cpu().numpy()
+        assert relmax(pz, p_lm.double().cpu().numpy()) < agree, (vx, vy)
+        assert relmax(lz, l_lm.double().cpu().numpy()) < agree, (vx, vy)
+        assert torch.equal(x, p_z), (vx, vy)
+        assert plan.workspace_bytes() >= 2 * nz * ny * (nx // 2) * (16 if precision == "fp64" else 8)
+        plan.close()
+        assert relmax(pz, ref) < TOL[precision], (vx, vy)
+        assert relmax(lz, lref) < TOL[precision], (vx, vy)
 
 
 def test_zyx_in_place_and_r1_refused():
