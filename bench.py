@@ -16,7 +16,9 @@ other workloads (32^2 x 16 plain, 256^2 x 64 plain, 512^2 x 128
 differentiation, the 48-problem uneven batch) under "configs", and on the
 CPU side the oracle timed on a bounded sample (all cores, and one core for
 the two small workloads) next to a fast FP64 CPU solve (scipy FFTs and a
-vectorised column sweep), which is labelled apart from the oracle.
+vectorised column sweep), which is labelled apart from the oracle.  The
+oracle runs only in the CPU baseline (timing); errors are reported against
+the FP64 GPU solve, whose parity with the oracle the GPU tests check.
 """
 from __future__ import annotations
 
@@ -94,23 +96,6 @@ def measured_traffic(form: str, kernel: str):
     if digest != kernel_sources_digest():
         return None
     return found
-
-
-def sampled_oracle_error(p: np.ndarray, b: np.ndarray, g, modes) -> float:
-    """Relative error of sampled wavenumber columns against the oracle's
-    column solve of a plain DFT of the input (test infrastructure)."""
-    import oracle
-    nz, ny, nx = p.shape
-    scale, err = 0.0, 0.0
-    for kx, ky in modes:
-        ex = np.exp(-2j * np.pi * kx * np.arange(nx) / nx)
-        ey = np.exp(-2j * np.pi * ky * np.arange(ny) / ny)
-        s = 4 * np.sin(np.pi * kx / nx) ** 2 / g.dx ** 2 + 4 * np.sin(np.pi * ky / ny) ** 2 / g.dy ** 2
-        want = oracle.column_solve(s, (b @ ex) @ ey, g.dz, g.rho)
-        got = (p @ ex) @ ey
-        scale = max(scale, np.abs(want).max())
-        err = max(err, np.abs(got - want).max())
-    return err / scale
 
 
 def cpu_baseline(g, nz_full: int):
@@ -295,18 +280,18 @@ def rel_max(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
 
-def config_forms(prob, forms, steps, warmup, oracle_ref=True):
+def config_forms(prob, forms, steps, warmup):
     """Solves/s and Mpts/s of each precision form on one workload (autotuned
-    plans), the per-solve time distribution, and rel_max against the oracle
-    (whole field) when oracle_ref."""
+    plans), the per-solve time distribution, and each FP32 form's rel_max
+    against the FP64 GPU solve of the same input (whole field; the FP64
+    solve's own parity with the oracle is a test's business)."""
     import torch
-    import oracle
     from paper_2010_14132_amd import Plan
     g = prob.grid
     b64 = prob.rhs_exact() if prob.dtype == "f32" else prob.rhs
-    ref = oracle.solve(b64, g.dx, g.dy, g.dz, g.rho) if oracle_ref else None
+    ref = None
     res = {}
-    for form in forms:
+    for form in sorted(forms, key=lambda f: f != "fp64"):
         plan = Plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.rho, precision=form)
         plan.autotune(reps=5)
         dt = torch.float64 if form == "fp64" else torch.float32
@@ -317,8 +302,10 @@ def config_forms(prob, forms, steps, warmup, oracle_ref=True):
         r = {"ms_per_solve": ms, "solves_per_s": 1e3 / ms, "mpts_per_s": g.points / ms / 1e3,
              "median_ms": d["median_ms"], "min_ms": d["min_ms"], "mean_ms": d["mean_ms"],
              "reps": d["reps"]}
-        if ref is not None:
-            r["rel_max_vs_oracle"] = rel_max(out.double().cpu().numpy(), ref)
+        if form == "fp64":
+            ref = out.double().cpu().numpy()
+        elif ref is not None:
+            r["rel_max_vs_fp64_gpu"] = rel_max(out.double().cpu().numpy(), ref)
         res[form] = r
         plan.close()
     return res
@@ -497,10 +484,10 @@ def config_batch(steps, warmup):
     the lane count), latency = median device time of one batched solve
     (events on the caller's stream around the whole replay) over >= 50
     replays, aggregate Mpts/s = total points / latency; beside it the same
-    48 solves issued one after another on one stream, and rel_max against
-    the oracle on the four smallest problems."""
+    48 solves issued one after another on one stream, and the largest
+    difference between a batched result and the same problem's standalone
+    solve (zero: the same kernels on the same data)."""
     import torch
-    import oracle
     from paper_2010_14132_amd import BatchPlan, Plan
     from paper_2010_14132_amd import workloads as wl
     probs = wl.batch_problems()
@@ -520,13 +507,6 @@ def config_batch(steps, warmup):
            "aggregate_mpts_per_s": npts / d["median_ms"] / 1e3,
            "batches_per_s": 1e3 / d["median_ms"],
            "alg_bytes": alg, "hbm_frac": alg / (d["median_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
-    small = sorted(range(len(probs)), key=lambda i: probs[i].grid.points)[:4]
-    errs = []
-    for i in small:
-        g = probs[i].grid
-        ref = oracle.solve(probs[i].rhs_exact(), g.dx, g.dy, g.dz, g.rho)
-        errs.append(rel_max(out[i].double().cpu().numpy(), ref))
-    res["rel_max_vs_oracle_smallest4"] = max(errs)
     plans = []
     for p in probs:
         q = Plan(p.grid.nx, p.grid.ny, p.grid.nz, p.grid.dx, p.grid.dy, p.grid.dz, p.grid.rho,
@@ -540,6 +520,8 @@ def config_batch(steps, warmup):
             q.solve(r, out=o)
 
     ds = time_distribution(sequential, max(20, steps // 2))
+    torch.cuda.synchronize()
+    res["max_abs_diff_vs_standalone"] = max((o - q).abs().max().item() for o, q in zip(out, seq))
     res["sequential_one_stream_median_ms"] = ds["median_ms"]
     res["speedup_vs_sequential"] = ds["median_ms"] / d["median_ms"]
     for q in plans:
@@ -556,7 +538,6 @@ def main():
     ap.add_argument("--precision", default="fp32_r2", choices=["fp32", "fp32_r2", "fp32_r1", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="time only the headline form")
-    ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the planner's kernel choice instead of timing the variants")
     ap.add_argument("--tune-cache", default=None,
@@ -692,7 +673,8 @@ def main():
     dk = kernels[dom]
     achieved = dk["gbs"] or 0.0
 
-    # accuracy: against the FP64 GPU solve (full field) and the oracle (sampled)
+    # accuracy: against the FP64 GPU solve (full field; parity of every form
+    # with the oracle at this size is checked by the GPU tests)
     errs = {}
     if "fp64" in outputs:
         ref = outputs["fp64"].double()
@@ -700,11 +682,6 @@ def main():
         for form, o in outputs.items():
             if form != "fp64":
                 errs[form + "_vs_fp64_gpu_rel_max"] = (o.double() - ref).abs().max().item() / den
-    if not args.no_oracle_check:
-        modes = [(1, 0), (0, 1), (1, 1), (3, 7), (100, 200), (512, 512), (0, 511)]
-        p_head = outputs[args.precision].double().cpu().numpy()
-        errs["headline_vs_oracle_sampled_rel"] = sampled_oracle_error(
-            p_head, prob.rhs_exact(), g, modes)
 
     line = {
         "metric": "Poisson solves/s & Mpts/s, 1024^2x128 fp32+refine vs fp64; % of HBM peak",
@@ -778,7 +755,7 @@ def main():
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(g, g.nz)
         if not args.no_fast_cpu:
-            line["oracle_small_workloads"] = oracle_small_configs()
+            line["cpu_baseline"]["small_workloads"] = oracle_small_configs()
     print(json.dumps(line), flush=True)
 
 

@@ -197,7 +197,8 @@ typedef struct ps_plan_info {
     int special_variant;  /* FP64-column kernel: 0 one lane per task through an HBM
                              workspace, 1 staged in LDS */
     int zyx_kc;           /* z-fastest-layout x passes: levels per tile (capped by the
-                             tile's rows) */
+                             tile's rows); with the register-resident passes >= 32
+                             selects the wide blocks */
     int fp64_beside;      /* where the FP64 columns (packed kx = 0 row, mean column,
                              near-singular columns) run: the tune cache's fp64_beside */
 } ps_plan_info;
@@ -220,8 +221,9 @@ int ps_plan_query(const ps_plan *plan, ps_plan_info *info);
  * taken in (with fp64_beside 1 only); both defaulting to 1; xi_variant the backward x
  * pass's, defaulting to x_variant; special_variant the FP64-column kernel's
  * (0 or 1), defaulting to 1; zyx_kc the levels per tile of the z-fastest
- * layout's x passes (1..256), defaulting to 64; it is timed with
- * ps_solve_zyx).
+ * layout's x passes (1..256), defaulting to 64 -- with the register-resident
+ * passes, values of 32 or more select blocks of twice the standard levels
+ * (32 FP32, 16 FP64) -- timed with ps_solve_zyx).
  * Synchronises. */
 int ps_plan_autotune(ps_plan *plan, int reps);
 int ps_tune_cache_save(const char *path);

@@ -105,14 +105,15 @@ __global__ __launch_bounds__(NT) void k_fft_y_zyx(const cx_t<T> *__restrict__ sr
     const int tile = tile_of(blockIdx.x, gridDim.x, 1);
     const int kx = tile / nkc, k0 = (tile % nkc) * RB, k = k0 + r;
     C v[R2], w[R2];
+    constexpr int IT = RB * L / NT; // staged values per thread: level kk, rows jj0 + (NT / RB) it
+    const int kk = threadIdx.x % RB, jj0 = threadIdx.x / RB;
     if constexpr (DIR < 0) {
-        const C *base = src + (long)kx * L * nz + k0;
-#pragma unroll 8
-        for (int e = threadIdx.x; e < RB * L; e += NT) {
-            const int kk = e % RB, jj = e / RB;
-            const int kq = k0 + kk < nz ? kk : nz - 1 - k0;
-            stg[kk * SW + jj] = base[(long)jj * nz + kq];
-        }
+        const C *col = src + (long)kx * L * nz + (k0 + kk < nz ? k0 + kk : nz - 1);
+        C ld[IT];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) ld[it] = col[(long)(jj0 + (NT / RB) * it) * nz];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) stg[kk * SW + jj0 + (NT / RB) * it] = ld[it];
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < R2; ++q) v[q] = stg[r * SW + t + R1 * q];
@@ -139,11 +140,11 @@ __global__ __launch_bounds__(NT) void k_fft_y_zyx(const cx_t<T> *__restrict__ sr
 #pragma unroll
             for (int k1 = 0; k1 < R1; ++k1) stg[r * SW + (t + R1 * j) + R2 * k1] = w[j * R1 + k1];
         __syncthreads();
-        C *base = dst + (long)kx * L * nz + k0;
-#pragma unroll 8
-        for (int e = threadIdx.x; e < RB * L; e += NT) {
-            const int kk = e % RB, jj = e / RB;
-            if (k0 + kk < nz) base[(long)jj * nz + kk] = stg[kk * SW + jj];
+        if (k0 + kk < nz) {
+            C *col = dst + (long)kx * L * nz + k0 + kk;
+#pragma unroll
+            for (int it = 0; it < IT; ++it)
+                col[(long)(jj0 + (NT / RB) * it) * nz] = stg[kk * SW + jj0 + (NT / RB) * it];
         }
     }
 }
@@ -234,12 +235,18 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
     if constexpr (ZYX) {
         // rows past the last level read level nz - 1: transformed, never stored
         constexpr int SW = 2 * L + 2;
-#pragma unroll 8
-        for (int e = threadIdx.x; e < ROWS * 2 * L; e += NT) {
-            const int kk = e % ROWS, i = e / ROWS;
-            const int kq = zk0 + kk < nz ? zk0 + kk : nz - 1;
-            lds[kk * SW + i] = in[((long)i * ny + zj) * nz + kq];
-        }
+        const long istride = (long)ny * nz;
+        // thread: level kk of the chunk, points i = i0 + (NT / ROWS) it
+        constexpr int IT = 2 * L * ROWS / NT;
+        static_assert(NT % ROWS == 0 && (2 * L * ROWS) % NT == 0, "staging split");
+        const int kk = threadIdx.x % ROWS, i0 = threadIdx.x / ROWS;
+        const int kq = zk0 + kk < nz ? zk0 + kk : nz - 1;
+        const T *col = in + (long)zj * nz + kq;
+        T ld[IT];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) ld[it] = col[(long)(i0 + (NT / ROWS) * it) * istride];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) lds[kk * SW + i0 + (NT / ROWS) * it] = ld[it];
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < R2; ++q) {
@@ -549,10 +556,15 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
             lds[r * SW + 2 * c + 1] = Z[i].y;
         }
         __syncthreads();
+        const long istride = (long)ny * nz;
+        constexpr int IT = 2 * L * ROWS / NT;
+        const int kk = threadIdx.x % ROWS, i0 = threadIdx.x / ROWS;
+        if (zk0 + kk < nz) {
+            T *col = out + (long)zj * nz + zk0 + kk;
 #pragma unroll 8
-        for (int e = threadIdx.x; e < ROWS * 2 * L; e += NT) {
-            const int kk = e % ROWS, i = e / ROWS;
-            if (zk0 + kk < nz) out[((long)i * ny + zj) * nz + zk0 + kk] = lds[kk * SW + i];
+            for (int it = 0; it < IT; ++it)
+                col[(long)(i0 + (NT / ROWS) * it) * istride] =
+                    lds[kk * SW + i0 + (NT / ROWS) * it];
         }
         return;
     }
@@ -793,14 +805,14 @@ hipError_t launch_fft_y_zyx(const cx_t<T> *src, cx_t<T> *dst, int nz, int nkx, i
 #undef PS_Y
 }
 
-template <typename T, int R1, int R2>
+template <typename T, int R1, int R2, bool WIDE>
 static hipError_t x_zyx(const T *in, cx_t<T> *tmp, double *rowsum, const cx_t<T> *tmp_in,
                         T *out, int ny, int nz, const cx_t<T> *tw4, const cx_t<T> *tws,
                         int pair, hipStream_t st)
 {
     if constexpr (R2 == 2 * R1) {
         if (pair) {
-            constexpr int ROWS = x_rows<T, R2, R1, false, true>();
+            constexpr int ROWS = x_rows<T, R2, R1, WIDE, true>();
             const int grid = ny * ((nz + ROWS - 1) / ROWS);
             if (in)
                 hipLaunchKernelGGL((k_r2c_fast<T, R2, R1, ROWS, false, true, false, true>),
@@ -814,7 +826,7 @@ static hipError_t x_zyx(const T *in, cx_t<T> *tmp, double *rowsum, const cx_t<T>
             return hipGetLastError();
         }
     }
-    constexpr int ROWS = x_rows<T, R1, R2, false>();
+    constexpr int ROWS = x_rows<T, R1, R2, WIDE>();
     const int grid = ny * ((nz + ROWS - 1) / ROWS);
     if (in)
         hipLaunchKernelGGL((k_r2c_fast<T, R1, R2, ROWS, false, false, false, true>), dim3(grid),
@@ -829,13 +841,16 @@ static hipError_t x_zyx(const T *in, cx_t<T> *tmp, double *rowsum, const cx_t<T>
 
 // Forward (in != NULL: z-fastest field -> [kx][j][k], row sums) or backward
 // (in == NULL: [kx][j][k] -> z-fastest field) x pass; pair selects the
-// paired row transform where nx/2 = 2 s^2.
+// paired row transform where nx/2 = 2 s^2; wide: twice the levels per
+// block (256-byte runs along k in FP32, within 128 KiB of LDS).
 template <typename T>
 hipError_t launch_x_zyx_fast(const T *in, cx_t<T> *tmp, double *rowsum, const cx_t<T> *tmp_in,
                              T *out, int nx, int ny, int nz, const cx_t<T> *tw4,
-                             const cx_t<T> *tws, int pair, hipStream_t st)
+                             const cx_t<T> *tws, int pair, int wide, hipStream_t st)
 {
-#define PS_X(a, b) x_zyx<T, a, b>(in, tmp, rowsum, tmp_in, out, ny, nz, tw4, tws, pair, st)
+#define PS_X(a, b)                                                                                 \
+    (wide ? x_zyx<T, a, b, true>(in, tmp, rowsum, tmp_in, out, ny, nz, tw4, tws, pair, st)         \
+          : x_zyx<T, a, b, false>(in, tmp, rowsum, tmp_in, out, ny, nz, tw4, tws, pair, st))
     PS_FAST_SWITCH(nx / 2, PS_X)
 #undef PS_X
 }
@@ -845,7 +860,7 @@ hipError_t launch_x_zyx_fast(const T *in, cx_t<T> *tmp, double *rowsum, const cx
                                             const cx_t<T> *, hipStream_t);                        \
     template hipError_t launch_x_zyx_fast<T>(const T *, cx_t<T> *, double *, const cx_t<T> *,    \
                                              T *, int, int, int, const cx_t<T> *,                 \
-                                             const cx_t<T> *, int, hipStream_t);                  \
+                                             const cx_t<T> *, int, int, hipStream_t);             \
     template hipError_t launch_fft_y_fast<T>(cx_t<T> *, int, int, int, int, int, int,            \
                                              const cx_t<T> *, hipStream_t, int, int);             \
     template hipError_t launch_r2c_fast<T>(const T *, cx_t<T> *, double *, int, int, int,        \

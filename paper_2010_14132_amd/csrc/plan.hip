@@ -820,10 +820,12 @@ template <typename T> static int run_zyx(ps_plan *p, const T *in, T *out, int ad
         }
         auto *tmp = reinterpret_cast<cx_t<T> *>(p->d_zyx);
         const int refine = p->precision == PS_FP32_R2;
+        const int wide = p->geom.zyx_kc >= 32;
         PS_HIP(timed(p, K_FWD_X, [&] {
             return launch_x_zyx_fast<T>(in, tmp, p->d_rowsum, nullptr, nullptr, p->nx, p->ny,
                                         p->nz, tb.tw4_x, tb.tw_s,
-                                        p->geom.variant_x == 4 && pair_length(p->L), p->stream);
+                                        p->geom.variant_x == 4 && pair_length(p->L), wide,
+                                        p->stream);
         }));
         PS_HIP(timed(p, K_FFT_Y_FWD, [&] {
             return launch_fft_y_zyx<T>(tmp, spec, p->nz, p->L, p->ny, -1, tb.tw4_y, p->stream);
@@ -835,7 +837,8 @@ template <typename T> static int run_zyx(ps_plan *p, const T *in, T *out, int ad
         PS_HIP(timed(p, K_INV_X, [&] {
             return launch_x_zyx_fast<T>(nullptr, nullptr, nullptr, tmp, out, p->nx, p->ny, p->nz,
                                         tb.tw4_x, tb.tw_s,
-                                        p->geom.variant_xi == 4 && pair_length(p->L), p->stream);
+                                        p->geom.variant_xi == 4 && pair_length(p->L), wide,
+                                        p->stream);
         }));
         return PS_OK;
     }
@@ -1078,8 +1081,12 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
     pick(&FftGeom::special_variant, {0, 1});
     pick(&FftGeom::special_side, {0, 1, 2});
     if (p->geom.special_side == 1) pick(&FftGeom::chunks, {1, 2, 4, 8});
-    if (p->precision != PS_FP32_R1 && !zyx_fast(p))
-        pick(&FftGeom::zyx_kc, {1, 2, 4, 8, 64}, solve_zyx_common);
+    if (p->precision != PS_FP32_R1) {
+        if (zyx_fast(p))
+            pick(&FftGeom::zyx_kc, {16, 64}, solve_zyx_common); // standard or wide blocks
+        else
+            pick(&FftGeom::zyx_kc, {1, 2, 4, 8, 64}, solve_zyx_common);
+    }
     p->prof.on = prof;
     (void)hipStreamSynchronize(p->stream);
     (void)hipFree(in);

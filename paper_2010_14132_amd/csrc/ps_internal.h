@@ -65,7 +65,9 @@ struct FftGeom {
     int chunks = 1;      // y forward / columns / y backward run in this many kx chunks
     int special_variant = 1; // FP64 columns: 0 one lane per task via the HBM workspace,
                              // 1 staged in LDS (k_special_lds)
-    int zyx_kc = 64;     // z-fastest (MONC) x passes: levels per tile (capped by the tile rows)
+    int zyx_kc = 64;     // z-fastest (MONC) x passes: levels per tile (capped by the tile
+                         // rows); with the register-resident passes, >= 32 selects blocks
+                         // of twice the standard levels (32 FP32, 16 FP64)
 };
 
 struct Launch {
@@ -148,12 +150,13 @@ hipError_t launch_inv_x_zyx(const cx_t<T> *spec, T *out, int nx, int ny, int nz,
 // The z-fastest solve's passes for fast lengths (fft_fast.hip), through
 // the [kx][j][k] layout (k fastest, tmp): forward x (in != NULL: field ->
 // tmp, row sums) or backward x (in == NULL: tmp_in -> field out), pair: the
-// paired row transform (nx/2 = 2 s^2); y forward (dir < 0: tmp -> spectrum)
-// or backward (dir > 0: spectrum -> tmp).
+// paired row transform (nx/2 = 2 s^2), wide: twice the levels per block;
+// y forward (dir < 0: tmp -> spectrum) or backward (dir > 0: spectrum ->
+// tmp).
 template <typename T>
 hipError_t launch_x_zyx_fast(const T *in, cx_t<T> *tmp, double *rowsum, const cx_t<T> *tmp_in,
                              T *out, int nx, int ny, int nz, const cx_t<T> *tw4,
-                             const cx_t<T> *tws, int pair, hipStream_t st);
+                             const cx_t<T> *tws, int pair, int wide, hipStream_t st);
 template <typename T>
 hipError_t launch_fft_y_zyx(const cx_t<T> *src, cx_t<T> *dst, int nz, int nkx, int ny, int dir,
                             const cx_t<T> *tw4, hipStream_t st);

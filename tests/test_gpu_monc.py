@@ -80,7 +80,7 @@ def test_zyx_solve_matches_level_major_and_oracle(tmp_path, precision, shape):
 
 
 FAST_SHAPES = [(16, 32, 64), (1, 16, 32), (33, 64, 256), (9, 16, 1024), (70, 64, 32),
-               (5, 128, 512), (3, 1024, 32)]
+               (5, 128, 512), (3, 1024, 32), (20, 64, 128), (36, 16, 256)]
 
 
 @pytest.mark.parametrize("shape", FAST_SHAPES, ids=lambda s: "x".join(map(str, s)))
@@ -89,7 +89,8 @@ def test_zyx_fast_passes_bit_equal_to_level_major(tmp_path, precision, shape):
     """Register-resident lengths: the z-fastest solve through the [kx][j][k]
     buffer (x passes staging along k, y passes between that buffer and the
     spectrum) runs the same row transforms as the level-major solve with
-    the same variants (plain and paired x, both y tile orders); the compiler
+    the same variants (plain and paired x, both y tile orders, standard and
+    wide blocks of levels); the compiler
     fuses a few products differently in the separately built kernels, so
     the two agree to rounding (not bit for bit), forward and adjoint, and
     each is checked against the oracle; the in-place call gives the same
@@ -106,10 +107,11 @@ def test_zyx_fast_passes_bit_equal_to_level_major(tmp_path, precision, shape):
         b = b.astype(np.float32).astype(np.float64)
     ref = oracle.solve(b, g.dx, g.dy, g.dz, g.rho)
     lref = oracle.solve_adjoint(b, g.dx, g.dy, g.dz, g.rho)
-    for vx, vy in ((1, 1), (4, 2)):
+    # plain x with the standard blocks, paired x with the wide blocks
+    for vx, vy, kc in ((1, 1, 16), (4, 2, 64)):
         f = tmp_path / ("tune%d.txt" % vx)
-        f.write_text("%s %d %d %d %d %d %d 3 1 1 %d 1 64\n"
-                     % (arch(), nx, ny, nz, PRECISIONS[precision], vx, vy, vx))
+        f.write_text("%s %d %d %d %d %d %d 3 1 1 %d 1 %d\n"
+                     % (arch(), nx, ny, nz, PRECISIONS[precision], vx, vy, vx, kc))
         tune_cache_load(str(f))
         plan = Plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.rho, precision=precision)
         plan.autotune()
