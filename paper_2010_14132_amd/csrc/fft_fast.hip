@@ -529,7 +529,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
         C xb;
         xb.x = __shfl(xa[R2 - 1 - q].x, src_lane, 64);
         xb.y = __shfl(xa[R2 - 1 - q].y, src_lane, 64);
-        if (t == 0) xb = xa[(R2 - q) & (R2 - 1)];
+        if (t == 0) xb = xa[(R2 - q) % R2];
         if (k == 0) {
             const T x0 = xa[q].x, xl = xa[q].y;
             v[q] = C{x0 + xl, x0 - xl};
@@ -624,8 +624,25 @@ static hipError_t y_fast(cx_t<T> *spec, int nrows, int dir, const cx_t<T> *tw4, 
     return hipGetLastError();
 }
 
-bool fast_length(int L) { return L == 16 || L == 32 || L == 64 || L == 128 || L == 256 || L == 512 || L == 1024; }
-int fast_r1(int L) { return L <= 32 ? 4 : L <= 128 ? 8 : L <= 512 ? 16 : 32; }
+// Powers of two from 16 to 1024, and 3 2^k from 24 to 192 (an R2 of 12 or 24
+// points: a prime-factor DFT in registers); in FP32 also 384 (R2 = 48, whose
+// FP64 registers would not fit).
+bool fast_length(int L, bool fp64)
+{
+    return L == 16 || L == 32 || L == 64 || L == 128 || L == 256 || L == 512 || L == 1024 ||
+           L == 24 || L == 48 || L == 96 || L == 192 || (!fp64 && L == 384);
+}
+int fast_r1(int L)
+{
+    switch (L) {
+    case 24: return 2;
+    case 48: return 4;
+    case 96: return 4;
+    case 192: return 8;
+    case 384: return 8;
+    default: return L <= 32 ? 4 : L <= 128 ? 8 : L <= 512 ? 16 : 32;
+    }
+}
 bool pair_length(int L) { return L == 32 || L == 128 || L == 512; }
 
 #define PS_FAST_SWITCH(L, F)                                                                       \
@@ -637,6 +654,13 @@ bool pair_length(int L) { return L == 32 || L == 128 || L == 512; }
     case 256: return F(16, 16);                                                                    \
     case 512: return F(16, 32);                                                                    \
     case 1024: return F(32, 32);                                                                   \
+    case 24: return F(2, 12);                                                                      \
+    case 48: return F(4, 12);                                                                      \
+    case 96: return F(4, 24);                                                                      \
+    case 192: return F(8, 24);                                                                     \
+    case 384:                                                                                      \
+        if constexpr (sizeof(T) == 4) return F(8, 48);                                             \
+        else return hipErrorNotSupported;                                                          \
     default: return hipErrorNotSupported;                                                          \
     }
 

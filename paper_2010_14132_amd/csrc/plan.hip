@@ -251,7 +251,7 @@ template <typename T> static int upload_tables(ps_plan *p, Tables<T> &t)
     PS_TRY(roots(t.tw_y, p->ny, p->ny));
     // four-step twiddles W_n^{t k2} at [k2 R1 + t] for the register kernels
     auto four = [&](C *dst, int n) -> int {
-        if (!fast_length(n)) return PS_OK;
+        if (!fast_length(n, sizeof(T) == 8)) return PS_OK;
         const int r1 = fast_r1(n), r2 = n / r1;
         std::vector<C> h(n);
         for (int k2 = 0; k2 < r2; ++k2)
@@ -332,9 +332,9 @@ static void choose_geometry(ps_plan *p)
     p->geom.rows_y = std::min(ry, p->nz * p->L);
     // register-resident kernels where the length has one: the paired row
     // transform forward where nx/2 = 2 s^2, XCD-contiguous tiles backward
-    p->geom.variant_x = pair_length(p->L) ? 4 : fast_length(p->L) ? 1 : 0;
-    p->geom.variant_xi = fast_length(p->L) ? 2 : 0;
-    p->geom.variant_y = fast_length(p->ny) ? 1 : 0;
+    p->geom.variant_x = pair_length(p->L) ? 4 : fast_length(p->L, p->fp64()) ? 1 : 0;
+    p->geom.variant_xi = fast_length(p->L, p->fp64()) ? 2 : 0;
+    p->geom.variant_y = fast_length(p->ny, p->fp64()) ? 1 : 0;
     // uniform-half column kernels: split lanes with the pivots in LDS for
     // FP64 and the in-register refinement, one complex column per lane for
     // the other FP32 forms
@@ -1024,9 +1024,9 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
         auto it = g_tune.find(key);
         if (it != g_tune.end()) {
             // only the tuned knobs: the tile shapes follow from the plan
-            p->geom.variant_x = fast_length(p->L) ? it->second.variant_x : 0;
-            p->geom.variant_xi = fast_length(p->L) ? it->second.variant_xi : 0;
-            p->geom.variant_y = fast_length(p->ny) ? it->second.variant_y : 0;
+            p->geom.variant_x = fast_length(p->L, p->fp64()) ? it->second.variant_x : 0;
+            p->geom.variant_xi = fast_length(p->L, p->fp64()) ? it->second.variant_xi : 0;
+            p->geom.variant_y = fast_length(p->ny, p->fp64()) ? it->second.variant_y : 0;
             p->geom.columns = it->second.columns;
             p->geom.special_side = it->second.special_side;
             p->geom.chunks = it->second.chunks;
@@ -1068,9 +1068,9 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
         p->geom.*knob = opts[best];
     };
     std::vector<int> vx{0}, vy{0};
-    if (fast_length(p->L)) vx.insert(vx.end(), {1, 2, 3});
+    if (fast_length(p->L, p->fp64())) vx.insert(vx.end(), {1, 2, 3});
     if (pair_length(p->L)) vx.push_back(4);
-    if (fast_length(p->ny)) vy.insert(vy.end(), {1, 2});
+    if (fast_length(p->ny, p->fp64())) vy.insert(vy.end(), {1, 2});
     pick(&FftGeom::variant_x, vx);
     pick(&FftGeom::variant_xi, vx);
     pick(&FftGeom::variant_y, vy);
@@ -1139,9 +1139,9 @@ extern "C" int ps_tune_cache_load(const char *path)
         std::ostringstream k;
         k << arch << ' ' << nx << ' ' << ny << ' ' << nz << ' ' << prec;
         FftGeom g;
-        g.variant_x = fast_length(nx / 2) ? vx : 0;
-        g.variant_xi = fast_length(nx / 2) ? vxi : 0;
-        g.variant_y = fast_length(ny) ? vy : 0;
+        g.variant_x = fast_length(nx / 2, prec == PS_FP64) ? vx : 0;
+        g.variant_xi = fast_length(nx / 2, prec == PS_FP64) ? vxi : 0;
+        g.variant_y = fast_length(ny, prec == PS_FP64) ? vy : 0;
         g.columns = col;
         g.special_side = side;
         g.chunks = chunks;

@@ -154,6 +154,41 @@ template <int DIR, typename C> __device__ __forceinline__ void dft32(C *v)
     }
 }
 
+// a^{-1} mod m (a and m coprime, m >= 2).
+constexpr int inv_mod(int a, int m)
+{
+    for (int x = 1; x < m; ++x)
+        if ((a * x) % m == 1) return x;
+    return 1;
+}
+
+template <int R, int DIR, typename C> __device__ __forceinline__ void dft(C *v);
+
+// Prime-factor (Good-Thomas) DFT of N = 3 M points, M a power of two (so 3
+// and M are coprime): element n1 M + 3 n2 (mod N) of the input is entry
+// (n1, n2) of a 3 x M array, M-point DFTs run over n2, then 3-point DFTs over
+// n1, with no twiddle factors between them, and entry (k1, k2) is output
+// element M U k1 + 3 W k2 (mod N), U = M^{-1} mod 3, W = 3^{-1} mod M (the
+// Chinese-remainder map).  In place; the index maps are compile-time.
+template <int M, int DIR, typename C> __device__ __forceinline__ void dft_pfa3(C *v)
+{
+    constexpr int N = 3 * M, U = inv_mod(M % 3, 3), W = inv_mod(3 % M, M);
+    C a[3][M];
+#pragma unroll
+    for (int n1 = 0; n1 < 3; ++n1)
+#pragma unroll
+        for (int n2 = 0; n2 < M; ++n2) a[n1][n2] = v[(M * n1 + 3 * n2) % N];
+#pragma unroll
+    for (int n1 = 0; n1 < 3; ++n1) dft<M, DIR>(a[n1]);
+#pragma unroll
+    for (int k2 = 0; k2 < M; ++k2) {
+        C b[3] = {a[0][k2], a[1][k2], a[2][k2]};
+        dft3<DIR>(b);
+#pragma unroll
+        for (int k1 = 0; k1 < 3; ++k1) v[(M * U * k1 + 3 * W * k2) % N] = b[k1];
+    }
+}
+
 template <int R, int DIR, typename C> __device__ __forceinline__ void dft(C *v)
 {
     if constexpr (R == 1) {
@@ -163,6 +198,11 @@ template <int R, int DIR, typename C> __device__ __forceinline__ void dft(C *v)
     else if constexpr (R == 8) dft8<DIR>(v);
     else if constexpr (R == 16) dft16<DIR>(v);
     else if constexpr (R == 32) dft32<DIR>(v);
+    else if constexpr (R == 6) dft_pfa3<2, DIR>(v);
+    else if constexpr (R == 12) dft_pfa3<4, DIR>(v);
+    else if constexpr (R == 24) dft_pfa3<8, DIR>(v);
+    else if constexpr (R == 48) dft_pfa3<16, DIR>(v);
+    else static_assert(R == 0, "no in-register DFT of this length");
 }
 
 // ---- four-step row transform in registers ----------------------------------

@@ -94,7 +94,7 @@ hipError_t launch_inv_x(const cx_t<T> *spec, T *out, int nx, int ny, int nz, int
                         const FftGeom &g, const StagePlan &spx, const Tables<T> &tb,
                         hipStream_t st);
 
-bool fast_length(int L);
+bool fast_length(int L, bool fp64); // a register-resident transform of this length exists
 bool pair_length(int L); // L = 2 s^2 among the fast lengths (32, 128, 512)
 int fast_r1(int L); // lanes per row of the register-resident kernels
 // variant (the plan's variant_x / variant_y >= 1): 1 = plain block order,

@@ -80,7 +80,7 @@ def test_zyx_solve_matches_level_major_and_oracle(tmp_path, precision, shape):
 
 
 FAST_SHAPES = [(16, 32, 64), (1, 16, 32), (33, 64, 256), (9, 16, 1024), (70, 64, 32),
-               (5, 128, 512), (3, 1024, 32), (20, 64, 128), (36, 16, 256)]
+               (5, 128, 512), (3, 1024, 32), (20, 64, 128), (36, 16, 256), (12, 96, 192)]
 
 
 @pytest.mark.parametrize("shape", FAST_SHAPES, ids=lambda s: "x".join(map(str, s)))

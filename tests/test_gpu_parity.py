@@ -482,6 +482,54 @@ def test_fp64_column_placement_via_tune_cache(tmp_path, precision, side):
     plan.close()
 
 
+# nx/2 and ny in {24, 48, 96, 192} (R2 = 12 or 24: prime-factor DFTs in registers),
+# and 384 (R2 = 48, FP32 forms only: the FP64 plans keep the generic passes)
+PFA_SHAPES = [(5, 24, 48), (9, 48, 96), (3, 96, 192), (2, 192, 384), (17, 192, 48),
+              (1, 24, 384), (40, 96, 64), (3, 384, 64), (2, 48, 768)]
+
+
+@pytest.mark.parametrize("shape", PFA_SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_r1", "fp32_r2"])
+def test_register_transforms_of_3x2k_lengths(tmp_path, precision, shape):
+    """Register-resident x and y passes for lengths 3 2^k (a prime-factor
+    3 x 2^m DFT inside the four-step row transform), forced through the tune
+    cache in each tile order, against the oracle forward and adjoint, and
+    against the generic Stockham passes to rounding; length 384 only in the
+    FP32 forms (an FP64 plan falls back to the generic passes)."""
+    from paper_2010_14132_amd.binding import PRECISIONS, tune_cache_load
+    nz, ny, nx = shape
+    announce("3x2^k register transforms %s %s" % (precision, shape))
+    g = stretched(nx, ny, nz, seed=31 + nz)
+    b = np.random.default_rng(12).standard_normal((nz, ny, nx)) + 0.2
+    if precision != "fp64":
+        b = b.astype(np.float32).astype(np.float64)
+    ref = oracle.solve(b, g.dx, g.dy, g.dz, g.rho)
+    lref = oracle.solve_adjoint(b, g.dx, g.dy, g.dz, g.rho)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    tol = TOL64 if precision == "fp64" else TOL32
+    got = {}
+    for vx, vy in ((0, 0), (1, 1), (2, 2), (3, 1)):
+        f = tmp_path / ("tune%d%d.txt" % (vx, vy))
+        f.write_text("%s %d %d %d %d %d %d 3 1 1 %d\n"
+                     % (_arch(), nx, ny, nz, PRECISIONS[precision], vx, vy, vx))
+        tune_cache_load(str(f))
+        plan = make_plan(g, precision)
+        plan.autotune()
+        info = plan.info()
+        fx = vx if (precision != "fp64" or nx // 2 != 384) else 0
+        fy = vy if (precision != "fp64" or ny != 384) else 0
+        assert (info["fft_variant_x"], info["fft_variant_y"], info["fft_variant_xi"]) == (fx, fy, fx)
+        bt = torch.from_numpy(b).to("cuda", dt)
+        p = plan.solve(bt).double().cpu().numpy()
+        lam = plan.solve_adjoint(bt).double().cpu().numpy()
+        plan.close()
+        assert relmax(p, ref) < tol, (vx, vy)
+        assert relmax(lam, lref) < tol, (vx, vy)
+        got[(vx, vy)] = p
+    for k, p in got.items():
+        assert relmax(p, got[(0, 0)]) < (1e-13 if precision == "fp64" else 2e-6), k
+
+
 PAIR_SHAPES = [(6, 32, 64), (5, 24, 256), (3, 16, 1024)]  # nx/2 = 32, 128, 512 (= 2 s^2)
 
 
