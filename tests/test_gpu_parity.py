@@ -325,6 +325,48 @@ def test_full_size_spectral_samples(precision1024, precision):
     assert err < TOL32
 
 
+def _dft_levels(x, kx, ky):
+    """dft_at level by level (bounded temporaries for the largest fields)."""
+    nz, ny, nx = x.shape
+    ex = np.exp(-2j * np.pi * kx * np.arange(nx) / nx)
+    ey = np.exp(-2j * np.pi * ky * np.arange(ny) / ny)
+    return np.array([(x[k].astype(np.float64) @ ex) @ ey for k in range(nz)])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_r2"])
+def test_maximum_size_sampled(precision):
+    """The largest supported grid, nx = 2048, ny = 1024, nz = 256 (2^29
+    points; planning defaults): sampled wavenumber columns against the
+    oracle's column solve of a plain DFT of the input, and the mean column
+    (the level means of p) against the oracle's solve of the level means of
+    the input on a one-point grid, which is the same (0, 0) system."""
+    nz, ny, nx = 256, 1024, 2048
+    announce("maximum size %dx%dx%d %s" % (nz, ny, nx, precision))
+    g = wl.stretched_grid(nx, ny, nz, stretch=1.01)
+    b32 = np.random.default_rng(41).standard_normal((nz, ny, nx), dtype=np.float32) + 0.1
+    b = b32 if precision != "fp64" else b32.astype(np.float64)
+    plan = make_plan(g, precision)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    p = plan.solve(torch.from_numpy(b).to("cuda", dt)).cpu().numpy()
+    plan.close()
+    tol = TOL64 if precision == "fp64" else TOL32
+    scale, errs = 0.0, []
+    for kx, ky in [(1, 0), (0, 1), (7, 300), (1024, 512), (1023, 1)]:
+        sk = (4 * np.sin(np.pi * kx / nx) ** 2 / g.dx ** 2
+              + 4 * np.sin(np.pi * ky / ny) ** 2 / g.dy ** 2)
+        want = oracle.column_solve(sk, _dft_levels(b32, kx, ky), g.dz, g.rho)
+        got = _dft_levels(p, kx, ky)
+        scale = max(scale, np.abs(want).max())
+        errs.append(np.abs(got - want).max())
+    err = max(errs) / scale
+    means = b32.astype(np.float64).mean(axis=(1, 2))
+    want_m = oracle.solve(means[:, None, None], g.dx, g.dy, g.dz, g.rho)[:, 0, 0]
+    got_m = p.astype(np.float64).mean(axis=(1, 2))
+    err_m = np.abs(got_m - want_m).max() / np.abs(want_m).max()
+    print("maximum size %s: sampled columns %.3e, mean column %.3e" % (precision, err, err_m))
+    assert err < tol and err_m < tol
+
+
 def test_stages_fp32_column_refinement():
     """The in-register refinement of the FP32 column solves does what it
     claims: the same FP32 spectrum (from the FP32 forward transform) is
