@@ -98,6 +98,18 @@ def measured_traffic(form: str, kernel: str):
     return found
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(g, nz_full: int):
     """Time the FP64 oracle (as it stands) on a bounded sample of the same
     workload: the full 1024 x 1024 horizontal grid with three levels per oracle
@@ -119,7 +131,7 @@ def cpu_baseline(g, nz_full: int):
             "sample": "FP64 oracle solve of %dx%dx%d levels of the same recipe in %.2f s, "
                       "scaled by %d/%d levels to %.1f s per full solve"
                       % (g.nx, g.ny, levels, t, nz_full, levels, t_full),
-            "mpts_per_s": g.nx * g.ny * nz_full / t_full / 1e6}
+            "mpts_per_s": g.nx * g.ny * nz_full / t_full / 1e6, "cpu_model": cpu_model()}
 
 
 def time_calls(call, steps, warmup):
@@ -681,7 +693,9 @@ def main():
         den = ref.abs().max().item()
         for form, o in outputs.items():
             if form != "fp64":
-                errs[form + "_vs_fp64_gpu_rel_max"] = (o.double() - ref).abs().max().item() / den
+                d = o.double() - ref
+                errs[form + "_vs_fp64_gpu_rel_max"] = d.abs().max().item() / den
+                errs[form + "_vs_fp64_gpu_rel_l2"] = (d.norm() / ref.norm()).item()
 
     line = {
         "metric": "Poisson solves/s & Mpts/s, 1024^2x128 fp32+refine vs fp64; % of HBM peak",
