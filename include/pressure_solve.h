@@ -133,8 +133,11 @@ int ps_solve(ps_plan *plan, const void *rhs, void *p);
  * transpose between columns and rows in LDS around ps_solve's y and column
  * passes.  The first call on a plan of the first kind allocates that buffer
  * (the size of the spectrum; synchronises): call it once before capturing
- * it into a graph.  rhs and p may alias.  PS_FP32_R1 plans give
- * PS_EUNSUPPORTED. */
+ * it into a graph.  PS_FP32_R1: the refinement's residual b - A p is formed
+ * in a pass of its own (FP64 accumulation, into a plan-owned field
+ * allocated on the first such call), solved, and accumulated into p by the
+ * last backward x pass.  rhs and p may alias, except for PS_FP32_R1
+ * (PS_EINVAL). */
 int ps_solve_zyx(ps_plan *plan, const void *rhs, void *p, int adjoint);
 
 /* One pressure-projection step of the dynamical core around the solve

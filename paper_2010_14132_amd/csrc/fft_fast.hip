@@ -87,7 +87,7 @@ __global__ __launch_bounds__(NT) void k_fft_y_fast(cx_t<T> *__restrict__ spec, i
 // (tiles level-chunk fastest, XCD-contiguous).  Forward: the rows are
 // gathered into an LDS staging by loads along k, transformed, and stored
 // into the spectrum along ky.  Backward: spectrum rows are loaded along ky,
-// transformed, staged in LDS and stored along k.  Levels past the last read
+// transformed, staged in LDS and stored along k.  Levels past the last one read
 // level nz - 1 and are never stored.  The row transform is k_fft_y_fast's.
 template <typename T, int R1, int R2, int DIR, int NT>
 __global__ __launch_bounds__(NT) void k_fft_y_zyx(const cx_t<T> *__restrict__ src,
@@ -449,7 +449,7 @@ __global__ __launch_bounds__(ROWS *R1) void k_r2c_fast(const T *__restrict__ in,
 // transforms backwards and stores real rows (optionally accumulated).
 // ZYX (nz > 0): the rows are ROWS consecutive levels of one row j read from
 // the [kx][j][k] layout (along k), and the result is staged in LDS and
-// stored along k into a z-fastest field ([nx][ny][nz]); no accumulation.
+// stored (or accumulated) along k into a z-fastest field ([nx][ny][nz]).
 template <typename T, int R1, int R2, int ROWS, bool PAIR = false, bool ZYX = false>
 __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict__ spec,
                                                       T *__restrict__ out, int ny, int nrows,
@@ -561,10 +561,18 @@ __global__ __launch_bounds__(ROWS *R1) void k_c2r_fast(const cx_t<T> *__restrict
         const int kk = threadIdx.x % ROWS, i0 = threadIdx.x / ROWS;
         if (zk0 + kk < nz) {
             T *col = out + (long)zj * nz + zk0 + kk;
+            if (accumulate) {
 #pragma unroll 8
-            for (int it = 0; it < IT; ++it)
-                col[(long)(i0 + (NT / ROWS) * it) * istride] =
-                    lds[kk * SW + i0 + (NT / ROWS) * it];
+                for (int it = 0; it < IT; ++it) {
+                    T *o = col + (long)(i0 + (NT / ROWS) * it) * istride;
+                    *o += lds[kk * SW + i0 + (NT / ROWS) * it];
+                }
+            } else {
+#pragma unroll 8
+                for (int it = 0; it < IT; ++it)
+                    col[(long)(i0 + (NT / ROWS) * it) * istride] =
+                        lds[kk * SW + i0 + (NT / ROWS) * it];
+            }
         }
         return;
     }
@@ -832,7 +840,7 @@ hipError_t launch_fft_y_zyx(const cx_t<T> *src, cx_t<T> *dst, int nz, int nkx, i
 template <typename T, int R1, int R2, bool WIDE>
 static hipError_t x_zyx(const T *in, cx_t<T> *tmp, double *rowsum, const cx_t<T> *tmp_in,
                         T *out, int ny, int nz, const cx_t<T> *tw4, const cx_t<T> *tws,
-                        int pair, hipStream_t st)
+                        int pair, int accumulate, hipStream_t st)
 {
     if constexpr (R2 == 2 * R1) {
         if (pair) {
@@ -845,8 +853,8 @@ static hipError_t x_zyx(const T *in, cx_t<T> *tmp, double *rowsum, const cx_t<T>
                                    (const double *)nullptr, 1, 0, (const T *)nullptr, 1.0);
             else
                 hipLaunchKernelGGL((k_c2r_fast<T, R2, R1, ROWS, true, true>), dim3(grid),
-                                   dim3(ROWS * R2), 0, st, tmp_in, out, ny, ny * nz, 0, tw4, tws,
-                                   1, nz);
+                                   dim3(ROWS * R2), 0, st, tmp_in, out, ny, ny * nz, accumulate,
+                                   tw4, tws, 1, nz);
             return hipGetLastError();
         }
     }
@@ -859,22 +867,27 @@ static hipError_t x_zyx(const T *in, cx_t<T> *tmp, double *rowsum, const cx_t<T>
                            (const T *)nullptr, 1.0);
     else
         hipLaunchKernelGGL((k_c2r_fast<T, R1, R2, ROWS, false, true>), dim3(grid),
-                           dim3(ROWS * R1), 0, st, tmp_in, out, ny, ny * nz, 0, tw4, tws, 1, nz);
+                           dim3(ROWS * R1), 0, st, tmp_in, out, ny, ny * nz, accumulate, tw4, tws,
+                           1, nz);
     return hipGetLastError();
 }
 
 // Forward (in != NULL: z-fastest field -> [kx][j][k], row sums) or backward
-// (in == NULL: [kx][j][k] -> z-fastest field) x pass; pair selects the
-// paired row transform where nx/2 = 2 s^2; wide: twice the levels per
-// block (256-byte runs along k in FP32, within 128 KiB of LDS).
+// (in == NULL: [kx][j][k] -> z-fastest field, added to it when accumulate)
+// x pass; pair selects the paired row transform where nx/2 = 2 s^2; wide:
+// twice the levels per block (256-byte runs along k in FP32, within 128 KiB
+// of LDS).
 template <typename T>
 hipError_t launch_x_zyx_fast(const T *in, cx_t<T> *tmp, double *rowsum, const cx_t<T> *tmp_in,
                              T *out, int nx, int ny, int nz, const cx_t<T> *tw4,
-                             const cx_t<T> *tws, int pair, int wide, hipStream_t st)
+                             const cx_t<T> *tws, int pair, int wide, int accumulate,
+                             hipStream_t st)
 {
 #define PS_X(a, b)                                                                                 \
-    (wide ? x_zyx<T, a, b, true>(in, tmp, rowsum, tmp_in, out, ny, nz, tw4, tws, pair, st)         \
-          : x_zyx<T, a, b, false>(in, tmp, rowsum, tmp_in, out, ny, nz, tw4, tws, pair, st))
+    (wide ? x_zyx<T, a, b, true>(in, tmp, rowsum, tmp_in, out, ny, nz, tw4, tws, pair, accumulate, \
+                                 st)                                                              \
+          : x_zyx<T, a, b, false>(in, tmp, rowsum, tmp_in, out, ny, nz, tw4, tws, pair,           \
+                                  accumulate, st))
     PS_FAST_SWITCH(nx / 2, PS_X)
 #undef PS_X
 }
@@ -884,7 +897,7 @@ hipError_t launch_x_zyx_fast(const T *in, cx_t<T> *tmp, double *rowsum, const cx
                                             const cx_t<T> *, hipStream_t);                        \
     template hipError_t launch_x_zyx_fast<T>(const T *, cx_t<T> *, double *, const cx_t<T> *,    \
                                              T *, int, int, int, const cx_t<T> *,                 \
-                                             const cx_t<T> *, int, int, hipStream_t);             \
+                                             const cx_t<T> *, int, int, int, hipStream_t);        \
     template hipError_t launch_fft_y_fast<T>(cx_t<T> *, int, int, int, int, int, int,            \
                                              const cx_t<T> *, hipStream_t, int, int);             \
     template hipError_t launch_r2c_fast<T>(const T *, cx_t<T> *, double *, int, int, int,        \

@@ -95,7 +95,8 @@ __global__ __launch_bounds__(256) void k_inv_x_zyx(const cx_t<T> *__restrict__ s
                                                    T *__restrict__ out, int nx, int ny, int nz,
                                                    int KC, int JC, int nkc, StagePlan sp,
                                                    const cx_t<T> *__restrict__ twx,
-                                                   const cx_t<T> *__restrict__ tws)
+                                                   const cx_t<T> *__restrict__ tws,
+                                                   int accumulate)
 {
     using C = cx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -139,12 +140,45 @@ __global__ __launch_bounds__(256) void k_inv_x_zyx(const cx_t<T> *__restrict__ s
     __syncthreads();
     const C *R = stockham_rows<1>(b, a, nr, L, sp, stw);
     const T *rr = reinterpret_cast<const T *>(R);
-    // stores run along z
+    // stores (or accumulations) run along z
     const int nst = nx * nr;
     for (int t = threadIdx.x; t < nst; t += blockDim.x) {
         const int kk = t % nk, rest = t / nk;
         const int jj = rest % nj, i = rest / nj;
-        out[((size_t)i * ny + (j0 + jj)) * nz + (k0 + kk)] = rr[(jj * nk + kk) * nx + i];
+        T *o = out + ((size_t)i * ny + (j0 + jj)) * nz + (k0 + kk);
+        const T val = rr[(jj * nk + kk) * nx + i];
+        *o = accumulate ? *o + val : val;
+    }
+}
+
+// r = b - A p at every point of z-fastest fields, one thread per point in
+// storage order (loads along k): the 7-point operator with periodic x and y
+// neighbours and the vertical coefficients rc (3 per level: upper, lower,
+// centre; zero at the top and bottom faces, where the missing neighbour is
+// read as the point itself), FP64 accumulation in the same order as the
+// level-major residual transform, rounded once.
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual_zyx(const T *__restrict__ b,
+                                                      const T *__restrict__ p, T *__restrict__ r,
+                                                      int nx, int ny, int nz, double idx2,
+                                                      double idy2, const double *__restrict__ rc)
+{
+    const unsigned n = (unsigned)nx * (unsigned)ny * (unsigned)nz; // < 2^31
+    const unsigned jstride = (unsigned)nz, istride = (unsigned)ny * (unsigned)nz;
+    for (unsigned c = blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += gridDim.x * blockDim.x) {
+        const unsigned k = c % (unsigned)nz, rest = c / (unsigned)nz;
+        const unsigned j = rest % (unsigned)ny, i = rest / (unsigned)ny;
+        const double pc = (double)p[c];
+        const double pe = (double)p[i + 1 == (unsigned)nx ? c - i * istride : c + istride];
+        const double pw = (double)p[i == 0 ? c + ((unsigned)nx - 1) * istride : c - istride];
+        const double pn = (double)p[j + 1 == (unsigned)ny ? c - j * jstride : c + jstride];
+        const double ps = (double)p[j == 0 ? c + ((unsigned)ny - 1) * jstride : c - jstride];
+        const double pu = k + 1 < (unsigned)nz ? (double)p[c + 1] : pc;
+        const double pd = k > 0 ? (double)p[c - 1] : pc;
+        const double lap = ((pe - 2.0 * pc + pw) * idx2 + (pn - 2.0 * pc + ps) * idy2 +
+                            rc[3 * k] * pu + rc[3 * k + 1] * pd - rc[3 * k + 2] * pc);
+        r[c] = (T)((double)b[c] - lap);
     }
 }
 
@@ -175,14 +209,25 @@ hipError_t launch_fwd_x_zyx(const T *in, cx_t<T> *spec, double *rowsum, int nx, 
 template <typename T>
 hipError_t launch_inv_x_zyx(const cx_t<T> *spec, T *out, int nx, int ny, int nz, int rows,
                             int kc_pref, const StagePlan &spx, const Tables<T> &tb,
-                            hipStream_t st)
+                            hipStream_t st, int accumulate)
 {
     int KC, JC;
     zyx_tile(rows, kc_pref, nz, &KC, &JC);
     const int nkc = (nz + KC - 1) / KC, njc = (ny + JC - 1) / JC;
     hipLaunchKernelGGL(k_inv_x_zyx<T>, dim3(nkc * njc), dim3(256),
                        lds_rows(KC * JC, nx / 2, sizeof(cx_t<T>)), st, spec, out, nx, ny, nz, KC,
-                       JC, nkc, spx, tb.tw_x, tb.tw_s);
+                       JC, nkc, spx, tb.tw_x, tb.tw_s, accumulate);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_residual_zyx(const T *b, const T *p, T *r, int nx, int ny, int nz, double idx2,
+                               double idy2, const double *rc, hipStream_t st)
+{
+    const long n = (long)nx * ny * nz;
+    const int grid = (int)std::min<long>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL(k_residual_zyx<T>, dim3(grid), dim3(256), 0, st, b, p, r, nx, ny, nz, idx2,
+                       idy2, rc);
     return hipGetLastError();
 }
 
@@ -193,9 +238,15 @@ template hipError_t launch_fwd_x_zyx<double>(const double *, cx_t<double> *, dou
                                              int, int, int, const StagePlan &,
                                              const Tables<double> &, hipStream_t);
 template hipError_t launch_inv_x_zyx<float>(const cx_t<float> *, float *, int, int, int, int, int,
-                                            const StagePlan &, const Tables<float> &, hipStream_t);
+                                            const StagePlan &, const Tables<float> &, hipStream_t,
+                                            int);
 template hipError_t launch_inv_x_zyx<double>(const cx_t<double> *, double *, int, int, int, int,
                                              int, const StagePlan &, const Tables<double> &,
-                                             hipStream_t);
+                                             hipStream_t, int);
+template hipError_t launch_residual_zyx<float>(const float *, const float *, float *, int, int,
+                                               int, double, double, const double *, hipStream_t);
+template hipError_t launch_residual_zyx<double>(const double *, const double *, double *, int,
+                                                int, int, double, double, const double *,
+                                                hipStream_t);
 
 } // namespace ps

@@ -808,7 +808,8 @@ static bool zyx_fast(const ps_plan *p) { return p->geom.variant_x >= 1 && p->geo
 // backward x, the same bytes per point as the level-major solve.  Other
 // lengths: x passes that transpose between columns and rows in LDS around
 // the level-major y / column / y passes.
-template <typename T> static int run_zyx(ps_plan *p, const T *in, T *out, int adjoint)
+template <typename T>
+static int run_zyx_pass(ps_plan *p, const T *in, T *out, int adjoint, int accumulate)
 {
     auto *spec = reinterpret_cast<cx_t<T> *>(p->d_spec);
     const Tables<T> &tb = tables<T>(p);
@@ -824,7 +825,7 @@ template <typename T> static int run_zyx(ps_plan *p, const T *in, T *out, int ad
         PS_HIP(timed(p, K_FWD_X, [&] {
             return launch_x_zyx_fast<T>(in, tmp, p->d_rowsum, nullptr, nullptr, p->nx, p->ny,
                                         p->nz, tb.tw4_x, tb.tw_s,
-                                        p->geom.variant_x == 4 && pair_length(p->L), wide,
+                                        p->geom.variant_x == 4 && pair_length(p->L), wide, 0,
                                         p->stream);
         }));
         PS_HIP(timed(p, K_FFT_Y_FWD, [&] {
@@ -838,7 +839,7 @@ template <typename T> static int run_zyx(ps_plan *p, const T *in, T *out, int ad
             return launch_x_zyx_fast<T>(nullptr, nullptr, nullptr, tmp, out, p->nx, p->ny, p->nz,
                                         tb.tw4_x, tb.tw_s,
                                         p->geom.variant_xi == 4 && pair_length(p->L), wide,
-                                        p->stream);
+                                        accumulate, p->stream);
         }));
         return PS_OK;
     }
@@ -849,16 +850,38 @@ template <typename T> static int run_zyx(ps_plan *p, const T *in, T *out, int ad
     PS_TRY(middle<T>(p, spec, adjoint, p->precision == PS_FP32_R2));
     PS_HIP(timed(p, K_INV_X, [&] {
         return launch_inv_x_zyx<T>(spec, out, p->nx, p->ny, p->nz, p->geom.rows_x,
-                                   p->geom.zyx_kc, p->spx, tb, p->stream);
+                                   p->geom.zyx_kc, p->spx, tb, p->stream, accumulate);
     }));
     return PS_OK;
+}
+
+// The z-fastest solve; the PS_FP32_R1 form adds one refinement step: the
+// residual of the first solution (FP64 accumulation, a pass of its own in
+// this layout), its solve, and the correction accumulated by the last
+// backward x pass.
+template <typename T> static int run_zyx(ps_plan *p, const T *in, T *out, int adjoint)
+{
+    PS_TRY(run_zyx_pass<T>(p, in, out, adjoint, 0));
+    if (p->precision != PS_FP32_R1) return PS_OK;
+    if (!p->d_zyx_res) {
+        T *buf = nullptr;
+        PS_TRY(dev_alloc(p, &buf, (size_t)p->nx * p->ny * p->nz));
+        p->d_zyx_res = buf;
+    }
+    T *res = reinterpret_cast<T *>(p->d_zyx_res);
+    PS_HIP(timed(p, K_FWD_X_RES, [&] {
+        return launch_residual_zyx<T>(in, out, res, p->nx, p->ny, p->nz, 1.0 / (p->dx * p->dx),
+                                      1.0 / (p->dy * p->dy),
+                                      p->d_rc + (adjoint ? 3 * (size_t)p->nz : 0), p->stream);
+    }));
+    return run_zyx_pass<T>(p, res, out, adjoint, 1);
 }
 
 static int solve_zyx_common(ps_plan *p, const void *in, void *out, int adjoint)
 {
     if (!p || !in || !out) return fail(PS_EINVAL, "plan, input and output must not be NULL");
-    if (p->precision == PS_FP32_R1)
-        return fail(PS_EUNSUPPORTED, "the z-fastest layout supports PS_FP64, PS_FP32 and PS_FP32_R2");
+    if (p->precision == PS_FP32_R1 && in == out)
+        return fail(PS_EINVAL, "the PS_FP32_R1 form needs input and output not to alias");
     if (p->fp64()) return run_zyx<double>(p, (const double *)in, (double *)out, adjoint != 0);
     return run_zyx<float>(p, (const float *)in, (float *)out, adjoint != 0);
 }
@@ -1081,12 +1104,10 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
     pick(&FftGeom::special_variant, {0, 1});
     pick(&FftGeom::special_side, {0, 1, 2});
     if (p->geom.special_side == 1) pick(&FftGeom::chunks, {1, 2, 4, 8});
-    if (p->precision != PS_FP32_R1) {
-        if (zyx_fast(p))
-            pick(&FftGeom::zyx_kc, {16, 64}, solve_zyx_common); // standard or wide blocks
-        else
-            pick(&FftGeom::zyx_kc, {1, 2, 4, 8, 64}, solve_zyx_common);
-    }
+    if (zyx_fast(p))
+        pick(&FftGeom::zyx_kc, {16, 64}, solve_zyx_common); // standard or wide blocks
+    else
+        pick(&FftGeom::zyx_kc, {1, 2, 4, 8, 64}, solve_zyx_common);
     p->prof.on = prof;
     (void)hipStreamSynchronize(p->stream);
     (void)hipFree(in);

@@ -145,7 +145,13 @@ hipError_t launch_fwd_x_zyx(const T *in, cx_t<T> *spec, double *rowsum, int nx, 
 template <typename T>
 hipError_t launch_inv_x_zyx(const cx_t<T> *spec, T *out, int nx, int ny, int nz, int rows,
                             int kc_pref, const StagePlan &spx, const Tables<T> &tb,
-                            hipStream_t st);
+                            hipStream_t st, int accumulate = 0);
+// r = b - A p for z-fastest fields (the refinement's residual; FP64
+// accumulation, rounded once), rc: 3 vertical coefficients per level as for
+// the level-major residual transform.
+template <typename T>
+hipError_t launch_residual_zyx(const T *b, const T *p, T *r, int nx, int ny, int nz, double idx2,
+                               double idy2, const double *rc, hipStream_t st);
 
 // The z-fastest solve's passes for fast lengths (fft_fast.hip), through
 // the [kx][j][k] layout (k fastest, tmp): forward x (in != NULL: field ->
@@ -156,7 +162,8 @@ hipError_t launch_inv_x_zyx(const cx_t<T> *spec, T *out, int nx, int ny, int nz,
 template <typename T>
 hipError_t launch_x_zyx_fast(const T *in, cx_t<T> *tmp, double *rowsum, const cx_t<T> *tmp_in,
                              T *out, int nx, int ny, int nz, const cx_t<T> *tw4,
-                             const cx_t<T> *tws, int pair, int wide, hipStream_t st);
+                             const cx_t<T> *tws, int pair, int wide, int accumulate,
+                             hipStream_t st);
 template <typename T>
 hipError_t launch_fft_y_zyx(const cx_t<T> *src, cx_t<T> *dst, int nz, int nkx, int ny, int dir,
                             const cx_t<T> *tw4, hipStream_t st);

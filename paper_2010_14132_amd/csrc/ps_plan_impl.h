@@ -75,6 +75,7 @@ struct ps_plan {
     double *d_rc = nullptr; // residual vertical coefficients [fwd: 3 nz][adj: 3 nz]
     double *d_dc = nullptr; // divergence / gradient coefficients, 3 per level
     void *d_zyx = nullptr;  // [kx][j][k] buffer of the z-fastest solve (allocated on its first call)
+    void *d_zyx_res = nullptr; // residual field of the z-fastest PS_FP32_R1 solve (idem)
     int nblk = 0;
     size_t bytes = 0;
     std::vector<void *> allocs;
