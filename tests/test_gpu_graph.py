@@ -111,6 +111,40 @@ def test_differentiation_step_graph():
     plan.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32_r2", "fp32_r1", "fp64"])
+def test_zyx_and_projection_graphs(precision):
+    """A z-fastest solve (its buffers allocated by the warm-up call) and a
+    projection step with the gradient correction, each captured and
+    replayed on new inputs, bit-equal to the eager calls."""
+    announce("graph-captured z-fastest solve and projection step %s" % precision)
+    g = grid()
+    plan = make_plan(g, precision)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    bz = field(3, dt).permute(2, 1, 0).contiguous()
+    pz = torch.empty_like(bz)
+    gz = capture(lambda: plan.solve_zyx(bz, out=pz))
+    u, v, w = field(4, dt), field(5, dt), field(6, dt)
+    pp = torch.empty_like(u)
+    gp = capture(lambda: plan.project(u, v, w, 2.0, out=pp, correct=True))
+    for rep in range(3):
+        nb = field(400 + rep, dt).permute(2, 1, 0).contiguous()
+        bz.copy_(nb)
+        gz.replay()
+        nu, nv, nw = field(500 + rep, dt), field(600 + rep, dt), field(700 + rep, dt)
+        u.copy_(nu)
+        v.copy_(nv)
+        w.copy_(nw)
+        gp.replay()
+        torch.cuda.synchronize()
+        ez = plan.solve_zyx(nb)
+        ep = plan.project(nu, nv, nw, 2.0, correct=True)
+        torch.cuda.synchronize()
+        assert torch.equal(pz, ez), rep
+        assert torch.equal(pp, ep) and torch.equal(u, nu) and torch.equal(v, nv) \
+            and torch.equal(w, nw), rep
+    plan.close()
+
+
 def test_graph_replay_launch_time_small_grid():
     """At 64 x 128 x 16 a solve is a few tens of microseconds, comparable
     with the launches it issues; replaying a captured graph removes their
