@@ -514,6 +514,7 @@ def config_batch(steps, warmup):
     res = {"workload": "48 problems, nx = ny in {64..512}, nz in {32..128}, stretch U[1, 1.05], "
                        "seed 4; problem i smooth RHS seed 4000+i",
            "problems": len(probs), "points": npts, "lanes": batch.info()["lanes"],
+           "fp64_in_order": batch.info()["fp64_in_order"],
            "latency_median_ms": d["median_ms"], "latency_min_ms": d["min_ms"],
            "latency_mean_ms": d["mean_ms"], "reps": d["reps"], "ms_per_batch_mean": ms,
            "aggregate_mpts_per_s": npts / d["median_ms"] / 1e3,

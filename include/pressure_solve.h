@@ -273,7 +273,8 @@ int ps_inverse_transform(ps_plan *plan, const void *spectrum, void *p);
  * streams, most points first, each to the lane with the fewest points so
  * far; each lane's solves are captured one after another into one graph on
  * its stream, and a solve forks the lanes from the caller's stream,
- * launches the graphs side by side and joins them back.
+ * launches the graphs side by side and joins them back.  Each problem's FP64
+ * columns run in order on its lane by default (ps_batch_set_fp64_order).
  *   nx, ny, nz, dx, dy : host arrays of count values.
  *   dz, rho            : host arrays of count host pointers to nz[i] values.
  *   precision          : a ps_precision value, shared by every problem.
@@ -306,14 +307,23 @@ int ps_batch_set_lanes(ps_batch *batch, int lanes);
  * during its capture). */
 enum { PS_BATCH_PHASES = 0, PS_BATCH_PERSISTENT = 1, PS_BATCH_PLANS = 2, PS_BATCH_LANES = 3 };
 int ps_batch_set_mode(ps_batch *batch, int mode);
+/* in_order 1 (the default): every problem's FP64 columns (the packed
+ * kx = 0 row, the mean column and the near-singular columns) run on its
+ * lane before its main column kernel, so each lane's graph is a single chain
+ * on one stream; 0: each plan keeps its own placement (ps_plan_info's
+ * fp64_beside), forking them onto the plan's second stream.  The result is
+ * the same bit for bit.  PS_EINVAL for other values; synchronises and drops
+ * the captured graphs when it changes. */
+int ps_batch_set_fp64_order(ps_batch *batch, int in_order);
 /* Autotune every problem's plan (ps_plan_autotune, reps repetitions; equal
- * shapes share the tune-cache entry), then time 1, 2, 4 and 8 lanes over
+ * shapes share the tune-cache entry), then time 1, 2, 4 and 8 lanes, each
+ * with the FP64 columns in order and with each plan's own placement, over
  * reps replays each on the given fields (which are written) and keep the
- * fastest.  Synchronises. */
+ * fastest pair.  Synchronises. */
 int ps_batch_autotune(ps_batch *batch, const void *const *rhs, void *const *p, int reps);
-/* count of problems and the number of lanes (grid); tiles and lds_budget
- * are 0 (kept for the withdrawn tile forms).  Any pointer may be NULL. */
-int ps_batch_query(const ps_batch *batch, int *count, int *tiles, int *grid, int *lds_budget);
+/* count of problems, the number of lanes and the FP64-column order (1: in
+ * order on the lanes).  Any pointer may be NULL. */
+int ps_batch_query(const ps_batch *batch, int *count, int *lanes, int *fp64_in_order);
 /* Synchronise the batch's streams; PS_OK, or PS_EHIP if an earlier solve
  * failed on the device. */
 int ps_batch_status(ps_batch *batch);

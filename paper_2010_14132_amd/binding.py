@@ -69,7 +69,8 @@ SIGNATURES = {
     "ps_batch_destroy": (ctypes.c_int, [_vp]),
     "ps_batch_set_stream": (ctypes.c_int, [_vp, _vp]),
     "ps_batch_autotune": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int]),
-    "ps_batch_query": (ctypes.c_int, [_vp, _I, _I, _I, _I]),
+    "ps_batch_query": (ctypes.c_int, [_vp, _I, _I, _I]),
+    "ps_batch_set_fp64_order": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ps_batch_status": (ctypes.c_int, [_vp]),
     "ps_batch_set_mode": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ps_batch_set_lanes": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -497,6 +498,12 @@ class BatchPlan:
     def set_lanes(self, lanes: int):
         check(load().ps_batch_set_lanes(self._h, int(lanes)), "ps_batch_set_lanes")
 
+    def set_fp64_order(self, in_order: bool):
+        """True (default): each problem's FP64 columns in order on its lane;
+        False: each plan's own placement (forked onto its second stream)."""
+        check(load().ps_batch_set_fp64_order(self._h, int(bool(in_order))),
+              "ps_batch_set_fp64_order")
+
     def _ptrs(self, rhs, out):
         n = len(self.grids)
         for i, (b, p, g) in enumerate(zip(rhs, out, self.grids)):
@@ -525,10 +532,10 @@ class BatchPlan:
         check(load().ps_batch_status(self._h), "ps_batch_status")
 
     def info(self) -> dict:
-        c, t, g, l = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        check(load().ps_batch_query(self._h, ctypes.byref(c), ctypes.byref(t), ctypes.byref(g),
-                                    ctypes.byref(l)), "ps_batch_query")
-        return {"count": c.value, "lanes": g.value}
+        c, l, o = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(load().ps_batch_query(self._h, ctypes.byref(c), ctypes.byref(l), ctypes.byref(o)),
+              "ps_batch_query")
+        return {"count": c.value, "lanes": l.value, "fp64_in_order": bool(o.value)}
 
     def close(self):
         h, self._h = getattr(self, "_h", None), None

@@ -10,14 +10,20 @@
 // Mode PS_BATCH_LANES: the problems are dealt to a few lanes, largest first,
 // each to the lane with the fewest points so far (LPT).  Each lane has its
 // own stream; the solves of a lane's problems are captured one after another
-// into one graph on that stream, with the stream as the capture's origin
-// (each plan's FP64 columns fork onto the plan's second stream and join back
-// inside the capture).  A batched solve forks the lanes from the caller's
-// stream, launches every lane's graph on its stream and joins them back, so
-// problems of different lanes run side by side and the small problems fill
-// the gaps the large ones leave.  Before the first capture every plan solves
-// once eagerly on the stream it will be captured on, so no kernel is first
-// launched inside a capture.
+// into one graph on that stream, with the stream as the capture's origin.
+// By default each plan's FP64 columns run in order on the lane (placement 0
+// of the plan), so a lane's graph is one chain on one stream; otherwise each
+// plan keeps its own placement and its FP64 columns fork onto the plan's
+// second stream and join back inside the capture.  The in-order form is the
+// faster one for the uneven batch: the plans' second streams share the
+// device's few hardware queues with the lanes, so their forks tie the lanes'
+// progress together, while the lanes themselves already overlap one
+// problem's FP64 columns with other problems' passes.  A batched solve forks
+// the lanes from the caller's stream, launches every lane's graph on its
+// stream and joins them back, so problems of different lanes run side by
+// side and the small problems fill the gaps the large ones leave.  Before the
+// first capture every plan solves once eagerly on the stream it will be
+// captured on, so no kernel is first launched inside a capture.
 //
 // Earlier forms, refused by ps_batch_set_mode (their code is removed):
 //   PS_BATCH_PERSISTENT: one persistent launch whose blocks took (problem,
@@ -60,6 +66,8 @@ struct ps_batch {
     hipStream_t lanes[kMaxLanes] = {};
     hipEvent_t ev_in = nullptr, ev_join[kMaxLanes] = {};
     hipGraphExec_t exec[kMaxLanes] = {};    // one graph per lane (null: empty lane)
+    int fp64_in_order = 1;                  // FP64 columns in order on the lanes
+    std::vector<int> tuned_side;            // each plan's own FP64-column placement
     bool captured = false;
     std::vector<const void *> cap_rhs;
     std::vector<void *> cap_out;
@@ -157,7 +165,9 @@ extern "C" int ps_batch_create(ps_batch **out, int count, const int *nx, const i
             return bail(rc);
         }
         b->points[i] = (long long)nx[i] * ny[i] * nz[i];
+        b->tuned_side.push_back(b->plans[i]->geom.special_side);
     }
+
     b->order.resize(count);
     std::iota(b->order.begin(), b->order.end(), 0);
     std::stable_sort(b->order.begin(), b->order.end(),
@@ -173,6 +183,8 @@ static int capture_lanes(ps_batch *b, const void *const *rhs, void *const *p)
 {
     destroy_graphs(b);
     assign_lanes(b);
+    for (int i = 0; i < b->count; ++i)
+        b->plans[i]->geom.special_side = b->fp64_in_order ? 0 : b->tuned_side[i];
     // eager pass: each plan's kernels run once, outside any capture, on the
     // stream the plan is captured on
     for (int i : b->order) {
@@ -286,6 +298,20 @@ extern "C" int ps_batch_set_lanes(ps_batch *b, int lanes)
     return PS_OK;
 }
 
+extern "C" int ps_batch_set_fp64_order(ps_batch *b, int in_order)
+{
+    if (!b) return bfail(PS_EINVAL, "batch is NULL");
+    if (in_order != 0 && in_order != 1) return bfail(PS_EINVAL, "in_order must be 0 or 1");
+    if (in_order == b->fp64_in_order) return PS_OK;
+    // a replay may still run the old graphs
+    PS_BHIP(hipStreamSynchronize(b->stream));
+    const int rc = sync_lanes(b);
+    if (rc != PS_OK) return rc;
+    destroy_graphs(b);
+    b->fp64_in_order = in_order;
+    return PS_OK;
+}
+
 extern "C" int ps_batch_set_stream(ps_batch *b, void *stream)
 {
     if (!b) return bfail(PS_EINVAL, "batch is NULL");
@@ -294,9 +320,10 @@ extern "C" int ps_batch_set_stream(ps_batch *b, void *stream)
 }
 
 // Each problem's plan times its own kernel variants (ps_plan_autotune;
-// equal shapes share the choice through the tune cache), then the lane
-// counts 1, 2, 4 and 8 are timed over reps replays each on the given fields
-// and the fastest is kept.  The graphs are captured again on the next solve.
+// equal shapes share the choice through the tune cache), then every lane
+// count 1, 2, 4, 8 with the FP64 columns in order on the lanes and with each
+// plan's own placement is timed over reps replays on the given fields, and
+// the fastest pair is kept.  The graphs are captured again on the next solve.
 extern "C" int ps_batch_autotune(ps_batch *b, const void *const *rhs, void *const *p, int reps)
 {
     if (!b || !rhs || !p) return bfail(PS_EINVAL, "batch, rhs and p must not be NULL");
@@ -309,6 +336,7 @@ extern "C" int ps_batch_autotune(ps_batch *b, const void *const *rhs, void *cons
     for (int i : b->order) {
         rc = ps_plan_set_stream(b->plans[i], b->lanes[0]);
         if (rc == PS_OK) rc = ps_plan_autotune(b->plans[i], reps);
+        if (rc == PS_OK) b->tuned_side[i] = b->plans[i]->geom.special_side;
         if (rc != PS_OK)
             return ps::set_error(rc, std::string("problem ") + std::to_string(i) + ": " +
                                          ps_last_error());
@@ -319,40 +347,46 @@ extern "C" int ps_batch_autotune(ps_batch *b, const void *const *rhs, void *cons
         (void)hipEventDestroy(e0);
         return bfail(PS_EHIP, "event creation failed");
     }
-    int best = b->nlanes;
+    int best = b->nlanes, best_order = b->fp64_in_order;
     float best_ms = 1e30f;
-    for (int lanes : {1, 2, 4, 8}) {
-        if (lanes > b->count && lanes > 1) break;
-        rc = ps_batch_set_lanes(b, lanes);
-        if (rc == PS_OK) rc = ps_batch_solve(b, rhs, p); // capture + one replay
-        if (rc != PS_OK) break;
-        float ms = 0.f;
-        if (hipEventRecord(e0, b->stream) != hipSuccess) rc = bfail(PS_EHIP, "autotune timing");
-        for (int r = 0; r < reps && rc == PS_OK; ++r) rc = ps_batch_solve(b, rhs, p);
-        if (rc == PS_OK && (hipEventRecord(e1, b->stream) != hipSuccess ||
-                            hipEventSynchronize(e1) != hipSuccess ||
-                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-            rc = bfail(PS_EHIP, "autotune timing");
-        if (rc != PS_OK) break;
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = lanes;
+    for (int order : {1, 0}) {
+        for (int lanes : {1, 2, 4, 8}) {
+            if (lanes > b->count && lanes > 1) break;
+            rc = ps_batch_set_fp64_order(b, order);
+            if (rc == PS_OK) rc = ps_batch_set_lanes(b, lanes);
+            if (rc == PS_OK) rc = ps_batch_solve(b, rhs, p); // capture + one replay
+            if (rc != PS_OK) break;
+            float ms = 0.f;
+            if (hipEventRecord(e0, b->stream) != hipSuccess)
+                rc = bfail(PS_EHIP, "autotune timing");
+            for (int r = 0; r < reps && rc == PS_OK; ++r) rc = ps_batch_solve(b, rhs, p);
+            if (rc == PS_OK && (hipEventRecord(e1, b->stream) != hipSuccess ||
+                                hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = bfail(PS_EHIP, "autotune timing");
+            if (rc != PS_OK) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = lanes;
+                best_order = order;
+            }
         }
+        if (rc != PS_OK) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != PS_OK) return rc;
+    rc = ps_batch_set_fp64_order(b, best_order);
+    if (rc != PS_OK) return rc;
     return ps_batch_set_lanes(b, best);
 }
 
-extern "C" int ps_batch_query(const ps_batch *b, int *count, int *tiles, int *grid,
-                              int *lds_budget)
+extern "C" int ps_batch_query(const ps_batch *b, int *count, int *lanes, int *fp64_in_order)
 {
     if (!b) return bfail(PS_EINVAL, "batch is NULL");
     if (count) *count = b->count;
-    if (tiles) *tiles = 0;
-    if (grid) *grid = b->nlanes;
-    if (lds_budget) *lds_budget = 0;
+    if (lanes) *lanes = b->nlanes;
+    if (fp64_in_order) *fp64_in_order = b->fp64_in_order;
     return PS_OK;
 }
 

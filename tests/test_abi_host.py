@@ -143,7 +143,8 @@ def test_new_entry_points_reject_bad_arguments_before_any_hip_call(lib):
     assert lib.ps_batch_set_lanes(None, 2) == 1
     assert lib.ps_batch_set_mode(None, 3) == 1
     assert lib.ps_batch_autotune(None, None, None, 1) == 1
-    assert lib.ps_batch_query(None, None, None, None, None) == 1
+    assert lib.ps_batch_query(None, None, None, None) == 1
+    assert lib.ps_batch_set_fp64_order(None, 1) == 1
     assert lib.ps_batch_status(None) == 1
     assert lib.ps_batch_destroy(None) == 0
     rho = np.ones(8)

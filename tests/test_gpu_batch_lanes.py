@@ -66,16 +66,21 @@ def check_oracle(probs, out, tol):
         assert err < tol, (i, g.nx, g.nz, err)
 
 
-@pytest.mark.parametrize("lanes", [1, 3])
+@pytest.mark.parametrize("lanes,in_order", [(1, True), (3, True), (3, False)])
 @pytest.mark.parametrize("precision", ["fp32", "fp64", "fp32_r2", "fp32_r1"])
-def test_small_uneven_batch(precision, lanes):
+def test_small_uneven_batch(precision, lanes, in_order):
+    """Both FP64-column orders: in order on the lanes (the default) and each
+    plan's own placement (forked onto its second stream inside the capture)."""
     from paper_2010_14132_amd import BatchPlan
-    announce("batch of %d uneven problems %s, %d lanes" % (len(SMALL), precision, lanes))
+    announce("batch of %d uneven problems %s, %d lanes, FP64 columns %s"
+             % (len(SMALL), precision, lanes, "in order" if in_order else "forked"))
     probs = [wl.stretched_smooth(n, n, nz, seed=4000 + i, dtype="f32", stretch=s)
              for i, (n, nz, s) in enumerate(SMALL)]
     dt = torch.float64 if precision == "fp64" else torch.float32
     batch = BatchPlan([p.grid for p in probs], precision=precision, lanes=lanes)
-    assert batch.info() == {"count": len(SMALL), "lanes": lanes}
+    assert batch.info() == {"count": len(SMALL), "lanes": lanes, "fp64_in_order": True}
+    batch.set_fp64_order(in_order)
+    assert batch.info()["fp64_in_order"] == in_order
     rhs = [torch.from_numpy(p.rhs_exact()).to("cuda", dt) for p in probs]
     out = [torch.empty_like(r) for r in rhs]
     batch.solve(rhs, out)
@@ -160,6 +165,10 @@ def test_batch_rejects_withdrawn_modes_and_bad_lanes():
     for bad in (0, 9, -1):
         with pytest.raises(PressureSolveError):
             batch.set_lanes(bad)
+    from paper_2010_14132_amd.binding import load
+    for bad in (2, -1):
+        assert load().ps_batch_set_fp64_order(batch._h, bad) == 1  # PS_EINVAL
+    assert batch.info()["fp64_in_order"]
     batch.close()
 
 
@@ -177,7 +186,9 @@ def test_full_uneven_batch_48():
     rhs = [torch.from_numpy(p.rhs_as("f32")).cuda() for p in probs]
     out = [torch.empty_like(r) for r in rhs]
     batch.autotune(rhs, out, reps=3)
-    announce("autotuned: %d lanes" % batch.info()["lanes"])
+    info = batch.info()
+    announce("autotuned: %d lanes, FP64 columns %s"
+             % (info["lanes"], "in order" if info["fp64_in_order"] else "forked"))
     for o in out:
         o.zero_()
     batch.solve(rhs, out)
