@@ -210,6 +210,19 @@ __device__ __forceinline__ float pivot_rcp(float u)
     return __builtin_fmaf(r, e, r);
 }
 __device__ __forceinline__ double pivot_rcp(double u) { return 1.0 / u; }
+// FP64 reciprocal of u > 0 in the normal range, for the latency-bound FP64
+// column sweeps: the hardware estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - u r) (each step squares the relative error), a shorter
+// dependent chain than IEEE division; within a few ulp of 1/u, not always
+// the correctly rounded quotient.
+__device__ __forceinline__ double fp64_rcp(double u)
+{
+    double r = __builtin_amdgcn_rcp(u);
+    double e = __builtin_fma(-u, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-u, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
 
 // Per-slot coefficients in each half's elimination order (built by the plan):
 // slot [half][i], i in [0, NH), for level k = i (low half) or k = nz - 1 - i

@@ -452,18 +452,84 @@ __global__ __launch_bounds__(64) void k_special_seq(
 }
 
 // LDS-staged form of the FP64 column tasks.  A block takes G consecutive
-// tasks: it loads every level of their columns into LDS in one batch, runs
-// the eliminations of special_seq_tile from LDS -- the A and B systems of a
-// packed-row pair on two lanes, a near-singular column on one -- with the
-// eliminated values and reciprocal pivots kept in LDS instead of the HBM
-// workspace, and stores every level in one batch.  Per system the
-// arithmetic and its order are those of special_seq_tile.  The few lanes of
-// the sweeps wait on LDS rather than on HBM round trips, which matters
-// because the kernel runs beside the main column kernel while that one
-// saturates memory.
-// LDS: [f (nz+1) | D | rs | os | sS (nz each) | pad] doubles, then
-// y [nz][2][G] double2, pivots [nz][2][G] double, input [nz][2][G] complex T,
-// columns [2][G] int (index 0: Z_ky / the column, 1: Z_-ky / the column).
+// tasks: it loads every level of their columns into LDS in one batch, solves
+// the same systems as special_seq_tile (the A and B systems of a packed-row
+// pair, a near-singular column's one system) with the eliminated values and
+// reciprocal pivots kept in LDS instead of the HBM workspace, and stores
+// every level in one batch.  The sweeps are latency-bound -- a few lanes per
+// block, one dependent chain per system, one wave per SIMD issuing -- so the
+// work on the chain is cut to the recurrence itself:
+//  - each system is eliminated from both ends toward its middle level m by
+//    two lanes (the chain is about nz/2 levels);
+//  - a parallel pass over all threads first forms every system's
+//    right-hand side and s D_k, and writes them into one row per (system,
+//    half) in step order, so consecutive steps of a lane sit at constant
+//    offsets (no address arithmetic per level), with the faces toward the end
+//    and toward the middle of each half's steps in a shared row;
+//  - both halves run the same number of steps, a whole number of chunks:
+//    each half starts with inert dummy steps at its far end (faces 0, s D
+//    = 1, right-hand side 0: y stays 0 and the first real step, a boundary
+//    level whose outer face is 0, starts afresh), so no step is guarded;
+//  - the next chunk of steps is read into registers (two buffers in turn)
+//    before the current chunk is eliminated;
+//  - each reciprocal pivot is a refined hardware estimate (fp64_rcp).
+// The results agree with special_seq_tile's one-ended sweep to rounding.
+constexpr int kSpecialChunk = 8;
+struct SpecialLds {
+    int NSTEP; // steps per half: m = nz/2 rounded up to whole chunks
+    int NS;    // row length: NSTEP + one chunk of read-ahead, odd
+    int f, D, rs, os, sS, ff, mc, y, gv, bm, xm, ss, zin, scol, total; // offsets in doubles
+};
+// LDS of k_special_lds for nz levels, G tasks and complex elements of csize
+// bytes, in doubles; every part starts 16-byte aligned.
+//   f (nz+1), D, rs, os, sS (nz each)   FP64 tables
+//   ff [2][NS] double2                  per half and step: (f toward the
+//                                       end, f toward the middle); zero for
+//                                       the dummy steps and the read-ahead
+//   mc [nz] double2                     the mean column
+//   y  [G][2][2][NS] double2            per (task, system, half) row: the
+//                                       right-hand side, then y, then x
+//   gv [G][2][2][NS] double             s D_k, then the reciprocal pivot
+//   bm, xm [G][2] double2               the middle level's right-hand side
+//                                       and solution
+//   ss [G][2] double                    s of each system
+//   zin [nz][2][G] complex T            the loaded columns
+//   scol [2][G] int                     the columns (index 0: Z_ky / the
+//                                       column, 1: Z_-ky / the column)
+// ff, y and gv are preceded by two chunks of padding, so the read-ahead of a
+// row's first or last chunk stays inside the allocation.
+__host__ __device__ inline SpecialLds special_lds_layout(int nz, int G, int csize)
+{
+    SpecialLds l{};
+    l.NSTEP = ((nz >> 1) + kSpecialChunk - 1) / kSpecialChunk * kSpecialChunk;
+    int ns = l.NSTEP + kSpecialChunk;
+    if (!(ns & 1)) ++ns;
+    l.NS = ns;
+    int o = 0;
+    auto take = [&o](int n) {
+        const int r = o;
+        o += (n + 1) & ~1;
+        return r;
+    };
+    const int pad2 = 2 * 2 * kSpecialChunk; // two chunks of double2
+    l.f = take(nz + 1);
+    l.D = take(nz);
+    l.rs = take(nz);
+    l.os = take(nz);
+    l.sS = take(nz);
+    l.ff = take(pad2 + 2 * ns * 2) + pad2;
+    l.mc = take(2 * nz);
+    l.y = take(pad2 + 4 * G * ns * 2) + pad2;
+    l.gv = take(2 * kSpecialChunk + 4 * G * ns) + 2 * kSpecialChunk;
+    l.bm = take(2 * G * 2);
+    l.xm = take(2 * G * 2);
+    l.ss = take(2 * G);
+    l.zin = take((nz * 2 * G * csize + 7) / 8);
+    l.scol = take((2 * G + 1) / 2);
+    l.total = o;
+    return l;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_special_lds(
     cx_t<T> *__restrict__ spec, int nx, int ny, int nz, int adjoint, const int *__restrict__ mlist,
@@ -472,16 +538,23 @@ __global__ __launch_bounds__(256) void k_special_lds(
     const double *__restrict__ rsg, const double *__restrict__ osg, int G)
 {
     using C = cx_t<T>;
+    constexpr int CH = kSpecialChunk;
     __builtin_amdgcn_s_setprio(3);
     extern __shared__ __align__(16) double sm[];
     const int L = nx / 2, npair = ny / 2 + 1, ntask = npair + nmask;
     const size_t lvl = (size_t)L * ny;
-    const int ntab = 5 * nz + 1 + ((5 * nz + 1) & 1);
-    double *f = sm, *D = f + nz + 1, *rs = D + nz, *os = rs + nz, *sS = os + nz;
-    double2 *ys = reinterpret_cast<double2 *>(sm + ntab);
-    double *gs = reinterpret_cast<double *>(ys + (size_t)nz * 2 * G);
-    C *zin = reinterpret_cast<C *>(gs + (size_t)nz * 2 * G);
-    int *scol = reinterpret_cast<int *>(zin + (size_t)nz * 2 * G);
+    const SpecialLds ly = special_lds_layout(nz, G, (int)sizeof(C));
+    const int NS = ly.NS, m = nz >> 1;
+    double *f = sm + ly.f, *D = sm + ly.D, *rs = sm + ly.rs, *os = sm + ly.os, *sS = sm + ly.sS;
+    double2 *FF = reinterpret_cast<double2 *>(sm + ly.ff);
+    double2 *MC = reinterpret_cast<double2 *>(sm + ly.mc);
+    double2 *Y = reinterpret_cast<double2 *>(sm + ly.y);
+    double *GV = sm + ly.gv;
+    double2 *BM = reinterpret_cast<double2 *>(sm + ly.bm);
+    double2 *XM = reinterpret_cast<double2 *>(sm + ly.xm);
+    double *SS = sm + ly.ss;
+    C *zin = reinterpret_cast<C *>(sm + ly.zin);
+    int *scol = reinterpret_cast<int *>(sm + ly.scol);
     const int t0 = blockIdx.x * G;
 
     for (int i = threadIdx.x; i <= nz; i += blockDim.x) {
@@ -500,6 +573,30 @@ __global__ __launch_bounds__(256) void k_special_lds(
     }
     __syncthreads();
 
+    // faces of each half's steps (the real steps of half h are the last
+    // nreal_h of the NSTEP); s of each system
+    const int NSTEP = ly.NSTEP;
+    for (int i = threadIdx.x; i < 2 * NS; i += blockDim.x) {
+        const int h = i / NS, st = i - h * NS;
+        const int j = st - (NSTEP - (h ? nz - 1 - m : m)); // real step index
+        double2 v = double2{0.0, 0.0};
+        if (j >= 0 && st < NSTEP) {
+            const int k = h ? nz - 1 - j : j;
+            v = h ? double2{f[k + 1], f[k]} : double2{f[k], f[k + 1]};
+        }
+        FF[i] = v;
+    }
+    if (threadIdx.x < 2 * G) {
+        const int g = threadIdx.x >> 1, sys = threadIdx.x & 1, t = t0 + g;
+        double sv = 0.0;
+        if (t < npair) {
+            sv = sys ? ax[L] + ay[t] : ay[t];
+        } else if (t < ntask) {
+            const int c = scol[g], kx = c / ny, ky = c - kx * ny;
+            sv = ax[kx] + ay[ky];
+        }
+        SS[threadIdx.x] = sv;
+    }
     // one batch of loads: UNR per thread in flight before the first is used;
     // indices past the end are clamped (their values are never used)
     constexpr int UNR = 8;
@@ -520,66 +617,158 @@ __global__ __launch_bounds__(256) void k_special_lds(
     }
     __syncthreads();
 
-    // the sweeps: lanes [0, 2G), two per task (pair: A and B; a
-    // near-singular column: one); the mean column (task 0's A) is computed by
-    // the block's last wave with scans (2G <= 128, so that wave does no
-    // sweep)
-    if ((int)threadIdx.x < 2 * G) {
-        const int g = threadIdx.x >> 1, sys = threadIdx.x & 1, t = t0 + g;
-        const bool pair = t < npair;
-        if (t < ntask && (sys == 0 || pair) && !(pair && t == 0 && sys == 0)) {
-            double s;
-            if (pair) {
-                s = sys ? ax[L] + ay[t] : ay[t];
+    // every system's right-hand side rs_k (A or B of a pair, A = (Z +
+    // conj Zm)/2, B = (Z - conj Zm)/(2i); or the column) and s D_k, into
+    // the sweep rows (the middle level apart)
+    for (int i = threadIdx.x; i < nload; i += blockDim.x) {
+        const int g = i % G, r = i / G, sys = r & 1, k = r >> 1, t = t0 + g;
+        const C z0 = zin[(k * 2) * G + g], z1 = zin[(k * 2 + 1) * G + g];
+        double ar, ai;
+        if (t < npair) {
+            const double zr = z0.x, zi = z0.y, mr = z1.x, mi = -(double)z1.y;
+            if (sys == 0) {
+                ar = 0.5 * (zr + mr);
+                ai = 0.5 * (zi + mi);
             } else {
-                const int c = scol[g], kx = c / ny, ky = c - kx * ny;
-                s = ax[kx] + ay[ky];
+                ar = 0.5 * (zi - mi);
+                ai = -0.5 * (zr - mr);
             }
-            // forward elimination (dominance-excess pivots)
-            double q = 0.0, gp = 0.0, yr = 0.0, yi = 0.0;
-#pragma unroll 4
-            for (int k = 0; k < nz; ++k) {
-                const C z0 = zin[(k * 2) * G + g], z1 = zin[(k * 2 + 1) * G + g];
-                double ar, ai;
-                if (pair) { // A = (Z + conj Zm)/2, B = (Z - conj Zm)/(2i)
-                    const double zr = z0.x, zi = z0.y, mr = z1.x, mi = -(double)z1.y;
-                    if (sys == 0) {
-                        ar = 0.5 * (zr + mr);
-                        ai = 0.5 * (zi + mi);
-                    } else {
-                        ar = 0.5 * (zi - mi);
-                        ai = -0.5 * (zr - mr);
-                    }
-                } else {
-                    ar = z0.x;
-                    ai = z0.y;
-                }
-                const double fp = f[k], fn = f[k + 1], r = rs[k];
-                const double e = s * D[k] + fp * q;
-                const double gi = 1.0 / (e + fn);
-                const double c = fp * gp;
-                yr = r * ar + c * yr;
-                yi = r * ai + c * yi;
-                ys[(k * 2 + sys) * G + g] = double2{yr, yi};
-                gs[(k * 2 + sys) * G + g] = gi;
-                q = e * gi;
+        } else {
+            ar = z0.x;
+            ai = z0.y;
+        }
+        const double2 b = double2{rs[k] * ar, rs[k] * ai};
+        if (k == m) {
+            BM[g * 2 + sys] = b;
+        } else {
+            const int h = k > m ? 1 : 0;
+            const int st = (h ? nz - 1 - k : k) + NSTEP - (h ? nz - 1 - m : m);
+            const int row = (g * 2 + sys) * 2 + h;
+            Y[row * NS + st] = b;
+            GV[row * NS + st] = SS[g * 2 + sys] * D[k];
+        }
+    }
+    // the dummy steps
+    for (int i = threadIdx.x; i < 4 * G * CH; i += blockDim.x) {
+        const int row = i / CH, st = i - row * CH;
+        if (st < NSTEP - ((row & 1) ? nz - 1 - m : m)) {
+            Y[row * NS + st] = double2{0.0, 0.0};
+            GV[row * NS + st] = 1.0;
+        }
+    }
+    __syncthreads();
+
+    // the sweeps: lanes [0, 4G), four per task -- (system, half), the
+    // system A or B of a packed-row pair (a near-singular column has only A)
+    // and the half the low levels 0..m-1 or the high levels nz-1..m+1 --
+    // eliminated toward the middle level m from both ends at once.  The two
+    // halves of a system sit in adjacent lanes and exchange their messages to
+    // the middle row with one shuffle.  The mean column (task 0's A) is
+    // computed by the block's last wave with scans (4G <= 192, so that wave
+    // does no sweep).
+    {
+        const int lane4 = threadIdx.x;
+        const int g = lane4 >> 2, sys = (lane4 >> 1) & 1, half = lane4 & 1, t = t0 + g;
+        const bool pair = t < npair;
+        const bool active = lane4 < 4 * G && t < ntask && (sys == 0 || pair) &&
+                            !(pair && t == 0 && sys == 0);
+        const int row = active ? (g * 2 + sys) * 2 + half : 0;
+        double2 *Yr = Y + row * NS;
+        double *Gr = GV + row * NS;
+        const double2 *Fh = FF + half * NS;
+        // forward elimination (dominance-excess pivots e_k, reciprocal
+        // pivots g_k = 1 / (e_k + fn_k); fp, fn the faces toward the end and
+        // toward the middle): e_k = s D_k + fp_k e_{k-1} g_{k-1}, with
+        // fp_k = fn_{k-1}
+        double e = 0.0, gp = 0.0, fpe = 0.0, yr = 0.0, yi = 0.0;
+        auto fw_load = [&](int i0, double2 (&b)[CH], double (&sd)[CH], double2 (&fc)[CH]) {
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                b[c] = Yr[i0 + c];
+                sd[c] = Gr[i0 + c];
+                fc[c] = Fh[i0 + c];
+            }
+        };
+        auto fw_step = [&](int i0, const double2 (&b)[CH], const double (&sd)[CH],
+                           const double2 (&fc)[CH]) {
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                e = __builtin_fma(fpe, gp, sd[c]);
+                const double gi = fp64_rcp(e + fc[c].y);
+                const double cc = fc[c].x * gp;
+                yr = __builtin_fma(cc, yr, b[c].x);
+                yi = __builtin_fma(cc, yi, b[c].y);
+                Yr[i0 + c] = double2{yr, yi};
+                Gr[i0 + c] = gi;
+                fpe = fc[c].y * e;
                 gp = gi;
             }
-            // backward substitution, in place
-            double xr = 0.0, xi = 0.0;
-#pragma unroll 4
-            for (int k = nz - 1; k >= 0; --k) {
-                const double2 y = ys[(k * 2 + sys) * G + g];
-                const double gi = gs[(k * 2 + sys) * G + g], fn = f[k + 1];
-                xr = gi * (y.x + fn * xr);
-                xi = gi * (y.y + fn * xi);
-                ys[(k * 2 + sys) * G + g] = double2{xr, xi};
+        };
+        if (active && NSTEP > 0) {
+            double2 b0[CH], f0[CH], b1[CH], f1[CH];
+            double s0[CH], s1[CH];
+            fw_load(0, b0, s0, f0);
+            for (int i0 = 0; i0 < NSTEP; i0 += 2 * CH) {
+                fw_load(i0 + CH, b1, s1, f1);
+                fw_step(i0, b0, s0, f0);
+                if (i0 + CH < NSTEP) {
+                    fw_load(i0 + 2 * CH, b0, s0, f0);
+                    fw_step(i0 + CH, b1, s1, f1);
+                }
+            }
+        }
+        // messages to the middle row: fn q and fn g y of this half's last
+        // step (q = e g; fn = 0 for a half of dummy steps only)
+        const double fnl = NSTEP > 0 ? Fh[NSTEP - 1].y : 0.0;
+        const double ma = active ? fnl * (e * gp) : 0.0;
+        const double mbr = active ? (fnl * gp) * yr : 0.0, mbi = active ? (fnl * gp) * yi : 0.0;
+        const double pa = __shfl_xor(ma, 1, 64);
+        const double pbr = __shfl_xor(mbr, 1, 64), pbi = __shfl_xor(mbi, 1, 64);
+        if (active) {
+            const double la = half ? pa : ma, ha = half ? ma : pa;
+            const double lbr = half ? pbr : mbr, hbr = half ? mbr : pbr;
+            const double lbi = half ? pbi : mbi, hbi = half ? mbi : pbi;
+            const double2 bm = BM[g * 2 + sys];
+            const double den = (SS[g * 2 + sys] * D[m] + la) + ha;
+            double xr = ((bm.x + lbr) + hbr) / den, xi = ((bm.y + lbi) + hbi) / den;
+            if (half == 0) XM[g * 2 + sys] = double2{xr, xi};
+            // backward substitution from the middle outward, in place (the
+            // dummy steps get x = 0)
+            auto bw_load = [&](int top, double2 (&y)[CH], double (&gv)[CH], double (&fn)[CH]) {
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    y[c] = Yr[top - c];
+                    gv[c] = Gr[top - c];
+                    fn[c] = Fh[top - c].y;
+                }
+            };
+            auto bw_step = [&](int top, const double2 (&y)[CH], const double (&gv)[CH],
+                               const double (&fn)[CH]) {
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    xr = gv[c] * __builtin_fma(fn[c], xr, y[c].x);
+                    xi = gv[c] * __builtin_fma(fn[c], xi, y[c].y);
+                    Yr[top - c] = double2{xr, xi};
+                }
+            };
+            if (NSTEP > 0) {
+                double2 y0[CH], y1[CH];
+                double g0[CH], g1[CH], n0[CH], n1[CH];
+                bw_load(NSTEP - 1, y0, g0, n0);
+                for (int top = NSTEP - 1; top >= 0; top -= 2 * CH) {
+                    bw_load(top - CH, y1, g1, n1);
+                    bw_step(top, y0, g0, n0);
+                    if (top - CH >= 0) {
+                        bw_load(top - 2 * CH, y0, g0, n0);
+                        bw_step(top - CH, y1, g1, n1);
+                    }
+                }
             }
         }
     }
     if (t0 == 0 && threadIdx.x >= blockDim.x - 64) {
-        double *base = reinterpret_cast<double *>(ys);
-        mean_column_wave(nz, nx, ny, adjoint, f, D, sS, base, base + 1, 4 * G);
+        double *base = reinterpret_cast<double *>(MC);
+        mean_column_wave(nz, nx, ny, adjoint, f, D, sS, base, base + 1, 2);
     }
     __syncthreads();
 
@@ -589,11 +778,16 @@ __global__ __launch_bounds__(256) void k_special_lds(
     for (int i = threadIdx.x; i < nst; i += blockDim.x) {
         const int g = i % G, k = i / G, t = t0 + g;
         if (t >= ntask) continue;
+        const int h = k > m ? 1 : 0;
+        const int st = (h ? nz - 1 - k : k) + NSTEP - (h ? nz - 1 - m : m);
+        auto x_of = [&](int sys) {
+            return k == m ? XM[g * 2 + sys] : Y[((g * 2 + sys) * 2 + h) * NS + st];
+        };
         const double o = os[k];
-        const double2 A = ys[(k * 2) * G + g];
+        const double2 A = t == 0 ? MC[k] : x_of(0);
         const size_t base = (size_t)k * lvl;
         if (t < npair) {
-            const double2 B = ys[(k * 2 + 1) * G + g];
+            const double2 B = x_of(1);
             const double Ar = o * A.x, Ai = o * A.y, Br = o * B.x, Bi = o * B.y;
             const int i0 = scol[g], i1 = scol[G + g];
             spec[base + i0] = C{(T)(Ar - Bi), (T)(Ai + Br)};
@@ -605,14 +799,13 @@ __global__ __launch_bounds__(256) void k_special_lds(
 }
 
 // Tasks per block of k_special_lds: as many as fit in 64 KiB of LDS (at most
-// 64), and the block's LDS bytes for them.
+// 48: four sweeping lanes per task, and the last wave kept free for the mean
+// column), and the block's LDS bytes for them.
 template <typename T> static int special_lds_tasks(int nz, size_t *bytes)
 {
-    const size_t tab = 8 * (size_t)(5 * nz + 2);
-    const size_t per = 2 * (size_t)nz * (16 + 8 + sizeof(cx_t<T>)) + 2 * sizeof(int);
-    int G = (int)((65536 - tab) / per);
-    G = std::max(1, std::min(64, G));
-    *bytes = tab + (size_t)G * per;
+    int G = 48;
+    while (G > 1 && (size_t)special_lds_layout(nz, G, sizeof(cx_t<T>)).total * 8 > 65536) --G;
+    *bytes = (size_t)special_lds_layout(nz, G, sizeof(cx_t<T>)).total * 8;
     return G;
 }
 

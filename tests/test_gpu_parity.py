@@ -629,12 +629,15 @@ SPECIAL_SHAPES = [(128, 64, 96), (20, 64, 128), (5, 12, 18), (1, 8, 8), (256, 8,
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_r2"])
 def test_fp64_column_kernels_agree(tmp_path, precision, shape):
     """The two FP64-column kernels (one lane per task through the HBM
-    workspace; staged in LDS, several tasks per block, the mean column by
-    wave scans), forced through the tune cache: each against the oracle
-    (forward and adjoint), and against each other within the sum of their
-    bars (the eliminations are the same arithmetic, the mean column's sums
-    are taken in another order, whose rounding the top of a tall stretched
-    grid amplifies)."""
+    workspace, a one-ended sweep with IEEE divisions; staged in LDS, several
+    tasks per block, each system swept from both ends toward its middle
+    level with refined reciprocal pivots, the mean column by wave scans),
+    forced through the tune cache: each against the oracle (forward and
+    adjoint), and against each other within the sum of their bars (the same
+    systems eliminated in another order, and the mean column's sums taken in
+    another order, whose rounding the top of a tall stretched grid
+    amplifies).  The shapes include nz = 1, odd and even nz (halves of
+    unequal and equal length) and ragged task blocks."""
     from paper_2010_14132_amd.binding import PRECISIONS, tune_cache_load
     nz, ny, nx = shape
     announce("FP64-column kernels %s %s" % (precision, shape))
