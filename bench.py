@@ -618,7 +618,8 @@ def main():
                          "fp64_columns": plan.info()["fp64_columns"], "steps": steps,
                          "kernels": {k: plan.info()[k] for k in
                                      ("fft_variant_x", "fft_variant_xi", "fft_variant_y",
-                                      "column_variant", "chunks", "special_variant", "fp64_beside")}}
+                                      "column_variant", "chunks", "special_variant", "fp64_beside",
+                                      "xy_chunks")}}
         outputs[form] = out
         dist = time_distribution(lambda: plan.solve(b, out=out), max(50, steps))
         results[form].update({"median_ms": dist["median_ms"], "min_ms": dist["min_ms"],

@@ -204,6 +204,8 @@ typedef struct ps_plan_info {
                              selects the wide blocks */
     int fp64_beside;      /* where the FP64 columns (packed kx = 0 row, mean column,
                              near-singular columns) run: the tune cache's fp64_beside */
+    int xy_chunks;        /* level ranges in which the forward x + y and backward
+                             y + x passes run pairwise (1: whole-field passes) */
 } ps_plan_info;
 
 int ps_plan_query(const ps_plan *plan, ps_plan_info *info);
@@ -216,7 +218,8 @@ int ps_plan_query(const ps_plan *plan, ps_plan_info *info);
  * nz, precision) for the life of the process -- a later autotune of an equal
  * plan just applies them -- and can be saved to / loaded from a text file
  * (one line per entry: arch nx ny nz precision x_variant y_variant
- * column_variant [fp64_beside [chunks [xi_variant [special_variant [zyx_kc]]]]]:
+ * column_variant [fp64_beside [chunks [xi_variant [special_variant [zyx_kc
+ * [xy_chunks]]]]]]:
  * fp64_beside where the FP64 columns run: 0 on the plan's stream before the
  * main column kernel, 1 on a second stream beside it (that stream also
  * transforms their rows in y), 2 on a second stream forked after the whole
@@ -226,7 +229,13 @@ int ps_plan_query(const ps_plan *plan, ps_plan_info *info);
  * (0 or 1), defaulting to 1; zyx_kc the levels per tile of the z-fastest
  * layout's x passes (1..256), defaulting to 64 -- with the register-resident
  * passes, values of 32 or more select blocks of twice the standard levels
- * (32 FP32, 16 FP64) -- timed with ps_solve_zyx).
+ * (32 FP32, 16 FP64) -- timed with ps_solve_zyx); xy_chunks (1..64,
+ * default 1) the number of level ranges in which the forward x and y passes,
+ * and the backward y and x passes, run pairwise, so that each second pass
+ * reads what the first has just written while it is still in the
+ * last-level cache (with the register-resident passes and fp64_beside 0 or
+ * 2; the result is the same bit for bit; the autotuner searches it jointly
+ * with fp64_beside).
  * Synchronises. */
 int ps_plan_autotune(ps_plan *plan, int reps);
 int ps_tune_cache_save(const char *path);

@@ -38,7 +38,8 @@ class PlanInfo(ctypes.Structure):
                 ("fft_variant_y", ctypes.c_int), ("spectrum_elems", ctypes.c_size_t),
                 ("column_variant", ctypes.c_int), ("chunks", ctypes.c_int),
                 ("fft_variant_xi", ctypes.c_int), ("special_variant", ctypes.c_int),
-                ("zyx_kc", ctypes.c_int), ("fp64_beside", ctypes.c_int)]
+                ("zyx_kc", ctypes.c_int), ("fp64_beside", ctypes.c_int),
+                ("xy_chunks", ctypes.c_int)]
 
 
 # name -> (restype, argtypes); mirrors include/pressure_solve.h

@@ -493,6 +493,15 @@ extern "C" int ps_plan_set_coeffs(ps_plan *p, const double *rho)
 
 extern "C" size_t ps_workspace_bytes(const ps_plan *p) { return p ? p->bytes : 0; }
 
+// Whether the forward and backward x / y passes run pairwise over level
+// ranges (fwd_xy_chunked): the register-resident passes, and the FP64
+// columns either before the main column kernel or forked after the y pass.
+static bool xy_chunked(const ps_plan *p)
+{
+    return p->geom.xy_chunks > 1 && p->geom.special_side != 1 && p->geom.variant_x >= 1 &&
+           p->geom.variant_xi >= 1 && p->geom.variant_y >= 1;
+}
+
 extern "C" int ps_plan_query(const ps_plan *p, ps_plan_info *info)
 {
     if (!p || !info) return fail(PS_EINVAL, "plan and info must not be NULL");
@@ -511,6 +520,7 @@ extern "C" int ps_plan_query(const ps_plan *p, ps_plan_info *info)
     info->special_variant = p->geom.special_variant;
     info->zyx_kc = p->geom.zyx_kc;
     info->fp64_beside = p->geom.special_side;
+    info->xy_chunks = xy_chunked(p) ? p->geom.xy_chunks : 1;
     return PS_OK;
 }
 
@@ -783,13 +793,70 @@ template <typename T> static int inv(ps_plan *p, cx_t<T> *spec, T *out, int accu
     return inv_x<T>(p, spec, out, accumulate);
 }
 
+// The forward x and y passes taken pairwise over xy_chunks level ranges,
+// and likewise the backward y and x passes: each y pass reads the range its
+// x pass has just written (and each backward x pass the range its y pass has
+// just written) while much of it is still in the last-level cache (the
+// 256 MB Infinity Cache: about 2 ranges at 1024^2 x 128 FP32, 4 FP64).
+// Every level is transformed by the same kernels as in the whole-field
+// passes, so the result is the same bit for bit.
+template <typename T> static int fwd_xy_chunked(ps_plan *p, const T *in, cx_t<T> *spec)
+{
+    const Tables<T> &tb = tables<T>(p);
+    const size_t lin = (size_t)p->nx * p->ny, lsp = (size_t)p->L * p->ny;
+    const int nc = p->geom.xy_chunks;
+    for (int c = 0; c < nc; ++c) {
+        const int k0 = (int)((long)p->nz * c / nc), k1 = (int)((long)p->nz * (c + 1) / nc);
+        if (k1 <= k0) continue;
+        PS_HIP(timed(p, K_FWD_X, [&] {
+            return launch_r2c_fast<T>(in + k0 * lin, spec + k0 * lsp,
+                                      p->d_rowsum + (size_t)k0 * p->ny, p->nx, p->ny, k1 - k0,
+                                      tb.tw4_x, tb.tw_s, p->stream, nullptr, 0.0, 0.0, nullptr,
+                                      p->geom.variant_x);
+        }));
+        PS_HIP(timed(p, K_FFT_Y_FWD, [&] {
+            return launch_fft_y_fast<T>(spec + k0 * lsp, k1 - k0, p->L, 0, p->L, p->ny, -1,
+                                        tb.tw4_y, p->stream, p->geom.variant_y, 0);
+        }));
+    }
+    return PS_OK;
+}
+
+template <typename T> static int inv_yx_chunked(ps_plan *p, cx_t<T> *spec, T *out)
+{
+    const Tables<T> &tb = tables<T>(p);
+    const size_t lin = (size_t)p->nx * p->ny, lsp = (size_t)p->L * p->ny;
+    const int nc = p->geom.xy_chunks;
+    for (int c = 0; c < nc; ++c) {
+        const int k0 = (int)((long)p->nz * c / nc), k1 = (int)((long)p->nz * (c + 1) / nc);
+        if (k1 <= k0) continue;
+        PS_HIP(timed(p, K_FFT_Y_INV, [&] {
+            return launch_fft_y_fast<T>(spec + k0 * lsp, k1 - k0, p->L, 0, p->L, p->ny, 1,
+                                        tb.tw4_y, p->stream, p->geom.variant_y, 0);
+        }));
+        PS_HIP(timed(p, K_INV_X, [&] {
+            return launch_c2r_fast<T>(spec + k0 * lsp, out + k0 * lin, p->nx, p->ny, k1 - k0, 0,
+                                      tb.tw4_x, tb.tw_s, p->stream, p->geom.variant_xi);
+        }));
+    }
+    return PS_OK;
+}
+
 template <typename T> static int run(ps_plan *p, const T *in, T *out, int adjoint)
 {
     auto *spec = reinterpret_cast<cx_t<T> *>(p->d_spec);
     const int refine = p->precision == PS_FP32_R2;
-    PS_TRY(fwd_x<T>(p, in, spec));
-    PS_TRY(middle<T>(p, spec, adjoint, refine));
-    PS_TRY(inv_x<T>(p, spec, out, 0));
+    if (xy_chunked(p)) {
+        PS_TRY(fwd_xy_chunked<T>(p, in, spec));
+        PS_TRY(columns<T>(p, spec, adjoint, refine));
+        PS_TRY(inv_yx_chunked<T>(p, spec, out));
+    } else {
+        PS_TRY(fwd_x<T>(p, in, spec));
+        PS_TRY(middle<T>(p, spec, adjoint, refine));
+        PS_TRY(inv_x<T>(p, spec, out, 0));
+    }
+    // R1's second solve takes the whole-field passes: its fused residual
+    // reads p at the neighbouring levels
     if (p->precision == PS_FP32_R1) {
         PS_TRY(fwd_residual_x<T>(p, in, out, spec, adjoint));
         PS_TRY(middle<T>(p, spec, adjoint, 0));
@@ -1055,6 +1122,7 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
             p->geom.chunks = it->second.chunks;
             p->geom.special_variant = it->second.special_variant;
             p->geom.zyx_kc = it->second.zyx_kc;
+            p->geom.xy_chunks = it->second.xy_chunks;
             return PS_OK;
         }
     }
@@ -1104,6 +1172,31 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
     pick(&FftGeom::special_variant, {0, 1});
     pick(&FftGeom::special_side, {0, 1, 2});
     if (p->geom.special_side == 1) pick(&FftGeom::chunks, {1, 2, 4, 8});
+    // The level-range passes with the FP64 columns in order or forked after
+    // the y pass, against the placement just chosen, in one search (the
+    // placement that wins with whole-field passes need not win with ranges).
+    if (rc == PS_OK && p->geom.variant_x >= 1 && p->geom.variant_xi >= 1 &&
+        p->geom.variant_y >= 1 && p->nz >= 2) {
+        std::vector<std::pair<int, int>> combos{{p->geom.special_side, 1}};
+        for (int c : {2, 3, 4, 8})
+            if (c <= p->nz)
+                for (int side : {0, 2}) combos.push_back({side, c});
+        std::vector<float> best_of(combos.size(), 1e30f);
+        for (int round = 0; round < 2 && rc == PS_OK; ++round) {
+            for (size_t i = 0; i < combos.size() && rc == PS_OK; ++i) {
+                p->geom.special_side = combos[i].first;
+                p->geom.xy_chunks = combos[i].second;
+                float ms = 0.f;
+                rc = time_solves(p, in, out, reps, &ms, solve_common);
+                best_of[i] = std::min(best_of[i], ms);
+            }
+        }
+        size_t best = 0;
+        for (size_t i = 1; i < combos.size(); ++i)
+            if (best_of[i] < best_of[best]) best = i;
+        p->geom.special_side = combos[best].first;
+        p->geom.xy_chunks = combos[best].second;
+    }
     if (zyx_fast(p))
         pick(&FftGeom::zyx_kc, {16, 64}, solve_zyx_common); // standard or wide blocks
     else
@@ -1120,8 +1213,8 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
 
 // Text format, one line per entry: arch nx ny nz precision variant_x
 // variant_y columns special_side chunks variant_xi special_variant zyx_kc
-// (the last five optional on reading; variant_xi defaults to variant_x,
-// special_variant to 1, zyx_kc to 64)
+// xy_chunks (the last six optional on reading; variant_xi defaults to
+// variant_x, special_variant to 1, zyx_kc to 64, xy_chunks to 1)
 extern "C" int ps_tune_cache_save(const char *path)
 {
     if (!path) return fail(PS_EINVAL, "path is NULL");
@@ -1132,7 +1225,7 @@ extern "C" int ps_tune_cache_save(const char *path)
         f << kv.first << ' ' << kv.second.variant_x << ' ' << kv.second.variant_y << ' '
           << kv.second.columns << ' ' << kv.second.special_side << ' ' << kv.second.chunks << ' '
           << kv.second.variant_xi << ' ' << kv.second.special_variant << ' '
-          << kv.second.zyx_kc << '\n';
+          << kv.second.zyx_kc << ' ' << kv.second.xy_chunks << '\n';
     return f.good() ? PS_OK : fail(PS_EINVAL, "write failed");
 }
 
@@ -1146,16 +1239,18 @@ extern "C" int ps_tune_cache_load(const char *path)
     while (std::getline(f, line)) {
         std::istringstream is(line);
         std::string arch;
-        int nx, ny, nz, prec, vx, vy, col, side = 1, chunks = 1, vxi = -1, spv = 1, zkc = 64;
+        int nx, ny, nz, prec, vx, vy, col, side = 1, chunks = 1, vxi = -1, spv = 1, zkc = 64,
+            xyc = 1;
         if (!(is >> arch >> nx >> ny >> nz >> prec >> vx >> vy >> col)) continue;
         if (!(is >> side)) side = 1;
         if (!(is >> chunks)) chunks = 1;
         if (!(is >> vxi)) vxi = vx;
         if (!(is >> spv)) spv = 1;
         if (!(is >> zkc)) zkc = 64;
+        if (!(is >> xyc)) xyc = 1;
         if (vx < 0 || vx > 4 || vy < 0 || vy > 2 || col < 0 || col > 8 || side < 0 || side > 2 ||
             chunks < 1 || chunks > 64 || vxi < 0 || vxi > 4 || spv < 0 || spv > 1 || zkc < 1 ||
-            zkc > 256)
+            zkc > 256 || xyc < 1 || xyc > 64)
             continue;
         std::ostringstream k;
         k << arch << ' ' << nx << ' ' << ny << ' ' << nz << ' ' << prec;
@@ -1168,6 +1263,7 @@ extern "C" int ps_tune_cache_load(const char *path)
         g.chunks = chunks;
         g.special_variant = spv;
         g.zyx_kc = zkc;
+        g.xy_chunks = xyc;
         got[k.str()] = g;
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -68,6 +68,9 @@ struct FftGeom {
     int zyx_kc = 64;     // z-fastest (MONC) x passes: levels per tile (capped by the tile
                          // rows); with the register-resident passes, >= 32 selects blocks
                          // of twice the standard levels (32 FP32, 16 FP64)
+    int xy_chunks = 1;   // level ranges in which the forward x and y passes, and the
+                         // backward y and x passes, run pairwise (register-resident
+                         // passes, FP64 columns not on the side stream with their rows)
 };
 
 struct Launch {

@@ -105,6 +105,8 @@ def test_tune_cache_round_trip_and_rejects_bad_lines(lib, tmp_path):
         "gfx950 64 64 8 2 9 1 3",            # x variant out of range
         "gfx950 64 64 8 3 1 1 9",            # column variant out of range
         "gfx950 64 64 8 1 1 1 3 1 0",        # chunks out of range
+        "gfx950 1024 1024 128 2 4 1 7 2 1 1 1 16 2",  # level ranges of the x / y passes
+        "gfx950 1024 1024 128 1 4 1 4 2 1 1 1 16 0",  # xy_chunks out of range
         "not a line",
         "",
     ]) + "\n")
@@ -112,9 +114,11 @@ def test_tune_cache_round_trip_and_rejects_bad_lines(lib, tmp_path):
     out = tmp_path / "out.txt"
     assert lib.ps_tune_cache_save(os.fsencode(str(out))) == 0
     lines = {tuple(l.split()[:5]): l.split()[5:] for l in out.read_text().splitlines() if l}
-    assert lines[("gfx950", "512", "256", "64", "1")] == ["2", "1", "5", "1", "4", "3", "0", "8"]
-    assert lines[("gfx950", "256", "256", "32", "0")] == ["1", "1", "3", "1", "1", "1", "1", "64"]
-    assert lines[("gfx950", "256", "256", "32", "2")] == ["1", "1", "7", "2", "1", "1", "1", "64"]
+    assert lines[("gfx950", "512", "256", "64", "1")] == ["2", "1", "5", "1", "4", "3", "0", "8", "1"]
+    assert lines[("gfx950", "256", "256", "32", "0")] == ["1", "1", "3", "1", "1", "1", "1", "64", "1"]
+    assert lines[("gfx950", "256", "256", "32", "2")] == ["1", "1", "7", "2", "1", "1", "1", "64", "1"]
+    assert lines[("gfx950", "1024", "1024", "128", "2")] == ["4", "1", "7", "2", "1", "1", "1", "16", "2"]
+    assert ("gfx950", "1024", "1024", "128", "1") not in lines
     assert ("gfx950", "512", "512", "32", "2") not in lines
     assert ("gfx950", "96", "96", "16", "1") not in lines
     assert ("gfx950", "128", "128", "16", "1") not in lines

@@ -492,6 +492,48 @@ def test_kernel_variants_via_tune_cache(tmp_path, precision, var):
     assert relmax(lam, lref) < (TOL64 if precision == "fp64" else TOL32)
 
 
+XY_SHAPES = [(37, 64, 128, 4), (2, 32, 64, 3), (20, 96, 192, 2)]
+
+
+@pytest.mark.parametrize("shape", XY_SHAPES, ids=lambda s: "x".join(map(str, s[:3])) + "-c%d" % s[3])
+@pytest.mark.parametrize("side", [0, 2])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_r1", "fp32_r2"])
+def test_level_range_passes_via_tune_cache(tmp_path, precision, side, shape):
+    """The forward x + y and backward y + x passes taken pairwise over level
+    ranges (the tune cache's xy_chunks), with the FP64 columns in order or
+    forked after the y pass: forward and adjoint solves bit-equal to the
+    whole-field passes of the same plan choices, and against the oracle.
+    The shapes cover ranges of unequal length (37 levels in 4), an empty
+    range (2 levels in 3) and 3 * 2^k lengths."""
+    from paper_2010_14132_amd.binding import PRECISIONS, tune_cache_load
+    nz, ny, nx, nc = shape
+    announce("level-range x/y passes %s side %d %s" % (precision, side, shape))
+    g = stretched(nx, ny, nz, seed=71 + nz)
+    b = np.random.default_rng(72).standard_normal((nz, ny, nx)) + 0.3
+    if precision != "fp64":
+        b = b.astype(np.float32).astype(np.float64)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    sols = {}
+    for c in (1, nc):
+        f = tmp_path / ("tune%d.txt" % c)
+        f.write_text("%s %d %d %d %d 1 1 3 %d 1 1 1 64 %d\n"
+                     % (_arch(), nx, ny, nz, PRECISIONS[precision], side, c))
+        tune_cache_load(str(f))
+        plan = make_plan(g, precision)
+        plan.autotune()
+        info = plan.info()
+        assert info["fp64_beside"] == side and info["xy_chunks"] == c
+        bt = torch.from_numpy(b).to("cuda", dt)
+        sols[c] = (plan.solve(bt).cpu(), plan.solve_adjoint(bt).cpu())
+        plan.close()
+    assert torch.equal(sols[nc][0], sols[1][0])
+    assert torch.equal(sols[nc][1], sols[1][1])
+    tol = TOL64 if precision == "fp64" else TOL32
+    assert relmax(sols[nc][0].double().numpy(), oracle.solve(b, g.dx, g.dy, g.dz, g.rho)) < tol
+    assert relmax(sols[nc][1].double().numpy(),
+                  oracle.solve_adjoint(b, g.dx, g.dy, g.dz, g.rho)) < tol
+
+
 @pytest.mark.parametrize("side", [0, 1, 2])
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_r1", "fp32_r2"])
 def test_fp64_column_placement_via_tune_cache(tmp_path, precision, side):
