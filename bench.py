@@ -679,9 +679,10 @@ def main():
     if args.tune_cache:
         binding.tune_cache_save(args.tune_cache)
     # dominant kernel: the largest share of the solve among the kernels that
-    # run once per transform pass (one launch = one full pass over the data)
+    # run as one launch per solve (one launch = one full pass over the data;
+    # passes taken in level or kx ranges launch in pieces)
     single = {k: v for k, v in kernels.items()
-              if v["gbs"] and abs(v["launches_per_solve"] - round(v["launches_per_solve"])) < 1e-9
+              if v["gbs"] and abs(v["launches_per_solve"] - 1.0) < 1e-9
               and not k.startswith("fft_y")}
     dom = max(single, key=lambda k: kernels[k]["ms_per_solve"])
     dk = kernels[dom]
