@@ -233,9 +233,10 @@ int ps_plan_query(const ps_plan *plan, ps_plan_info *info);
  * default 1) the number of level ranges in which the forward x and y passes,
  * and the backward y and x passes, run pairwise, so that each second pass
  * reads what the first has just written while it is still in the
- * last-level cache (with the register-resident passes and fp64_beside 0 or
- * 2; the result is the same bit for bit; the autotuner searches it jointly
- * with fp64_beside).
+ * last-level cache (with the register-resident passes; with fp64_beside 1
+ * the second stream transforms the FP64 rows of each range after its x
+ * pass; the result is the same bit for bit; the autotuner searches it
+ * jointly with fp64_beside).
  * Synchronises. */
 int ps_plan_autotune(ps_plan *plan, int reps);
 int ps_tune_cache_save(const char *path);

@@ -494,12 +494,11 @@ extern "C" int ps_plan_set_coeffs(ps_plan *p, const double *rho)
 extern "C" size_t ps_workspace_bytes(const ps_plan *p) { return p ? p->bytes : 0; }
 
 // Whether the forward and backward x / y passes run pairwise over level
-// ranges (fwd_xy_chunked): the register-resident passes, and the FP64
-// columns either before the main column kernel or forked after the y pass.
+// ranges (fwd_xy_chunked): the register-resident passes.
 static bool xy_chunked(const ps_plan *p)
 {
-    return p->geom.xy_chunks > 1 && p->geom.special_side != 1 && p->geom.variant_x >= 1 &&
-           p->geom.variant_xi >= 1 && p->geom.variant_y >= 1;
+    return p->geom.xy_chunks > 1 && p->geom.variant_x >= 1 && p->geom.variant_xi >= 1 &&
+           p->geom.variant_y >= 1;
 }
 
 extern "C" int ps_plan_query(const ps_plan *p, ps_plan_info *info)
@@ -800,11 +799,19 @@ template <typename T> static int inv(ps_plan *p, cx_t<T> *spec, T *out, int accu
 // 256 MB Infinity Cache: about 2 ranges at 1024^2 x 128 FP32, 4 FP64).
 // Every level is transformed by the same kernels as in the whole-field
 // passes, so the result is the same bit for bit.
-template <typename T> static int fwd_xy_chunked(ps_plan *p, const T *in, cx_t<T> *spec)
+// With the FP64 columns on the side stream with their rows (placement 1),
+// the side stream transforms the rows kx < kmask of each range in y as soon
+// as the range's x pass is done (an event per range, recorded after it),
+// then forms the level sums and solves the FP64 columns; the plan's stream
+// transforms the other rows of each range meanwhile.
+template <typename T>
+static int fwd_xy_chunked(ps_plan *p, const T *in, cx_t<T> *spec, int adjoint)
 {
     const Tables<T> &tb = tables<T>(p);
     const size_t lin = (size_t)p->nx * p->ny, lsp = (size_t)p->L * p->ny;
     const int nc = p->geom.xy_chunks;
+    const bool beside = p->geom.special_side == 1;
+    const int km = beside ? std::min(p->kmask, p->L) : 0;
     for (int c = 0; c < nc; ++c) {
         const int k0 = (int)((long)p->nz * c / nc), k1 = (int)((long)p->nz * (c + 1) / nc);
         if (k1 <= k0) continue;
@@ -814,10 +821,29 @@ template <typename T> static int fwd_xy_chunked(ps_plan *p, const T *in, cx_t<T>
                                       tb.tw4_x, tb.tw_s, p->stream, nullptr, 0.0, 0.0, nullptr,
                                       p->geom.variant_x);
         }));
-        PS_HIP(timed(p, K_FFT_Y_FWD, [&] {
-            return launch_fft_y_fast<T>(spec + k0 * lsp, k1 - k0, p->L, 0, p->L, p->ny, -1,
-                                        tb.tw4_y, p->stream, p->geom.variant_y, 0);
-        }));
+        if (beside) {
+            PS_HIP(hipEventRecord(p->fork, p->stream));
+            PS_HIP(hipStreamWaitEvent(p->side, p->fork, 0));
+        }
+        if (beside && km > 0) {
+            PS_HIP(timed(
+                p, K_FFT_Y_FWD,
+                [&] {
+                    return launch_fft_y_fast<T>(spec + k0 * lsp, k1 - k0, p->L, 0, km, p->ny, -1,
+                                                tb.tw4_y, p->side, p->geom.variant_y, 0);
+                },
+                p->side));
+        }
+        if (km < p->L)
+            PS_HIP(timed(p, K_FFT_Y_FWD, [&] {
+                return launch_fft_y_fast<T>(spec + k0 * lsp, k1 - k0, p->L, km, p->L - km, p->ny,
+                                            -1, tb.tw4_y, p->stream, p->geom.variant_y, 0);
+            }));
+    }
+    if (beside) {
+        PS_HIP(hipEventRecord(p->ydone, p->side));
+        PS_HIP(special_columns<T>(p, spec, adjoint, p->side));
+        PS_HIP(hipEventRecord(p->join, p->side));
     }
     return PS_OK;
 }
@@ -847,8 +873,16 @@ template <typename T> static int run(ps_plan *p, const T *in, T *out, int adjoin
     auto *spec = reinterpret_cast<cx_t<T> *>(p->d_spec);
     const int refine = p->precision == PS_FP32_R2;
     if (xy_chunked(p)) {
-        PS_TRY(fwd_xy_chunked<T>(p, in, spec));
-        PS_TRY(columns<T>(p, spec, adjoint, refine));
+        PS_TRY(fwd_xy_chunked<T>(p, in, spec, adjoint));
+        if (p->geom.special_side == 1) {
+            // the side stream's y pass of the rows kx < kmask, then its FP64
+            // columns (joined before the backward passes)
+            PS_HIP(hipStreamWaitEvent(p->stream, p->ydone, 0));
+            PS_HIP(main_columns<T>(p, spec, adjoint, refine, 1, p->L));
+            PS_HIP(hipStreamWaitEvent(p->stream, p->join, 0));
+        } else {
+            PS_TRY(columns<T>(p, spec, adjoint, refine));
+        }
         PS_TRY(inv_yx_chunked<T>(p, spec, out));
     } else {
         PS_TRY(fwd_x<T>(p, in, spec));
@@ -1172,15 +1206,15 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
     pick(&FftGeom::special_variant, {0, 1});
     pick(&FftGeom::special_side, {0, 1, 2});
     if (p->geom.special_side == 1) pick(&FftGeom::chunks, {1, 2, 4, 8});
-    // The level-range passes with the FP64 columns in order or forked after
-    // the y pass, against the placement just chosen, in one search (the
-    // placement that wins with whole-field passes need not win with ranges).
+    // The level-range passes with each FP64-column placement, against the
+    // placement just chosen, in one search (the placement that wins with
+    // whole-field passes need not win with ranges).
     if (rc == PS_OK && p->geom.variant_x >= 1 && p->geom.variant_xi >= 1 &&
         p->geom.variant_y >= 1 && p->nz >= 2) {
         std::vector<std::pair<int, int>> combos{{p->geom.special_side, 1}};
         for (int c : {2, 3, 4, 8})
             if (c <= p->nz)
-                for (int side : {0, 2}) combos.push_back({side, c});
+                for (int side : {0, 1, 2}) combos.push_back({side, c});
         std::vector<float> best_of(combos.size(), 1e30f);
         for (int round = 0; round < 2 && rc == PS_OK; ++round) {
             for (size_t i = 0; i < combos.size() && rc == PS_OK; ++i) {

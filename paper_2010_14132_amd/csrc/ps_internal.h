@@ -70,7 +70,7 @@ struct FftGeom {
                          // of twice the standard levels (32 FP32, 16 FP64)
     int xy_chunks = 1;   // level ranges in which the forward x and y passes, and the
                          // backward y and x passes, run pairwise (register-resident
-                         // passes, FP64 columns not on the side stream with their rows)
+                         // passes)
 };
 
 struct Launch {

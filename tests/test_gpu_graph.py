@@ -81,6 +81,39 @@ def test_solve_graph_replays_match_eager(precision):
     plan.close()
 
 
+@pytest.mark.parametrize("side", [0, 1, 2])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_r2", "fp32_r1"])
+def test_level_range_solve_graph(tmp_path, precision, side):
+    """A solve whose x and y passes run over 3 level ranges (the tune cache's
+    xy_chunks), with each FP64-column placement -- with placement 1 the
+    second stream waits on an event re-recorded after every range's x pass
+    -- captured into a graph and replayed against eager solves."""
+    from paper_2010_14132_amd.binding import PRECISIONS, tune_cache_load
+    announce("graph-captured level-range solve %s side %d" % (precision, side))
+    g = grid()
+    f = tmp_path / "tune.txt"
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    f.write_text("%s %d %d %d %d 1 1 3 %d 1 1 1 64 3\n"
+                 % (arch, NX, NY, NZ, PRECISIONS[precision], side))
+    tune_cache_load(str(f))
+    plan = make_plan(g, precision)
+    plan.autotune()
+    assert plan.info()["xy_chunks"] == 3 and plan.info()["fp64_beside"] == side
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    static_b = field(5, dt)
+    static_out = torch.empty_like(static_b)
+    graph = capture(lambda: plan.solve(static_b, out=static_out))
+    for rep in range(3):
+        b = field(400 + rep, dt)
+        static_b.copy_(b)
+        graph.replay()
+        torch.cuda.synchronize()
+        eager = plan.solve(b)
+        torch.cuda.synchronize()
+        assert torch.equal(static_out, eager), "replay %d differs from the eager solve" % rep
+    plan.close()
+
+
 def test_differentiation_step_graph():
     """Solve, adjoint solve and density gradient in one captured graph
     (FP32 + in-register refinement), replayed against the eager calls."""

@@ -496,13 +496,15 @@ XY_SHAPES = [(37, 64, 128, 4), (2, 32, 64, 3), (20, 96, 192, 2)]
 
 
 @pytest.mark.parametrize("shape", XY_SHAPES, ids=lambda s: "x".join(map(str, s[:3])) + "-c%d" % s[3])
-@pytest.mark.parametrize("side", [0, 2])
+@pytest.mark.parametrize("side", [0, 1, 2])
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_r1", "fp32_r2"])
 def test_level_range_passes_via_tune_cache(tmp_path, precision, side, shape):
     """The forward x + y and backward y + x passes taken pairwise over level
-    ranges (the tune cache's xy_chunks), with the FP64 columns in order or
-    forked after the y pass: forward and adjoint solves bit-equal to the
-    whole-field passes of the same plan choices, and against the oracle.
+    ranges (the tune cache's xy_chunks), with each placement of the FP64
+    columns (in order; on the second stream with the y pass of their rows
+    per range; forked after the y pass): forward and adjoint solves bit-equal
+    to the whole-field passes of the same plan choices, and against the
+    oracle.
     The shapes cover ranges of unequal length (37 levels in 4), an empty
     range (2 levels in 3) and 3 * 2^k lengths."""
     from paper_2010_14132_amd.binding import PRECISIONS, tune_cache_load
