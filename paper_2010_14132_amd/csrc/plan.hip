@@ -1230,6 +1230,12 @@ extern "C" int ps_plan_autotune(ps_plan *p, int reps)
             if (best_of[i] < best_of[best]) best = i;
         p->geom.special_side = combos[best].first;
         p->geom.xy_chunks = combos[best].second;
+        // the transform variants again, for launches over level ranges
+        if (p->geom.xy_chunks > 1) {
+            pick(&FftGeom::variant_x, vx);
+            pick(&FftGeom::variant_xi, vx);
+            pick(&FftGeom::variant_y, vy);
+        }
     }
     if (zyx_fast(p))
         pick(&FftGeom::zyx_kc, {16, 64}, solve_zyx_common); // standard or wide blocks
